@@ -144,7 +144,9 @@ def hop_event(model, ens, idx, seed, times=None):
         l = int(ens.comp[b])
         w = philox.block(seed, int(ens.gid[b]), int(ens.nhop[b]) + 1, philox.TAG_HOP)
         U, Y = philox.u01(w[0]), philox.u01(w[1])
-        col = G[t, :, l]
+        # |gamma_jl| and gamma_jl/|gamma_jl| with CPython's complex abs (hypot), which is
+        # exact for real gamma: the phase factor exp(i arg gamma) is then exactly +-1
+        col = [complex(g) for g in G[t, :, l]]
         order = [j for j in range(model.n_comp) if j != l]
         R = 0.0
         for j in order:
