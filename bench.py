@@ -1,0 +1,207 @@
+"""Benchmark: one pass of the whole SHGB hot path on one MI355X.
+
+A step is: sample the ensemble (init_beams), advance it over every interval
+(step_ensemble: RK4 beam ODEs, hop times, hops, weights), reduce the
+component populations and sum the field at the evaluation points
+(reconstruct), on the 1-D avoided-crossing QCLE workload with 1e6 beams,
+4000 intervals of 0.5 and a 64 x 64 (q, p) grid, all in FP64, inputs and
+outputs resident in HBM.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config qcle1d_1e6]
+                    [--no-cpu-baseline]
+
+Prints one JSON line.  `value` is beam-steps per second of the whole step;
+the field's beam-point evaluations per second, per-kernel times and the
+dominant kernel's roofline figure are reported beside it.  The CPU
+baseline times the FP64 oracle on a bounded sample of the same workload.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "beam-steps/s + beam·point evals/s vs FP64 plain path at equal population error"
+
+# FP64 operations per beam-step of the m = 2 stepping kernel, counted from the
+# formulas it evaluates (add, multiply, divide, square root and each exp
+# count 1; a multiply-add counts 2): 4 right-hand sides of about 120
+# (adiabatic quantities and derivatives 87, beam ODE right-hand side 33) plus
+# the Runge-Kutta combinations (3 x 24 + 73).
+FLOPS_PER_BEAM_STEP_M2 = 4 * 120 + 3 * 24 + 73
+# per beam-point evaluation of the m = 2 field: y, quadratic form and phase
+# (18), exp, sincos (counted 2), complex multiply-accumulate (8)
+FLOPS_PER_EVAL_M2 = 18 + 1 + 2 + 8
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 64 lanes x 2 flop x 2.4 GHz
+# HBM bytes per launch of step_m2_kernel at 1e6 beams, from rocprofv3 FETCH_SIZE (x2.000) and
+# WRITE_SIZE (x1.000) scaled by a 1 GiB copy (profiles/step_m2_qcle1d_1e6.md); the kernel
+# reads and writes 136 B of state per beam.  None when the kernel or workload differs.
+STEP_M2_TRAFFIC = {"qcle1d_1e6": (66717.3125 * 2.0 + 133300.78125 * 1.0) * 1024}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="qcle1d_1e6")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-beams", type=int, default=512)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy a 1 GiB float64 buffer three times (calibrates the HBM byte counters)")
+    return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read_per_copy": n * 8, "copies": 3}))
+
+
+def cpu_baseline(c, n_beams, pts):
+    """The FP64 oracle, single process, on n_beams beams of the same workload."""
+    import numpy as np
+    from oracle import models, observables, sampling, shgb as oshgb
+    om = models.QCLE(c["A"], c["B"], c["C"], c["D"], c["mass"], d=c["d"], lam=c["lam"],
+                     bath_omega=c["bath_omega"])
+    t0 = time.perf_counter()
+    ens = sampling.init_beams(om, n_beams, c["eps"], c["seed"], c["q_mean"], c["q_std"], c["p_dist"],
+                              c["p_a"], c["p_b"], c["comp0"])
+    oshgb.advance(om, ens, c["nsteps"], c["dt"], c["seed"])
+    t1 = time.perf_counter()
+    observables.populations(ens, c["eps"])
+    nq = min(len(pts), 4096)
+    t2 = time.perf_counter()
+    observables.reconstruct(ens, c["eps"], np.asarray(pts[:nq]))
+    t3 = time.perf_counter()
+    return {
+        "value": n_beams * c["nsteps"] / (t1 - t0),
+        "unit": "beam-steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{n_beams} beams x {c['nsteps']} intervals (init + stepping), then the field of those "
+                  f"beams at {nq} points; numpy float64, one process",
+        "evals_per_s": n_beams * nq / (t3 - t2),
+        "seconds": round(t3 - t0, 2),
+    }
+
+
+def main():
+    a = parse()
+    if a.copy_probe:
+        copy_probe()
+        return
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {a.gpus}). "
+              "Beams are independent; a multi-GPU run would shard beams and sum the tallies once.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1703_06116_amd import shgb, workloads
+
+    c = workloads.config(a.config)
+    N, nsteps, dt, seed, m = c["n_beams"], c["nsteps"], c["dt"], c["seed"], 2 * c["d"]
+    if m != 2:
+        raise SystemExit("bench.py drives the m = 2 workloads")
+    mdl = shgb.make_model(c["d"], c["mass"], c["eps"], c["A"], c["B"], c["C"], c["D"], c["lam"],
+                          c["bath_omega"])
+    spec = shgb.make_init_spec(c["q_mean"], c["q_std"], c["p_dist"], c["p_a"], c["p_b"], c["comp0"])
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    st = shgb.State(N, m, device=dev)
+    diag = shgb.new_diag(dev)
+    pops = torch.empty((4, 5), dtype=torch.float64, device=dev)
+    pop_work = torch.empty(max(shgb.populations_workspace(N, m), 8), dtype=torch.uint8, device=dev)
+    pts_np = workloads.grid_points_2d()
+    Q = pts_np.shape[0] if c["n_points"] else 0
+    pts = torch.from_numpy(pts_np[:Q]).to(dev)
+    rec = torch.empty((4, Q, 2), dtype=torch.float64, device=dev)
+    rec_work = torch.empty(max(shgb.reconstruct_workspace(N, m, Q), 8), dtype=torch.uint8, device=dev)
+
+    names = ("init", "step", "populations", "reconstruct")
+
+    def one_step(evs=None):
+        def mark(i):
+            if evs is not None:
+                evs[i].record()
+        mark(0)
+        shgb.init_beams(mdl, spec, st, seed)
+        mark(1)
+        shgb.step_ensemble(mdl, st, nsteps, dt, seed, diag)
+        mark(2)
+        shgb.populations(mdl, st, out=pops, work=pop_work)
+        mark(3)
+        if Q:
+            shgb.reconstruct(mdl, st, pts, out=rec, work=rec_work)
+        mark(4)
+
+    for _ in range(a.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    diag.zero_()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        one_step(events[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / a.steps
+    phase_ms = {n: float(np.mean([events[k][i].elapsed_time(events[k][i + 1]) for k in range(a.steps)]))
+                for i, n in enumerate(names)}
+    value = N * nsteps / (ms_per_step / 1e3)
+    evals_per_s = N * Q / (phase_ms["reconstruct"] / 1e3) if Q else None
+    step_tflops = FLOPS_PER_BEAM_STEP_M2 * N * nsteps / (phase_ms["step"] / 1e3) / 1e12
+    pop_host = pops.cpu().numpy()
+    mean, se = shgb.population_mean_se(pop_host, N)
+    d = diag.cpu().numpy() // max(a.steps, 1)
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "beam-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": a.config, "model": "qcle-two-level-1d", "n_beams": N, "intervals": nsteps,
+                   "dt": dt, "eps": c["eps"], "eval_points": Q, "phase_space_dim": m,
+                   "parallelism": "none (1 GPU)"},
+        "beam_point_evals_per_s": evals_per_s,
+        "kernel_ms": phase_ms,
+        "roofline": {"bound": "alu", "kernel": "step_m2_kernel", "achieved": step_tflops,
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": step_tflops / PEAK_FP64_TFLOPS,
+                     "traffic": STEP_M2_TRAFFIC.get(a.config), "traffic_unit": "bytes/launch",
+                     "algorithmic_bytes": 272 * N,
+                     "flops_per_unit": FLOPS_PER_BEAM_STEP_M2, "units_per_launch": N * nsteps},
+        "reconstruct_roofline": ({"bound": "alu", "achieved": FLOPS_PER_EVAL_M2 * evals_per_s / 1e12,
+                                  "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": FLOPS_PER_EVAL_M2 * evals_per_s / 1e12 / PEAK_FP64_TFLOPS}
+                                 if Q else None),
+        "populations": {"mean_re": mean.real.tolist(), "mean_im": mean.imag.tolist(),
+                        "se_re": se.real.tolist()},
+        "diag_per_step": {n: int(v) for n, v in zip(shgb.DIAG_NAMES, d)},
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(c, a.cpu_beams, pts_np)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

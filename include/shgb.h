@@ -1,0 +1,194 @@
+/*
+ * shgb.h -- surface hopping Gaussian beam (SHGB) ensemble on AMD Instinct
+ * MI355X (gfx950): the C ABI of libshgb.so.
+ *
+ * Method: Z. Cai and J. Lu, "A surface hopping Gaussian beam method for
+ * high-dimensional transport systems", arXiv:1703.06116.  A Monte Carlo
+ * ensemble of complex Gaussian beams solves the n-component transport system
+ *
+ *   d_t u_i + alpha_i(x)^T grad u_i = (i/eps) beta_i(x) u_i + sum_j gamma_ij(x) u_j   (Sec. 1, eq. (1.1))
+ *
+ * Each beam follows the characteristic of its current component, carries a
+ * phase, a complex Hessian and an amplitude (Sec. 2.3, eq. (2.24)), hops
+ * between components at rates |gamma_jl| (Sec. 2.4) and updates its weight
+ * exp(omega).  The solution estimate is U_i(x) = E[exp(omega) G(x) delta_{i,l}]
+ * (Sec. 2.3, eq. (2.26)).
+ *
+ * The model is the two-level quantum-classical Liouville equation of Sec. 3.3
+ * (eqs. (3.5)-(3.6)) with nuclear mass, as the linear four-component system
+ * for (u11, u22, u21, u12 = conj u21); component order 0 = u11 (upper
+ * adiabatic surface), 1 = u22 (lower), 2 = u21, 3 = u12.
+ *
+ * Conventions for every entry point:
+ *  - All arrays are device pointers unless stated, owned by the caller.  The
+ *    library never allocates or frees device memory; kernels that need scratch
+ *    space take a caller workspace whose size a *_workspace query returns.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL is the default
+ *    stream) and never synchronise.  Read outputs after synchronising.
+ *  - Return 0 (SHGB_OK) or a negative SHGB_E* code; nothing is thrown.
+ *    Numerical faults do not fail a call; they are counted in `diag`
+ *    (uint64_t[SHGB_NDIAG] on the device, atomically incremented; may be NULL).
+ *  - Random numbers: Philox4x64-10 (Salmon et al., SC'11) with key
+ *    (seed, 0) and counter (global beam id, draw index, stream tag, 0), so a
+ *    beam's draws depend only on its global id and its hop count: sharding
+ *    beams or resuming from a saved state never changes them.
+ */
+#ifndef SHGB_H
+#define SHGB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------- */
+#define SHGB_OK 0
+#define SHGB_EINVAL (-1)       /* null pointer, bad size, bad parameter     */
+#define SHGB_EUNSUPPORTED (-2) /* valid but not built (e.g. model or dimension) */
+#define SHGB_EHIP (-3)         /* a HIP launch or runtime call failed        */
+#define SHGB_EWORKSPACE (-4)   /* workspace smaller than the query returned  */
+
+/* ---- fixed sizes -------------------------------------------------------- */
+#define SHGB_MODEL_QCLE 1
+#define SHGB_NCOMP 4      /* components of the QCLE system                    */
+#define SHGB_MAX_D 12     /* nuclear dimensions: phase space m = 2d <= 24     */
+#define SHGB_HOP_CAP 16   /* hops per beam per interval; later ones deferred  */
+
+#define SHGB_DIST_NORMAL 0
+#define SHGB_DIST_UNIFORM 1
+
+/* diagnostic counters (indices into diag[]) */
+#define SHGB_DIAG_HOPS 0          /* hops performed                           */
+#define SHGB_DIAG_THR_TIES 1      /* |Lam' - E| <= 1e-12 E at a hop test        */
+#define SHGB_DIAG_DEST_TIES 2     /* |U R - C_j| <= 1e-12 R at a destination draw */
+#define SHGB_DIAG_CAP_OVERFLOW 3  /* intervals that reached SHGB_HOP_CAP hops  */
+#define SHGB_DIAG_NONFINITE 4     /* beams with a non-finite state after a call */
+#define SHGB_DIAG_NONSPD 5        /* populations: an LDL^T pivot with Re <= 0   */
+#define SHGB_DIAG_ZERO_RATE 6     /* hop requested where every rate is zero    */
+#define SHGB_DIAG_BAD_INDEX 7     /* shgb_hop: index outside [0, n_beams)      */
+#define SHGB_NDIAG 8
+
+/* ---- model -------------------------------------------------------------
+ * Two-level QCLE (Sec. 3.3) with nuclear coordinates r = (q1..qd), momenta
+ * p = (p1..pd), phase space x = (r, p), m = 2d.  Diabatic potential
+ *   V11 =  A tanh(B q1) + Vb(r),  V22 = -A tanh(B q1) + Vb(r),  V12 = C exp(-D q1^2),
+ *   Vb(r) = sum_{k=2..d} ( mass w_k^2 q_k^2 / 2 + lam q1 q_k ),
+ * adiabatic energies and coupling d21 by eq. (3.6); transport fields
+ * alpha_l = (p/mass, -grad E_l), phases beta = (0, 0, E1-E2, E2-E1), couplings
+ * gamma from (p/mass).d21 as in eq. (3.5).  eps is the semiclassical
+ * parameter: it enters only the beam shape G, never the beam ODEs.       */
+typedef struct shgb_model {
+  int32_t kind;                       /* SHGB_MODEL_QCLE                    */
+  int32_t d;                          /* 1..SHGB_MAX_D                      */
+  double mass, eps;                   /* > 0                                */
+  double A, B, C, D;                  /* potential parameters (C != 0)      */
+  double lam;                         /* bath coupling (unused when d == 1) */
+  double bath_omega[SHGB_MAX_D - 1];  /* w_2..w_d (> 0), unused when d == 1  */
+} shgb_model;
+
+/* ---- beam state --------------------------------------------------------
+ * Structure of arrays: field f of beam b is f64[f * ld + b].  With
+ * T = m(m+1)/2 the fields are, in order:
+ *   X[m], P[m], Zre[T], Zim[T], S, Are, Aim, logw, phre, phim, Lam, E
+ * Z = M + iN is the complex symmetric beam Hessian (Sec. 2, eq. (2.2)) packed
+ * by rows of its upper triangle ((i, j), i <= j, at i*m - i(i-1)/2 + j - i);
+ * A the complex amplitude; Re omega = logw + Lam where Lam is the rate
+ * integral since the last hop; exp(i Im omega) = phre + i phim; E the current
+ * waiting-time threshold (the beam hops when Lam reaches E).
+ * comp[b] is the current component l_t, nhop[b] the number of hops so far.
+ * Beam b has global id beam_id_offset + b.                                  */
+typedef struct shgb_state {
+  double *f64;              /* device, shgb_nfields(m) * ld doubles */
+  int32_t *comp;            /* device, n_beams                      */
+  uint32_t *nhop;           /* device, n_beams                      */
+  int64_t n_beams;          /* >= 0                                 */
+  int64_t ld;               /* >= n_beams                           */
+  uint64_t beam_id_offset;
+  int32_t m;                /* must equal 2 * model.d               */
+} shgb_state;
+
+/* number of double fields per beam for phase-space dimension m */
+static inline int32_t shgb_nfields(int32_t m) { return 2 * m + m * (m + 1) + 8; }
+
+/* ---- initial data -------------------------------------------------------
+ * Sec. 2.5 and Sec. 2.4 step 2.  Beam shape M0 = I, N0 = 0, P0 = 0, S0 = 0,
+ * A0 = (2 pi eps)^(-m/2) (each beam integrates to one), omega = 0, phase 1,
+ * all beams on component comp0, a fresh threshold from draw 0.  Centres:
+ *   q1 ~ N(q_mean, q_std^2);  p1 ~ N(p_a, p_b^2) or U[p_a, p_b);
+ *   bath k >= 2: q_k ~ N(0, eps/(2 mass w_k)), p_k ~ N(0, eps mass w_k / 2)
+ * (ground-state Wigner function with hbar -> eps).  Normals by Box-Muller. */
+typedef struct shgb_init_spec {
+  double q_mean, q_std;
+  int32_t p_dist;           /* SHGB_DIST_NORMAL or SHGB_DIST_UNIFORM */
+  double p_a, p_b;
+  int32_t comp0;            /* 0..SHGB_NCOMP-1 */
+} shgb_init_spec;
+
+/* Sample every beam of `st` (Sec. 2.5).  Errors: EINVAL for null pointers,
+ * m != 2d, ld < n_beams, bad spec. */
+int shgb_init_beams(const shgb_model *model, const shgb_init_spec *spec,
+                    const shgb_state *st, uint64_t seed, void *stream);
+
+/* Advance every beam by `nsteps` intervals of length dt (Sec. 2.4 steps 3-5):
+ * per interval a classical RK4 trial step of the beam ODEs (Sec. 2.3,
+ * eq. (2.24)) on the current component; if the rate integral reaches the
+ * threshold, the hop time is found by linear interpolation of Lam, the system
+ * is re-integrated to it, the hop is applied (shgb_hop) and the beam finishes
+ * the interval on its new component, up to SHGB_HOP_CAP hops per interval.
+ * The state is read once and written once per call; nsteps may be large.
+ * Errors: EINVAL (null pointers, nsteps < 0, dt not finite or <= 0),
+ * EUNSUPPORTED (d not built). */
+int shgb_step_ensemble(const shgb_model *model, const shgb_state *st, int32_t nsteps,
+                       double dt, uint64_t seed, uint64_t *diag, void *stream);
+
+/* Apply one hop (Sec. 2.4 step 5) to each listed beam at its current state:
+ * destination j != l drawn with probability |gamma_jl| / sum_k |gamma_kl|
+ * (inverse CDF over j ascending, uniform U from draw nhop+1), phase times
+ * gamma_jl/|gamma_jl|, logw += Lam, Lam = 0, l = j, nhop += 1, new threshold
+ * E = -log(1 - Y) from the same draw.  idx: device int32[n_idx], distinct
+ * beam indices (duplicates race); indices outside [0, n_beams) are skipped
+ * and counted in SHGB_DIAG_BAD_INDEX.  Errors: EINVAL. */
+int shgb_hop(const shgb_model *model, const shgb_state *st, const int32_t *idx,
+             int64_t n_idx, uint64_t seed, uint64_t *diag, void *stream);
+
+/* Component populations (Sec. 2.3 eq. (2.26) integrated over x, Sec. 2.4
+ * steps 6-7).  Per beam c = exp(logw+Lam) phase A exp(iS/eps)
+ * (2 pi eps)^(m/2) det(Z)^(-1/2) exp(-P^T Z^-1 P / (2 eps)) with the branch of
+ * det(Z)^(1/2) = prod of principal square roots of the LDL^T pivots.  out:
+ * device double[SHGB_NCOMP * 5], per component {sum Re c, sum Im c,
+ * sum (Re c)^2, sum (Im c)^2, count}; the population is sum c / N_traj.
+ * The reduction order is fixed: results are bitwise reproducible.
+ * work: device, >= shgb_populations_workspace(n_beams, m) bytes.
+ * Errors: EINVAL, EWORKSPACE. */
+int64_t shgb_populations_workspace(int64_t n_beams, int32_t m);
+int shgb_populations(const shgb_model *model, const shgb_state *st, double *out,
+                     void *work, int64_t work_bytes, uint64_t *diag, void *stream);
+
+/* Superposition at Q evaluation points (Sec. 2.3 eq. (2.26), Sec. 2.4 step 6):
+ * out[(i*Q + q)*2 + {0,1}] = Re, Im of sum_{k: l_k = i} exp(omega_k) G_k(x_q),
+ * G(x) = A exp(-(x-X)^T Z (x-X)/(2 eps) + i P.(x-X)/eps + i S/eps), unnormalised
+ * (divide by N_traj for U_i).  points: device double[Q * m], row-major.
+ * Fixed reduction order (bitwise reproducible).  work: device, >=
+ * shgb_reconstruct_workspace(n_beams, m, Q) bytes.  Errors: EINVAL, EWORKSPACE,
+ * EUNSUPPORTED. */
+int64_t shgb_reconstruct_workspace(int64_t n_beams, int32_t m, int64_t Q);
+int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double *points,
+                     int64_t Q, double *out, void *work, int64_t work_bytes, void *stream);
+
+/* Diagnostic: the raw Philox4x64-10 blocks for n counters (device
+ * uint64[4n] in and out) under key (seed, 0), as the kernels draw them. */
+int shgb_philox(uint64_t seed, const uint64_t *counters, uint64_t *out, int64_t n, void *stream);
+
+/* sizeof(shgb_model), sizeof(shgb_state), sizeof(shgb_init_spec) into sizes[0..2]
+ * (host array), so bindings can check their struct layouts. */
+void shgb_abi_sizes(int64_t *sizes);
+
+const char *shgb_strerror(int code);
+int32_t shgb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHGB_H */

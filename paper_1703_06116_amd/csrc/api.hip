@@ -1,0 +1,176 @@
+// The C ABI of libshgb: argument validation, model conversion and dispatch
+// to the kernels on the caller's stream.  No device allocation, no
+// synchronisation, no exceptions across the boundary.
+#include <cmath>
+#include <cstring>
+
+#include "device.h"
+
+namespace shgb {
+hipError_t launch_init(const DevModel &, const shgb_init_spec &, const shgb_state &, uint64_t, hipStream_t);
+hipError_t launch_step_m2(const DevModel &, const shgb_state &, int, double, uint64_t, uint64_t *, hipStream_t);
+hipError_t launch_step_wave(const DevModel &, const shgb_state &, int, double, uint64_t, uint64_t *, hipStream_t);
+bool step_wave_supported(int d);
+hipError_t launch_hop(const DevModel &, const shgb_state &, const int32_t *, int64_t, uint64_t, uint64_t *,
+                      hipStream_t);
+hipError_t launch_philox(uint64_t, const uint64_t *, uint64_t *, int64_t, hipStream_t);
+int64_t pop_workspace_bytes(int64_t, int);
+hipError_t launch_populations(const DevModel &, const shgb_state &, double *, void *, uint64_t *, hipStream_t);
+int64_t recon_m2_workspace_bytes(int64_t, int64_t);
+hipError_t launch_recon_m2(const DevModel &, const shgb_state &, const double *, int64_t, double *, void *,
+                           hipStream_t);
+int64_t recon_wave_workspace_bytes(int64_t, int, int64_t);
+bool recon_wave_supported(int m);
+hipError_t launch_recon_wave(const DevModel &, const shgb_state &, const double *, int64_t, double *, void *,
+                             hipStream_t);
+}  // namespace shgb
+
+using namespace shgb;
+
+namespace {
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int to_dev_model(const shgb_model *m, DevModel &md) {
+  if (!m) return SHGB_EINVAL;
+  if (m->kind != SHGB_MODEL_QCLE) return SHGB_EUNSUPPORTED;
+  if (m->d < 1 || m->d > SHGB_MAX_D) return SHGB_EINVAL;
+  if (!finite_pos(m->mass) || !finite_pos(m->eps)) return SHGB_EINVAL;
+  if (!std::isfinite(m->A) || !std::isfinite(m->B) || !std::isfinite(m->C) || !std::isfinite(m->D) ||
+      !std::isfinite(m->lam) || m->C == 0.0)
+    return SHGB_EINVAL;
+  std::memset(&md, 0, sizeof(md));
+  md.mass = m->mass;
+  md.inv_mass = 1.0 / m->mass;
+  md.eps = m->eps;
+  md.A = m->A;
+  md.B = m->B;
+  md.C = m->C;
+  md.D = m->D;
+  md.lam = m->lam;
+  md.d = m->d;
+  for (int k = 1; k < m->d; ++k) {
+    const double w = m->bath_omega[k - 1];
+    if (!finite_pos(w)) return SHGB_EINVAL;
+    md.bath_w[k] = w;
+    md.bath_k[k] = m->mass * w * w;
+  }
+  return SHGB_OK;
+}
+
+int check_state(const shgb_state *st, const DevModel &md) {
+  if (!st) return SHGB_EINVAL;
+  if (st->m != 2 * md.d || st->n_beams < 0 || st->ld < st->n_beams) return SHGB_EINVAL;
+  if (st->n_beams > 0 && (!st->f64 || !st->comp || !st->nhop)) return SHGB_EINVAL;
+  if (st->n_beams > (int64_t)INT32_MAX) return SHGB_EINVAL;  // beam indices are int32 in shgb_hop
+  return SHGB_OK;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? SHGB_OK : SHGB_EHIP; }
+
+}  // namespace
+
+extern "C" {
+
+int shgb_init_beams(const shgb_model *model, const shgb_init_spec *spec, const shgb_state *st, uint64_t seed,
+                    void *stream) {
+  DevModel md;
+  int rc = to_dev_model(model, md);
+  if (rc) return rc;
+  if ((rc = check_state(st, md))) return rc;
+  if (!spec) return SHGB_EINVAL;
+  if (!std::isfinite(spec->q_mean) || !(spec->q_std >= 0.0) || !std::isfinite(spec->p_a) ||
+      !std::isfinite(spec->p_b) || spec->comp0 < 0 || spec->comp0 >= SHGB_NCOMP)
+    return SHGB_EINVAL;
+  if (spec->p_dist != SHGB_DIST_NORMAL && spec->p_dist != SHGB_DIST_UNIFORM) return SHGB_EINVAL;
+  return hip_status(launch_init(md, *spec, *st, seed, (hipStream_t)stream));
+}
+
+int shgb_step_ensemble(const shgb_model *model, const shgb_state *st, int32_t nsteps, double dt, uint64_t seed,
+                       uint64_t *diag, void *stream) {
+  DevModel md;
+  int rc = to_dev_model(model, md);
+  if (rc) return rc;
+  if ((rc = check_state(st, md))) return rc;
+  if (nsteps < 0 || !finite_pos(dt)) return SHGB_EINVAL;
+  if (md.d == 1) return hip_status(launch_step_m2(md, *st, nsteps, dt, seed, diag, (hipStream_t)stream));
+  if (!step_wave_supported(md.d)) return SHGB_EUNSUPPORTED;
+  return hip_status(launch_step_wave(md, *st, nsteps, dt, seed, diag, (hipStream_t)stream));
+}
+
+int shgb_hop(const shgb_model *model, const shgb_state *st, const int32_t *idx, int64_t n_idx, uint64_t seed,
+             uint64_t *diag, void *stream) {
+  DevModel md;
+  int rc = to_dev_model(model, md);
+  if (rc) return rc;
+  if ((rc = check_state(st, md))) return rc;
+  if (n_idx < 0 || (n_idx > 0 && !idx)) return SHGB_EINVAL;
+  return hip_status(launch_hop(md, *st, idx, n_idx, seed, diag, (hipStream_t)stream));
+}
+
+int64_t shgb_populations_workspace(int64_t n_beams, int32_t m) {
+  if (n_beams < 0 || m < 2 || m > 2 * SHGB_MAX_D || (m & 1)) return -1;
+  return pop_workspace_bytes(n_beams, m);
+}
+
+int shgb_populations(const shgb_model *model, const shgb_state *st, double *out, void *work, int64_t work_bytes,
+                     uint64_t *diag, void *stream) {
+  DevModel md;
+  int rc = to_dev_model(model, md);
+  if (rc) return rc;
+  if ((rc = check_state(st, md))) return rc;
+  if (!out || !work) return SHGB_EINVAL;
+  if (st->m != 2 && st->m != 4 && st->m != 6 && st->m != 8 && st->m != 24) return SHGB_EUNSUPPORTED;
+  if (work_bytes < pop_workspace_bytes(st->n_beams, st->m)) return SHGB_EWORKSPACE;
+  return hip_status(launch_populations(md, *st, out, work, diag, (hipStream_t)stream));
+}
+
+int64_t shgb_reconstruct_workspace(int64_t n_beams, int32_t m, int64_t Q) {
+  if (n_beams < 0 || Q < 0 || m < 2 || m > 2 * SHGB_MAX_D || (m & 1)) return -1;
+  if (m == 2) return recon_m2_workspace_bytes(n_beams, Q);
+  return recon_wave_workspace_bytes(n_beams, m, Q);
+}
+
+int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double *points, int64_t Q, double *out,
+                     void *work, int64_t work_bytes, void *stream) {
+  DevModel md;
+  int rc = to_dev_model(model, md);
+  if (rc) return rc;
+  if ((rc = check_state(st, md))) return rc;
+  if (Q < 0 || (Q > 0 && (!points || !out || !work))) return SHGB_EINVAL;
+  if (Q > (int64_t)INT32_MAX) return SHGB_EINVAL;
+  if (st->m == 2) {
+    if (work_bytes < recon_m2_workspace_bytes(st->n_beams, Q)) return SHGB_EWORKSPACE;
+    return hip_status(launch_recon_m2(md, *st, points, Q, out, work, (hipStream_t)stream));
+  }
+  if (!recon_wave_supported(st->m)) return SHGB_EUNSUPPORTED;
+  if (work_bytes < recon_wave_workspace_bytes(st->n_beams, st->m, Q)) return SHGB_EWORKSPACE;
+  return hip_status(launch_recon_wave(md, *st, points, Q, out, work, (hipStream_t)stream));
+}
+
+int shgb_philox(uint64_t seed, const uint64_t *counters, uint64_t *out, int64_t n, void *stream) {
+  if (n < 0 || (n > 0 && (!counters || !out))) return SHGB_EINVAL;
+  return hip_status(launch_philox(seed, counters, out, n, (hipStream_t)stream));
+}
+
+const char *shgb_strerror(int code) {
+  switch (code) {
+    case SHGB_OK: return "ok";
+    case SHGB_EINVAL: return "invalid argument";
+    case SHGB_EUNSUPPORTED: return "unsupported model or dimension";
+    case SHGB_EHIP: return "HIP launch or runtime error";
+    case SHGB_EWORKSPACE: return "workspace too small";
+    default: return "unknown error";
+  }
+}
+
+int32_t shgb_version(void) { return 1; }
+
+void shgb_abi_sizes(int64_t *sizes) {
+  if (!sizes) return;
+  sizes[0] = (int64_t)sizeof(shgb_model);
+  sizes[1] = (int64_t)sizeof(shgb_state);
+  sizes[2] = (int64_t)sizeof(shgb_init_spec);
+}
+
+}  // extern "C"

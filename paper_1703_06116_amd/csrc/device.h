@@ -1,0 +1,214 @@
+// Device-side building blocks of libshgb: model parameters, state layout,
+// Philox4x64-10, the QCLE coefficient functions and the hop event.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "shgb.h"
+
+namespace shgb {
+
+// Kernel-argument copy of the model (by value, no host pointers).
+struct DevModel {
+  double mass, inv_mass, eps;
+  double A, B, C, D, lam;
+  double bath_w[SHGB_MAX_D];  // w_k for bath modes k = 1..d-1 (index 0 unused)
+  double bath_k[SHGB_MAX_D];  // mass * w_k^2
+  int d;
+};
+
+// Field offsets of the structure-of-arrays state for phase-space dimension m.
+struct Layout {
+  int m, T;
+  int64_t ld;
+  __host__ __device__ Layout(int m_, int64_t ld_) : m(m_), T(m_ * (m_ + 1) / 2), ld(ld_) {}
+  __host__ __device__ int X(int i) const { return i; }
+  __host__ __device__ int P(int i) const { return m + i; }
+  __host__ __device__ int Zre(int k) const { return 2 * m + k; }
+  __host__ __device__ int Zim(int k) const { return 2 * m + T + k; }
+  __host__ __device__ int S() const { return 2 * m + 2 * T; }
+  __host__ __device__ int Are() const { return S() + 1; }
+  __host__ __device__ int Aim() const { return S() + 2; }
+  __host__ __device__ int logw() const { return S() + 3; }
+  __host__ __device__ int phre() const { return S() + 4; }
+  __host__ __device__ int phim() const { return S() + 5; }
+  __host__ __device__ int Lam() const { return S() + 6; }
+  __host__ __device__ int E() const { return S() + 7; }
+  __host__ __device__ int nfields() const { return S() + 8; }
+  // packed upper-triangle index of (i, j), i <= j
+  __host__ __device__ static int tri(int m, int i, int j) { return i * m - i * (i - 1) / 2 + (j - i); }
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10, from Salmon, Moraes, Dror & Shaw, "Parallel random numbers:
+// as easy as 1, 2, 3" (SC'11): ten rounds of two 64x64->128 multiplications
+// with the published multipliers, key bumped by the Weyl constants.
+constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t kPhiloxM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73Bull;
+
+constexpr uint64_t kTagHop = 0x48;     // hop draws: word 0 -> U, word 1 -> Y
+constexpr uint64_t kTagNormal = 0x4E;  // Box-Muller normals, 4 per block
+constexpr uint64_t kTagUnif = 0x55;    // one uniform per coordinate
+
+struct U64x4 { uint64_t v[4]; };
+
+__host__ __device__ inline void mulhilo64(uint64_t a, uint64_t b, uint64_t &hi, uint64_t &lo) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  lo = a * b;
+  hi = __umul64hi(a, b);
+#else
+  unsigned __int128 p = (unsigned __int128)a * b;
+  lo = (uint64_t)p;
+  hi = (uint64_t)(p >> 64);
+#endif
+}
+
+__host__ __device__ inline U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                               uint64_t k0, uint64_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += kPhiloxW0; k1 += kPhiloxW1; }
+    uint64_t hi0, lo0, hi1, lo1;
+    mulhilo64(kPhiloxM0, c0, hi0, lo0);
+    mulhilo64(kPhiloxM1, c2, hi1, lo1);
+    uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  return U64x4{{c0, c1, c2, c3}};
+}
+
+__host__ __device__ inline U64x4 draw(uint64_t seed, uint64_t gid, uint64_t index, uint64_t tag) {
+  return philox4x64_10(gid, index, tag, 0, seed, 0);
+}
+
+// A 64-bit word to a double strictly inside (0, 1): ((w >> 12) + 1/2) 2^-52.
+__host__ __device__ inline double u01(uint64_t w) { return ((double)(w >> 12) + 0.5) * 0x1p-52; }
+
+// ---------------------------------------------------------------------------
+// QCLE adiabatic quantities along q1 (Sec. 3.3, eq. (3.6)):
+//   a = A tanh(Bq), c = C exp(-Dq^2), s = sqrt(a^2 + c^2) = (E1 - E2)/2,
+//   d21 = (a c' - c a') / (2 s^2);
+// with derivatives of s up to third order (the Hessian of E feeds the beam
+// Jacobian, the third derivative the curvature of P . alpha).
+struct Q1 { double s, s1, s2, s3, d21; };
+
+__host__ __device__ inline Q1 qcle_q1(const DevModel &md, double q) {
+  const double A = md.A, B = md.B, C = md.C, D = md.D;
+  // tanh and sech^2 from one exponential, accurate in the tails
+  const double x = B * q;
+  const double e = exp(-2.0 * fabs(x));
+  const double r = 1.0 / (1.0 + e);
+  const double th = copysign((1.0 - e) * r, x);
+  const double sech2 = 4.0 * e * r * r;
+  const double a = A * th;
+  const double a1 = A * B * sech2;
+  const double a2 = -2.0 * A * B * B * th * sech2;
+  const double a3 = -2.0 * A * B * B * B * sech2 * (1.0 - 3.0 * th * th);
+  const double c = C * exp(-D * q * q);
+  const double c1 = -2.0 * D * q * c;
+  const double c2 = (4.0 * D * D * q * q - 2.0 * D) * c;
+  const double c3 = (12.0 * D * D * q - 8.0 * D * D * D * q * q * q) * c;
+  const double s = sqrt(a * a + c * c);
+  const double rs = 1.0 / s;
+  Q1 o;
+  o.s = s;
+  o.s1 = (a * a1 + c * c1) * rs;
+  o.s2 = (a1 * a1 + a * a2 + c1 * c1 + c * c2 - o.s1 * o.s1) * rs;
+  o.s3 = (3.0 * (a1 * a2 + c1 * c2) + a * a3 + c * c3 - 3.0 * o.s1 * o.s2) * rs;
+  o.d21 = 0.5 * (a * c1 - c * a1) * rs * rs;
+  return o;
+}
+
+// E_l = Vb + sigma_l s and beta_l = bcoef_l s for the four components.
+__host__ __device__ inline double comp_sigma(int l) { return l == 0 ? 1.0 : (l == 1 ? -1.0 : 0.0); }
+__host__ __device__ inline double comp_bcoef(int l) { return l == 2 ? 2.0 : (l == 3 ? -2.0 : 0.0); }
+
+// Column l of gamma (row j receives from l) for the coupling kappa = (p/M).d21,
+// eq. (3.5) written for (u11, u22, u21, u12): gamma_jl = sign(l, j) kappa with
+//   l = 0: (0, 0, -1, -1);  l = 1: (0, 0, 1, 1);  l = 2, 3: (1, -1, 0, 0).
+// Written without branches: hipcc for gfx950 (ROCm 7.2) miscompiled the
+// equivalent if/else chain, leaving gamma_1l = 0 for l = 2, 3 in the
+// divergent case (the LLVM IR was correct; the machine code lost the store).
+__host__ __device__ inline void qcle_gamma_col(int l, double kappa, double col[SHGB_NCOMP]) {
+  const double coh = (l >= 2) ? 1.0 : 0.0;                       // leaving u21 or u12
+  const double pop = (l == 0) ? -1.0 : ((l == 1) ? 1.0 : 0.0);   // leaving u11 or u22
+  col[0] = coh * kappa;
+  col[1] = -coh * kappa;
+  col[2] = pop * kappa;
+  col[3] = pop * kappa;
+}
+
+// ---------------------------------------------------------------------------
+// Hop event (Sec. 2.4 step 5) on the scalar part of one beam's state.
+struct HopScalars {
+  double logw, phre, phim, Lam, E;
+  int comp;
+  uint32_t nhop;
+};
+
+struct Counters {
+  uint32_t hops = 0, thr_ties = 0, dest_ties = 0, cap = 0, zero_rate = 0, nonfinite = 0;
+};
+
+constexpr double kTieRel = 1e-12;
+
+__host__ __device__ inline void hop_event(const DevModel &md, double q1, double p1, HopScalars &h,
+                                 uint64_t gid, uint64_t seed, Counters &cnt) {
+  const Q1 k = qcle_q1(md, q1);
+  const double kappa = p1 * md.inv_mass * k.d21;
+  double col[SHGB_NCOMP];
+  qcle_gamma_col(h.comp, kappa, col);
+  const U64x4 w = draw(seed, gid, (uint64_t)h.nhop + 1u, kTagHop);
+  const double U = u01(w.v[0]);
+  const double Y = u01(w.v[1]);
+  const int l = h.comp;
+  double R = 0.0;
+#pragma unroll
+  for (int j = 0; j < SHGB_NCOMP; ++j)
+    if (j != l) R = R + fabs(col[j]);
+  int dest = l;
+  if (R > 0.0) {
+    const double UR = U * R;
+    double C = 0.0;
+    int last_pos = l;
+    bool chosen = false;
+#pragma unroll
+    for (int j = 0; j < SHGB_NCOMP; ++j) {
+      if (j == l) continue;
+      C = C + fabs(col[j]);
+      if (fabs(col[j]) > 0.0) last_pos = j;
+      if (fabs(UR - C) <= kTieRel * R) cnt.dest_ties++;
+      if (!chosen && UR < C) { dest = j; chosen = true; }
+    }
+    if (!chosen) dest = last_pos;
+    if (col[dest] < 0.0) { h.phre = -h.phre; h.phim = -h.phim; }  // gamma/|gamma| = -1
+  } else {
+    cnt.zero_rate++;
+  }
+  h.logw += h.Lam;
+  h.Lam = 0.0;
+  h.comp = dest;
+  h.nhop += 1u;
+  h.E = -log(1.0 - Y);
+  cnt.hops++;
+}
+
+// Wave-level sum of per-lane counters, one atomic per wave and counter.
+__device__ inline void flush_counters(const Counters &c, uint64_t *diag) {
+  if (!diag) return;
+  uint32_t v[6] = {c.hops, c.thr_ties, c.dest_ties, c.cap, c.zero_rate, c.nonfinite};
+  const int idx[6] = {SHGB_DIAG_HOPS, SHGB_DIAG_THR_TIES, SHGB_DIAG_DEST_TIES,
+                      SHGB_DIAG_CAP_OVERFLOW, SHGB_DIAG_ZERO_RATE, SHGB_DIAG_NONFINITE};
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    uint32_t x = v[t];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if ((threadIdx.x & 63) == 0 && x) atomicAdd((unsigned long long *)&diag[idx[t]], (unsigned long long)x);
+  }
+}
+
+}  // namespace shgb

@@ -1,0 +1,234 @@
+// Component populations (Sec. 2.3 eq. (2.26) integrated over x; Sec. 2.4
+// steps 6-7).  For each beam
+//   c = exp(logw + Lam) phase A exp(iS/eps) (2 pi eps)^(m/2) det(Z)^(-1/2)
+//       exp(-P^T Z^-1 P / (2 eps)),
+// the closed-form integral of exp(omega) G over R^m, with Z = L D L^T
+// (complex symmetric, no pivoting: Re Z = M is positive definite, so every
+// pivot has a positive real part) giving det(Z)^(1/2) = prod sqrt(d_j)
+// (principal roots: the branch continuous from real Z) and
+// P^T Z^-1 P = sum_j w_j^2 / d_j with L w = P.
+// Per component the kernel sums c, (Re c)^2, (Im c)^2 and the count; each
+// block writes its partial sums and one block adds the partials in a fixed
+// order, so the result is bitwise reproducible.
+#include "cplx.h"
+#include "device.h"
+
+namespace shgb {
+
+constexpr int kPopVals = SHGB_NCOMP * 5;
+constexpr int kPopThreads = 256;
+constexpr int64_t kPopMaxBlocks = 2048;
+
+int64_t pop_blocks(int64_t n) {
+  int64_t b = (n + kPopThreads - 1) / kPopThreads;
+  if (b < 1) b = 1;
+  return b < kPopMaxBlocks ? b : kPopMaxBlocks;
+}
+
+__device__ inline double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// Block-sum kPopVals values per thread into out[0..kPopVals) (thread 0 writes).
+__device__ inline void block_sum_store(const double (&acc)[kPopVals], double *out) {
+  __shared__ double red[kPopThreads / 64][kPopVals];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kPopVals; ++k) {
+    const double s = wave_sum(acc[k]);
+    if (lane == 0) red[wid][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kPopVals) {
+    double s = 0.0;
+    for (int w = 0; w < kPopThreads / 64; ++w) s += red[w][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+__device__ inline void tally(double (&acc)[kPopVals], int comp, cd c) {
+#pragma unroll
+  for (int i = 0; i < SHGB_NCOMP; ++i) {
+    const bool on = (comp == i);
+    acc[5 * i + 0] += on ? c.re : 0.0;
+    acc[5 * i + 1] += on ? c.im : 0.0;
+    acc[5 * i + 2] += on ? c.re * c.re : 0.0;
+    acc[5 * i + 3] += on ? c.im * c.im : 0.0;
+    acc[5 * i + 4] += on ? 1.0 : 0.0;
+  }
+}
+
+// exp(omega) A exp(iS/eps) for beam b
+__device__ inline cd beam_weight(const Layout &L, const double *f, int64_t ld, int64_t b, double inv_eps) {
+  const cd ph = {f[L.phre() * ld + b], f[L.phim() * ld + b]};
+  const cd A = {f[L.Are() * ld + b], f[L.Aim() * ld + b]};
+  const double mag = exp(f[L.logw() * ld + b] + f[L.Lam() * ld + b]);
+  double s, c;
+  sincos(f[L.S() * ld + b] * inv_eps, &s, &c);
+  return cmul(cmul(cscale(ph, mag), A), {c, s});
+}
+
+__global__ void __launch_bounds__(kPopThreads)
+pop_m2_kernel(DevModel md, const double *__restrict__ f, const int32_t *__restrict__ comp, int64_t n,
+              int64_t ld, double norm, double *__restrict__ partial, uint64_t *diag) {
+  const Layout L(2, ld);
+  const double inv_eps = 1.0 / md.eps;
+  double acc[kPopVals];
+#pragma unroll
+  for (int k = 0; k < kPopVals; ++k) acc[k] = 0.0;
+  uint32_t nonspd = 0;
+  for (int64_t b = (int64_t)blockIdx.x * kPopThreads + threadIdx.x; b < n;
+       b += (int64_t)gridDim.x * kPopThreads) {
+    const cd z11 = {f[L.Zre(0) * ld + b], f[L.Zim(0) * ld + b]};
+    const cd z12 = {f[L.Zre(1) * ld + b], f[L.Zim(1) * ld + b]};
+    const cd z22 = {f[L.Zre(2) * ld + b], f[L.Zim(2) * ld + b]};
+    const double P1 = f[L.P(0) * ld + b], P2 = f[L.P(1) * ld + b];
+    const cd d1 = z11;
+    const cd l21 = cdiv(z12, z11);
+    const cd d2 = csub(z22, cmul(l21, z12));
+    if (!(d1.re > 0.0) || !(d2.re > 0.0)) ++nonspd;
+    const cd w1 = {P1, 0.0};
+    const cd w2 = {P2 - l21.re * P1, -l21.im * P1};
+    const cd quad = cadd(cdiv(cmul(w1, w1), d1), cdiv(cmul(w2, w2), d2));
+    const cd sq = cmul(csqrt_principal(d1), csqrt_principal(d2));
+    const cd g = cdiv(cexp(cscale(quad, -0.5 * inv_eps)), sq);
+    const cd c = cscale(cmul(beam_weight(L, f, ld, b, inv_eps), g), norm);
+    tally(acc, comp[b], c);
+  }
+  block_sum_store(acc, partial + (int64_t)blockIdx.x * kPopVals);
+  if (diag) {
+    uint32_t x = nonspd;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if ((threadIdx.x & 63) == 0 && x) atomicAdd((unsigned long long *)&diag[SHGB_DIAG_NONSPD], (unsigned long long)x);
+  }
+}
+
+// One wave per beam for m > 2: Z in LDS, LDL^T with lanes over the trailing
+// submatrix.  kWaves beams per block.
+constexpr int kPopWaves = 4;
+
+template <int M>
+__global__ void __launch_bounds__(64 * kPopWaves)
+pop_wave_kernel(DevModel md, const double *__restrict__ f, const int32_t *__restrict__ comp, int64_t n,
+                int64_t ld, double norm, double *__restrict__ partial, uint64_t *diag) {
+  __shared__ double zr[kPopWaves][M][M + 1];
+  __shared__ double zi[kPopWaves][M][M + 1];
+  __shared__ double pw_re[kPopWaves][M], pw_im[kPopWaves][M];
+  const Layout L(M, ld);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const double inv_eps = 1.0 / md.eps;
+  double acc[kPopVals];
+#pragma unroll
+  for (int k = 0; k < kPopVals; ++k) acc[k] = 0.0;
+  uint32_t nonspd = 0;
+  for (int64_t b0 = (int64_t)blockIdx.x * kPopWaves; b0 < n; b0 += (int64_t)gridDim.x * kPopWaves) {
+    const int64_t b = b0 + wid;
+    const bool live = b < n;
+    if (live) {
+      for (int t = lane; t < M * M; t += 64) {
+        const int i = t / M, j = t % M;
+        const int k = i <= j ? Layout::tri(M, i, j) : Layout::tri(M, j, i);
+        zr[wid][i][j] = f[L.Zre(k) * ld + b];
+        zi[wid][i][j] = f[L.Zim(k) * ld + b];
+      }
+      if (lane < M) { pw_re[wid][lane] = f[L.P(lane) * ld + b]; pw_im[wid][lane] = 0.0; }
+    }
+    __syncthreads();
+    cd sq = {1.0, 0.0}, quad = {0.0, 0.0};
+    bool bad = false;
+    if (live) {
+      for (int k = 0; k < M; ++k) {
+        const cd dk = {zr[wid][k][k], zi[wid][k][k]};
+        if (!(dk.re > 0.0)) bad = true;
+        sq = cmul(sq, csqrt_principal(dk));
+        const cd wk = {pw_re[wid][k], pw_im[wid][k]};
+        quad = cadd(quad, cdiv(cmul(wk, wk), dk));
+        // trailing update: Z_ij -= Z_ik Z_kj / d_k, w_i -= (Z_ik / d_k) w_k  (i, j > k)
+        const int r = M - 1 - k;
+        for (int t = lane; t < r * r; t += 64) {
+          const int i = k + 1 + t / r, j = k + 1 + t % r;
+          const cd lik = cdiv({zr[wid][i][k], zi[wid][i][k]}, dk);
+          const cd u = cmul(lik, {zr[wid][k][j], zi[wid][k][j]});
+          zr[wid][i][j] -= u.re;
+          zi[wid][i][j] -= u.im;
+        }
+        if (lane < r) {
+          const int i = k + 1 + lane;
+          const cd lik = cdiv({zr[wid][i][k], zi[wid][i][k]}, dk);
+          const cd u = cmul(lik, wk);
+          pw_re[wid][i] -= u.re;
+          pw_im[wid][i] -= u.im;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+    __syncthreads();
+    if (live && lane == 0) {
+      if (bad) ++nonspd;
+      const double pre = pow(2.0 * M_PI * md.eps, 0.5 * M);
+      const cd g = cscale(cdiv(cexp(cscale(quad, -0.5 * inv_eps)), sq), pre);
+      const cd c = cscale(cmul(beam_weight(L, f, ld, b, inv_eps), g), norm);
+      tally(acc, comp[b], c);
+    }
+  }
+  block_sum_store(acc, partial + (int64_t)blockIdx.x * kPopVals);
+  if (diag) {
+    uint32_t x = nonspd;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if ((threadIdx.x & 63) == 0 && x) atomicAdd((unsigned long long *)&diag[SHGB_DIAG_NONSPD], (unsigned long long)x);
+  }
+}
+
+__global__ void __launch_bounds__(kPopThreads)
+pop_final_kernel(const double *__restrict__ partial, int64_t nblocks, double *__restrict__ out) {
+  double acc[kPopVals];
+#pragma unroll
+  for (int k = 0; k < kPopVals; ++k) acc[k] = 0.0;
+  for (int64_t p = threadIdx.x; p < nblocks; p += kPopThreads)
+#pragma unroll
+    for (int k = 0; k < kPopVals; ++k) acc[k] += partial[p * kPopVals + k];
+  block_sum_store(acc, out);
+}
+
+int64_t pop_workspace_bytes(int64_t n, int m) {
+  const int64_t blocks = (m == 2) ? pop_blocks(n) : pop_blocks((n + kPopWaves - 1) / kPopWaves * kPopThreads);
+  return blocks * kPopVals * (int64_t)sizeof(double);
+}
+
+hipError_t launch_populations(const DevModel &md, const shgb_state &st, double *out, void *work,
+                              uint64_t *diag, hipStream_t stream) {
+  double *partial = (double *)work;
+  if (st.m == 2) {
+    const int64_t blocks = pop_blocks(st.n_beams);
+    const double norm = 2.0 * M_PI * md.eps;  // (2 pi eps)^(m/2)
+    hipLaunchKernelGGL(pop_m2_kernel, dim3((unsigned)blocks), dim3(kPopThreads), 0, stream, md, st.f64,
+                       st.comp, st.n_beams, st.ld, norm, partial, diag);
+    hipLaunchKernelGGL(pop_final_kernel, dim3(1), dim3(kPopThreads), 0, stream, partial, blocks, out);
+    return hipGetLastError();
+  }
+  const int64_t blocks = pop_blocks((st.n_beams + kPopWaves - 1) / kPopWaves * kPopThreads);
+#define SHGB_POP_CASE(MM)                                                                             \
+  case MM:                                                                                            \
+    hipLaunchKernelGGL(pop_wave_kernel<MM>, dim3((unsigned)blocks), dim3(64 * kPopWaves), 0, stream, md, \
+                       st.f64, st.comp, st.n_beams, st.ld, 1.0, partial, diag);                       \
+    break;
+  switch (st.m) {
+    SHGB_POP_CASE(4)
+    SHGB_POP_CASE(6)
+    SHGB_POP_CASE(8)
+    SHGB_POP_CASE(24)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef SHGB_POP_CASE
+  hipLaunchKernelGGL(pop_final_kernel, dim3(1), dim3(kPopThreads), 0, stream, partial, blocks, out);
+  return hipGetLastError();
+}
+
+}  // namespace shgb

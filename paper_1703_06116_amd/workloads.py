@@ -1,0 +1,93 @@
+"""Seeded synthetic inputs shaped like the paper's QCLE workloads.
+
+Parameter tables and random draws only: no step of the method lives here.
+Both the HIP path (bench, tests) and the CPU oracle (tests) receive their
+inputs from this module; it imports neither.
+
+Workloads (two-level QCLE, Sec. 3.3, with nuclear mass 2000):
+
+* ``qcle1d_1e4``   1-D avoided crossing, 1e4 beams, 2000 RK4 steps of 0.5,
+                   q ~ N(-5, 0.5^2), p ~ N(20, 1), lower surface, eps = 0.01.
+* ``qcle1d_1e6``   same model, 1e6 beams, 4000 steps, p ~ U[10, 30];
+                   populations and the field on a 64 x 64 grid of (q, p).
+* ``qcle12d_2p18`` d = 12 nuclear coordinates (phase space m = 24): q2..q12
+                   harmonic with w_k ~ U[0.002, 0.02] coupled to q1 by
+                   lam = 1e-3, 2^18 beams, 2000 steps, eps = 0.02; the field at
+                   16384 points scattered around beam centres.
+"""
+
+import numpy as np
+
+POT = dict(A=0.01, B=1.6, C=0.005, D=1.0, mass=2000.0)
+
+CONFIGS = {
+    "qcle1d_1e4": dict(d=1, eps=0.01, n_beams=10_000, nsteps=2000, dt=0.5, q_mean=-5.0, q_std=0.5,
+                       p_dist="normal", p_a=20.0, p_b=1.0, comp0=1, seed=0x1703061160000001,
+                       n_points=0),
+    "qcle1d_1e6": dict(d=1, eps=0.01, n_beams=1_000_000, nsteps=4000, dt=0.5, q_mean=-5.0, q_std=0.5,
+                       p_dist="uniform", p_a=10.0, p_b=30.0, comp0=1, seed=0x1703061160000002,
+                       n_points=4096),
+    "qcle12d_2p18": dict(d=12, eps=0.02, n_beams=2**18, nsteps=2000, dt=0.5, q_mean=-5.0, q_std=0.5,
+                         p_dist="normal", p_a=20.0, p_b=1.0, comp0=1, seed=0x1703061160000003,
+                         n_points=16384, lam=1e-3),
+}
+
+
+def bath_omega(d, seed=1703061163):
+    """Bath frequencies w_2..w_d ~ U[0.002, 0.02], drawn once."""
+    if d <= 1:
+        return np.zeros(0)
+    return np.random.default_rng(seed).uniform(0.002, 0.02, d - 1)
+
+
+def config(name, **overrides):
+    c = dict(CONFIGS[name])
+    c.update(POT)
+    c.setdefault("lam", 0.0)
+    c["bath_omega"] = bath_omega(c["d"])
+    c.update(overrides)
+    return c
+
+
+def grid_points_2d(nq=64, npts=64, qlim=(0.0, 30.0), plim=(0.0, 35.0)):
+    """Uniform (q, p) grid covering the final 1-D ensemble, row-major, (nq*npts, 2)."""
+    q = np.linspace(qlim[0], qlim[1], nq)
+    p = np.linspace(plim[0], plim[1], npts)
+    Q, P = np.meshgrid(q, p, indexing="ij")
+    return np.ascontiguousarray(np.stack([Q.ravel(), P.ravel()], 1))
+
+
+def points_near(centres, eps, n, seed):
+    """n points x = X_k + sqrt(eps) xi around randomly chosen centres."""
+    rng = np.random.default_rng(seed)
+    centres = np.asarray(centres, dtype=np.float64)
+    k = rng.integers(0, centres.shape[0], n)
+    return np.ascontiguousarray(centres[k] + np.sqrt(eps) * rng.normal(size=(n, centres.shape[1])))
+
+
+def synthetic_ensemble(n, m, seed, q_range=(5.0, 25.0), p_range=(10.0, 30.0), z_scale=0.5,
+                       p_scale=1.0, s_scale=3.0, logw_scale=1.0, n_comp=4, a0=1.0):
+    """A random beam state shaped like an evolved QCLE ensemble (host arrays).
+
+    Centres spread over the ranges the ensemble reaches, Z = M + iN with M
+    symmetric positive definite (M = I + L L^T / m) and N symmetric, phase
+    space wave vectors P of size p_scale, phases S, weights exp(logw + Lam)
+    with unit phase +-1, components uniform over n_comp.
+    """
+    rng = np.random.default_rng(seed)
+    d = m // 2
+    X = np.zeros((n, m))
+    X[:, 0] = rng.uniform(*q_range, n)
+    X[:, d] = rng.uniform(*p_range, n)
+    if d > 1:
+        X[:, 1:d] = rng.normal(0, 0.05, (n, d - 1))
+        X[:, d + 1:] = rng.normal(0, 0.5, (n, d - 1))
+    L = rng.normal(0, z_scale, (n, m, m))
+    M = np.eye(m)[None] + L @ np.swapaxes(L, 1, 2) / m
+    K = rng.normal(0, z_scale, (n, m, m))
+    N = 0.5 * (K + np.swapaxes(K, 1, 2))
+    return dict(
+        X=X, P=rng.normal(0, p_scale, (n, m)), Z=M + 1j * N, S=rng.normal(0, s_scale, n),
+        A=np.full(n, a0, dtype=np.complex128), logw=np.abs(rng.normal(0, logw_scale, n)),
+        phase=rng.choice([-1.0, 1.0], n).astype(np.complex128), Lam=np.abs(rng.normal(0, 0.3, n)),
+        E=rng.exponential(1.0, n), comp=rng.integers(0, n_comp, n), nhop=rng.integers(0, 5, n))

@@ -1,0 +1,130 @@
+"""Host-side checks of libshgb.so (no GPU needed, no kernel launched).
+
+* the library loads and exports every function include/shgb.h declares;
+* the ctypes structs match the C struct sizes;
+* argument validation rejects bad calls before any HIP call.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "shgb.h")
+
+
+def _ensure_built():
+    from paper_1703_06116_amd import build
+    srcs = [os.path.join(build.CSRC, f) for f in os.listdir(build.CSRC)] + [HEADER]
+    newest = max(os.path.getmtime(s) for s in srcs)
+    if not os.path.exists(build.LIB) or os.path.getmtime(build.LIB) < newest:
+        build.build(verbose=False)
+
+
+@pytest.fixture(scope="module")
+def binding():
+    _ensure_built()
+    import paper_1703_06116_amd.shgb as b
+    return b
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b(shgb_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n != "shgb_nfields"))   # shgb_nfields is static inline
+
+
+def test_every_declared_function_is_exported(binding):
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    decl = declared_functions()
+    assert len(decl) >= 10, decl
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert set(decl) == set(binding.EXPORTED)
+
+
+def test_abi_sizes_and_version(binding):
+    sizes = (ctypes.c_int64 * 3)()
+    binding._lib.shgb_abi_sizes(ctypes.cast(sizes, ctypes.c_void_p))
+    assert tuple(sizes) == (ctypes.sizeof(binding.Model), ctypes.sizeof(binding.StateDesc),
+                            ctypes.sizeof(binding.InitSpec))
+    assert binding._lib.shgb_version() >= 1
+    assert binding._lib.shgb_strerror(-1) == b"invalid argument"
+
+
+def _model(binding, d=1, **kw):
+    p = dict(mass=2000.0, eps=0.01, A=0.01, B=1.6, C=0.005, D=1.0)
+    p.update(kw)
+    return binding.make_model(d, **p)
+
+
+def _desc(binding, n=16, m=2, ld=None, fake=0x1000):
+    return binding.StateDesc(fake, fake, fake, n, n if ld is None else ld, 0, m)
+
+
+def test_validation_rejects_bad_arguments(binding):
+    lib = binding._lib
+    mdl, st = _model(binding), _desc(binding)
+    spec = binding.make_init_spec(-5, 0.5, "normal", 20, 1, 1)
+    nul = ctypes.c_void_p(0)
+    EINVAL, EUNS, EWS = -1, -2, -4
+    by = ctypes.byref
+    # null model / state / spec
+    assert lib.shgb_init_beams(None, by(spec), by(st), 1, nul) == EINVAL
+    assert lib.shgb_init_beams(by(mdl), None, by(st), 1, nul) == EINVAL
+    assert lib.shgb_step_ensemble(by(mdl), None, 1, 0.5, 1, nul, nul) == EINVAL
+    # m inconsistent with d, ld < n, null arrays
+    assert lib.shgb_step_ensemble(by(mdl), by(_desc(binding, m=4)), 1, 0.5, 1, nul, nul) == EINVAL
+    assert lib.shgb_step_ensemble(by(mdl), by(_desc(binding, ld=3)), 1, 0.5, 1, nul, nul) == EINVAL
+    assert lib.shgb_step_ensemble(by(mdl), by(_desc(binding, fake=0)), 1, 0.5, 1, nul, nul) == EINVAL
+    # bad step parameters
+    assert lib.shgb_step_ensemble(by(mdl), by(st), -1, 0.5, 1, nul, nul) == EINVAL
+    assert lib.shgb_step_ensemble(by(mdl), by(st), 1, 0.0, 1, nul, nul) == EINVAL
+    assert lib.shgb_step_ensemble(by(mdl), by(st), 1, float("nan"), 1, nul, nul) == EINVAL
+    # bad model parameters
+    for bad in (dict(mass=0.0), dict(eps=-1.0), dict(C=0.0), dict(A=float("inf"))):
+        assert lib.shgb_step_ensemble(by(_model(binding, **bad)), by(st), 1, 0.5, 1, nul, nul) == EINVAL
+    bad_kind = _model(binding)
+    bad_kind.kind = 7
+    assert lib.shgb_step_ensemble(by(bad_kind), by(st), 1, 0.5, 1, nul, nul) == EUNS
+    m3 = _model(binding, d=3)   # bath frequencies must be positive
+    assert lib.shgb_step_ensemble(by(m3), by(_desc(binding, m=6)), 1, 0.5, 1, nul, nul) == EINVAL
+    # bad init spec
+    spec_bad = binding.make_init_spec(-5, -0.5, "normal", 20, 1, 1)
+    assert lib.shgb_init_beams(by(mdl), by(spec_bad), by(st), 1, nul) == EINVAL
+    spec_bad = binding.make_init_spec(-5, 0.5, "normal", 20, 1, 4)
+    assert lib.shgb_init_beams(by(mdl), by(spec_bad), by(st), 1, nul) == EINVAL
+    # hop: negative count, null list
+    assert lib.shgb_hop(by(mdl), by(st), nul, 3, 1, nul, nul) == EINVAL
+    assert lib.shgb_hop(by(mdl), by(st), ctypes.c_void_p(0x10), -1, 1, nul, nul) == EINVAL
+    # workspaces
+    need = lib.shgb_populations_workspace(16, 2)
+    assert need > 0
+    assert lib.shgb_populations(by(mdl), by(st), ctypes.c_void_p(0x10), ctypes.c_void_p(0x10), need - 1,
+                                nul, nul) == EWS
+    assert lib.shgb_populations_workspace(-1, 2) == -1 and lib.shgb_populations_workspace(4, 3) == -1
+    wr = lib.shgb_reconstruct_workspace(16, 2, 100)
+    assert wr > 0
+    assert lib.shgb_reconstruct(by(mdl), by(st), ctypes.c_void_p(0x10), 100, ctypes.c_void_p(0x10),
+                                ctypes.c_void_p(0x10), wr - 1, nul) == EWS
+    assert lib.shgb_reconstruct(by(mdl), by(st), nul, 100, ctypes.c_void_p(0x10), ctypes.c_void_p(0x10),
+                                wr, nul) == EINVAL
+    assert lib.shgb_philox(1, nul, nul, 5, nul) == EINVAL
+
+
+def test_zero_work_calls_launch_nothing(binding):
+    # zero beams / zero steps / zero listed beams return OK without touching the device
+    lib = binding._lib
+    mdl = _model(binding)
+    nul = ctypes.c_void_p(0)
+    empty = binding.StateDesc(0, 0, 0, 0, 0, 0, 2)
+    by = ctypes.byref
+    spec = binding.make_init_spec(-5, 0.5, "uniform", 10, 30, 1)
+    assert lib.shgb_init_beams(by(mdl), by(spec), by(empty), 1, nul) == 0
+    assert lib.shgb_step_ensemble(by(mdl), by(empty), 10, 0.5, 1, nul, nul) == 0
+    assert lib.shgb_step_ensemble(by(mdl), by(_desc(binding)), 0, 0.5, 1, nul, nul) == 0
+    assert lib.shgb_hop(by(mdl), by(_desc(binding)), nul, 0, 1, nul, nul) == 0
+    assert lib.shgb_philox(1, nul, nul, 0, nul) == 0
