@@ -34,6 +34,15 @@ def oracle_init(c, n, offset=0):
                                c["p_dist"], c["p_a"], c["p_b"], c["comp0"], beam_id_offset=offset)
 
 
+def oracle_init_ids(c, ids):
+    """Oracle initial beams for arbitrary global ids (each sampled on its own)."""
+    parts = [oracle_init(c, 1, int(g)) for g in ids]
+    e = oshgb.Ensemble(len(ids), parts[0].m, parts[0].n_comp)
+    for f in ("X", "P", "M", "N", "S", "A", "logw", "phase", "Lam", "E", "comp", "nhop", "gid"):
+        getattr(e, f)[:] = np.concatenate([getattr(p, f) for p in parts])
+    return e
+
+
 def ensemble_from_arrays(a, n_comp=4, gid0=0):
     """Oracle ensemble from host arrays (workloads.synthetic_ensemble or an oracle dump)."""
     X = np.asarray(a["X"])

@@ -1,0 +1,81 @@
+"""Full-size GPU checks in the launch configuration bench.py times.
+
+The whole workload runs on the GPU; the oracle recomputes a sample of beams
+one by one from their global ids (same seeds), and the quantities the oracle
+cannot reach at this size are checked through properties that hold at any
+size (trace conservation, conjugate symmetry, vanishing imaginary parts).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import observables, shgb as oshgb
+from paper_1703_06116_amd import workloads
+
+from _parity import (compare_states, ensemble_from_arrays, gpu_model, gpu_spec, oracle_init_ids,
+                     oracle_model)
+
+pytestmark = pytest.mark.gpu
+
+
+def run_gpu(gpu, c):
+    st = gpu.State(c["n_beams"], 2 * c["d"], device="cuda")
+    diag = gpu.new_diag()
+    mdl = gpu_model(c)
+    gpu.init_beams(mdl, gpu_spec(c), st, c["seed"])
+    gpu.step_ensemble(mdl, st, c["nsteps"], c["dt"], c["seed"], diag)
+    return st, diag
+
+
+def sample_ids(n, k, seed):
+    rng = np.random.default_rng(seed)
+    ids = np.sort(rng.choice(n - 2, k - 2, replace=False) + 1)
+    return np.concatenate([[0], ids, [n - 1]])
+
+
+@pytest.mark.parametrize("name,k", [("qcle1d_1e4", 64), ("qcle1d_1e6", 40)])
+def test_full_size_sampled_beams(gpu, name, k):
+    c = workloads.config(name)
+    st, diag = run_gpu(gpu, c)
+    g_all = gpu.unpack(st)
+    ids = sample_ids(c["n_beams"], k, seed=5)
+    g = {key: v[ids] for key, v in g_all.items()}
+    e = oracle_init_ids(c, ids)
+    oshgb.advance(oracle_model(c), e, c["nsteps"], c["dt"], c["seed"])
+    errs, ties = compare_states(g, e, min_ok=0.9, label=name)
+    assert e.nhop.sum() > 0
+    d = diag.cpu().numpy()
+    assert d[3] == 0 and d[4] == 0
+    # properties over the whole ensemble
+    sums = gpu.populations(gpu_model(c), st).cpu().numpy()
+    mean, se = gpu.population_mean_se(sums, c["n_beams"])
+    assert sums[:, 4].sum() == c["n_beams"]
+    assert abs(mean[0].real + mean[1].real - 1.0) < 4 * np.hypot(se[0].real, se[1].real)
+    for i in (0, 1):
+        assert abs(mean[i].imag) < 4 * se[i].imag + 1e-12
+    dc = mean[3] - np.conj(mean[2])
+    assert abs(dc.real) < 4 * np.hypot(se[2].real, se[3].real)
+    assert abs(dc.imag) < 4 * np.hypot(se[2].imag, se[3].imag)
+    print(name, "errors", errs, "ties", ties, "hops", int(d[0]))
+
+
+def test_full_size_field_on_grid(gpu):
+    """Field of a 1e6-beam ensemble on the bench's 64 x 64 grid; sampled points by the oracle."""
+    c = workloads.config("qcle1d_1e6")
+    n = c["n_beams"]
+    a = workloads.synthetic_ensemble(n, 2, seed=11, q_range=(5.0, 25.0), p_range=(10.0, 30.0),
+                                     a0=1.0 / (2 * np.pi * c["eps"]))
+    st = gpu.pack(a)
+    pts = workloads.grid_points_2d()
+    out = gpu.reconstruct(gpu_model(c), st, torch.from_numpy(pts).cuda()).cpu().numpy()
+    rng = np.random.default_rng(3)
+    qs = np.concatenate([[0, len(pts) - 1], rng.choice(len(pts), 10, replace=False)])
+    e = ensemble_from_arrays(a)
+    ref = observables.reconstruct(e, c["eps"], pts[qs], chunk=50_000)
+    scale = observables.reconstruct_abs(e, c["eps"], pts[qs], chunk=50_000)
+    assert (np.abs(out[:, qs] - ref) <= 1e-10 * scale + 1e-300).all()
+    assert np.abs(ref).max() > 0
+    sums = gpu.populations(gpu_model(c), st).cpu().numpy()
+    pref = observables.populations(e, c["eps"])
+    assert np.abs(sums[:, :2] - pref[:, :2]).max() <= 1e-12 * np.abs(observables.beam_integrals(e, c["eps"])).sum()
