@@ -37,6 +37,14 @@ FLOPS_PER_BEAM_STEP_M2 = 4 * 120 + 3 * 24 + 73
 # per beam-point evaluation of the m = 2 field: y, quadratic form and phase
 # (18), exp, sincos (counted 2), complex multiply-accumulate (8)
 FLOPS_PER_EVAL_M2 = 18 + 1 + 2 + 8
+# FP64 operations per beam-step of the m = 24 wave kernel, counted the same way:
+# per right-hand side 3616 (adiabatic quantities 87, Zrr 78 entries x 14 + 3,
+# Zrp 144 x 10, Zpp 78 x 4, row/column sums 528, X and P 150, scalars 4) and 13
+# per state double for the Runge-Kutta combinations (650 doubles).
+FLOPS_PER_BEAM_STEP_M24 = 4 * 3616 + 13 * 650
+# per beam-point evaluation of the m = 24 field: the exponent as a contraction over
+# F = 325 features for Re and Im (4 F = 1300, the matrix-core work)
+FLOPS_PER_EVAL_M24 = 4 * 325
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 64 lanes x 2 flop x 2.4 GHz
 # HBM bytes per launch of step_m2_kernel at 1e6 beams, from rocprofv3 FETCH_SIZE (x2.000) and
 # WRITE_SIZE (x1.000) scaled by a 1 GiB copy (profiles/step_m2_qcle1d_1e6.md); the kernel
@@ -112,8 +120,8 @@ def main():
 
     c = workloads.config(a.config)
     N, nsteps, dt, seed, m = c["n_beams"], c["nsteps"], c["dt"], c["seed"], 2 * c["d"]
-    if m != 2:
-        raise SystemExit("bench.py drives the m = 2 workloads")
+    if m not in (2, 24):
+        raise SystemExit("bench.py drives the m = 2 and m = 24 workloads")
     mdl = shgb.make_model(c["d"], c["mass"], c["eps"], c["A"], c["B"], c["C"], c["D"], c["lam"],
                           c["bath_omega"])
     spec = shgb.make_init_spec(c["q_mean"], c["q_std"], c["p_dist"], c["p_a"], c["p_b"], c["comp0"])
@@ -123,7 +131,7 @@ def main():
     diag = shgb.new_diag(dev)
     pops = torch.empty((4, 5), dtype=torch.float64, device=dev)
     pop_work = torch.empty(max(shgb.populations_workspace(N, m), 8), dtype=torch.uint8, device=dev)
-    pts_np = workloads.grid_points_2d()
+    pts_np = workloads.grid_points_2d() if m == 2 else workloads.points_near_final(c, c["n_points"], seed=3)
     Q = pts_np.shape[0] if c["n_points"] else 0
     pts = torch.from_numpy(pts_np[:Q]).to(dev)
     rec = torch.empty((4, Q, 2), dtype=torch.float64, device=dev)
@@ -162,7 +170,9 @@ def main():
                 for i, n in enumerate(names)}
     value = N * nsteps / (ms_per_step / 1e3)
     evals_per_s = N * Q / (phase_ms["reconstruct"] / 1e3) if Q else None
-    step_tflops = FLOPS_PER_BEAM_STEP_M2 * N * nsteps / (phase_ms["step"] / 1e3) / 1e12
+    fps = FLOPS_PER_BEAM_STEP_M2 if m == 2 else FLOPS_PER_BEAM_STEP_M24
+    fpe = FLOPS_PER_EVAL_M2 if m == 2 else FLOPS_PER_EVAL_M24
+    step_tflops = fps * N * nsteps / (phase_ms["step"] / 1e3) / 1e12
     pop_host = pops.cpu().numpy()
     mean, se = shgb.population_mean_se(pop_host, N)
     d = diag.cpu().numpy() // max(a.steps, 1)
@@ -180,19 +190,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": a.config, "model": "qcle-two-level-1d", "n_beams": N, "intervals": nsteps,
+        "config": {"workload": a.config, "model": f"qcle-two-level-{c['d']}d", "n_beams": N, "intervals": nsteps,
                    "dt": dt, "eps": c["eps"], "eval_points": Q, "phase_space_dim": m,
                    "parallelism": "none (1 GPU)"},
         "beam_point_evals_per_s": evals_per_s,
         "kernel_ms": phase_ms,
-        "roofline": {"bound": "alu", "kernel": "step_m2_kernel", "achieved": step_tflops,
+        "roofline": {"bound": "alu", "kernel": "step_m2_kernel" if m == 2 else "step_wave_kernel<12>",
+                     "achieved": step_tflops,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": step_tflops / PEAK_FP64_TFLOPS,
                      "traffic": STEP_M2_TRAFFIC.get(a.config), "traffic_unit": "bytes/launch",
-                     "algorithmic_bytes": 272 * N,
-                     "flops_per_unit": FLOPS_PER_BEAM_STEP_M2, "units_per_launch": N * nsteps},
-        "reconstruct_roofline": ({"bound": "alu", "achieved": FLOPS_PER_EVAL_M2 * evals_per_s / 1e12,
+                     "algorithmic_bytes": (272 if m == 2 else 2 * 8 * (2 * m + m * (m + 1) + 6)) * N,
+                     "flops_per_unit": fps, "units_per_launch": N * nsteps},
+        "reconstruct_roofline": ({"bound": "alu" if m == 2 else "mfma", "achieved": fpe * evals_per_s / 1e12,
                                   "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                                  "frac": FLOPS_PER_EVAL_M2 * evals_per_s / 1e12 / PEAK_FP64_TFLOPS}
+                                  "frac": fpe * evals_per_s / 1e12 / PEAK_FP64_TFLOPS,
+                                  "flops_per_unit": fpe}
                                  if Q else None),
         "populations": {"mean_re": mean.real.tolist(), "mean_im": mean.imag.tolist(),
                         "se_re": se.real.tolist()},

@@ -43,6 +43,10 @@ def _compile(src):
 def build(jobs=None, verbose=True):
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    live = {os.path.basename(x) + ".o" for x in srcs}
+    for stale in glob.glob(os.path.join(BUILD, "*.o")):
+        if os.path.basename(stale) not in live:
+            os.remove(stale)
     jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))

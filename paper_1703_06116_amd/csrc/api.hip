@@ -23,6 +23,9 @@ int64_t recon_wave_workspace_bytes(int64_t, int, int64_t);
 bool recon_wave_supported(int m);
 hipError_t launch_recon_wave(const DevModel &, const shgb_state &, const double *, int64_t, double *, void *,
                              hipStream_t);
+int64_t recon_mfma_workspace_bytes(int64_t, int64_t);
+hipError_t launch_recon_mfma(const DevModel &, const shgb_state &, const double *, int64_t, double *, void *,
+                             hipStream_t);
 }  // namespace shgb
 
 using namespace shgb;
@@ -128,6 +131,7 @@ int shgb_populations(const shgb_model *model, const shgb_state *st, double *out,
 int64_t shgb_reconstruct_workspace(int64_t n_beams, int32_t m, int64_t Q) {
   if (n_beams < 0 || Q < 0 || m < 2 || m > 2 * SHGB_MAX_D || (m & 1)) return -1;
   if (m == 2) return recon_m2_workspace_bytes(n_beams, Q);
+  if (m == 24) return recon_mfma_workspace_bytes(n_beams, Q);
   return recon_wave_workspace_bytes(n_beams, m, Q);
 }
 
@@ -142,6 +146,10 @@ int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double
   if (st->m == 2) {
     if (work_bytes < recon_m2_workspace_bytes(st->n_beams, Q)) return SHGB_EWORKSPACE;
     return hip_status(launch_recon_m2(md, *st, points, Q, out, work, (hipStream_t)stream));
+  }
+  if (st->m == 24) {
+    if (work_bytes < recon_mfma_workspace_bytes(st->n_beams, Q)) return SHGB_EWORKSPACE;
+    return hip_status(launch_recon_mfma(md, *st, points, Q, out, work, (hipStream_t)stream));
   }
   if (!recon_wave_supported(st->m)) return SHGB_EUNSUPPORTED;
   if (work_bytes < recon_wave_workspace_bytes(st->n_beams, st->m, Q)) return SHGB_EWORKSPACE;

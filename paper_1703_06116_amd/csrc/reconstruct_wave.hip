@@ -1,4 +1,4 @@
-// Superposition at evaluation points for phase space m = 2d > 2, FP64 on
+// Superposition at evaluation points for phase space m = 4, 6, 8, FP64 on
 // the vector ALU (Sec. 2.3 eq. (2.26), Sec. 2.4 step 6).  A block owns 256
 // points (one per thread, kept in registers) and a chunk of beams; beams pass
 // through LDS in tiles whose coefficients are formed once per tile:
@@ -143,7 +143,7 @@ __global__ void recon_wave_reduce(const double *__restrict__ partial, int64_t n_
   out[e] = s;
 }
 
-bool recon_wave_supported(int m) { return m == 4 || m == 6 || m == 8 || m == 24; }
+bool recon_wave_supported(int m) { return m == 4 || m == 6 || m == 8; }
 
 int64_t recon_wave_workspace_bytes(int64_t n, int, int64_t Q) {
   const RwTiling t = rw_tiling(n, Q);
@@ -171,7 +171,6 @@ hipError_t launch_recon_wave(const DevModel &md, const shgb_state &st, const dou
     SHGB_RW_CASE(4)
     SHGB_RW_CASE(6)
     SHGB_RW_CASE(8)
-    SHGB_RW_CASE(24)
     default:
       return hipErrorInvalidValue;
   }

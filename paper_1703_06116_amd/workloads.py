@@ -65,6 +65,30 @@ def points_near(centres, eps, n, seed):
     return np.ascontiguousarray(centres[k] + np.sqrt(eps) * rng.normal(size=(n, centres.shape[1])))
 
 
+def points_near_final(c, n, seed):
+    """n evaluation points around a stand-in for the final ensemble of a QCLE workload.
+
+    Centres: p1 from the workload's initial law, q1 = q0 + p1 T / M (free flight
+    over T = nsteps dt), bath coordinates from their ground-state Wigner widths;
+    each point is a centre plus sqrt(eps) times a standard normal vector.
+    """
+    rng = np.random.default_rng(seed)
+    d, eps, M = c["d"], c["eps"], c["mass"]
+    T = c["nsteps"] * c["dt"]
+    X = np.zeros((n, 2 * d))
+    if c["p_dist"] == "normal":
+        p1 = rng.normal(c["p_a"], c["p_b"], n)
+    else:
+        p1 = rng.uniform(c["p_a"], c["p_b"], n)
+    X[:, 0] = rng.normal(c["q_mean"], c["q_std"], n) + p1 * T / M
+    X[:, d] = p1
+    w = np.asarray(c["bath_omega"])
+    if d > 1:
+        X[:, 1:d] = rng.normal(size=(n, d - 1)) * np.sqrt(eps / (2 * M * w))
+        X[:, d + 1:] = rng.normal(size=(n, d - 1)) * np.sqrt(eps * M * w / 2)
+    return np.ascontiguousarray(X + np.sqrt(eps) * rng.normal(size=X.shape))
+
+
 def synthetic_ensemble(n, m, seed, q_range=(5.0, 25.0), p_range=(10.0, 30.0), z_scale=0.5,
                        p_scale=1.0, s_scale=3.0, logw_scale=1.0, n_comp=4, a0=1.0):
     """A random beam state shaped like an evolved QCLE ensemble (host arrays).

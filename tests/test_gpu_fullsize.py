@@ -79,3 +79,39 @@ def test_full_size_field_on_grid(gpu):
     sums = gpu.populations(gpu_model(c), st).cpu().numpy()
     pref = observables.populations(e, c["eps"])
     assert np.abs(sums[:, :2] - pref[:, :2]).max() <= 1e-12 * np.abs(observables.beam_integrals(e, c["eps"])).sum()
+
+
+def test_full_size_d12_sampled_beams(gpu):
+    """The m = 24 workload at full size (2^18 beams x 2000 intervals); 24 beams by the oracle."""
+    c = workloads.config("qcle12d_2p18")
+    st, diag = run_gpu(gpu, c)
+    ids = sample_ids(c["n_beams"], 24, seed=9)
+    g_all = gpu.unpack(st)
+    g = {key: v[ids] for key, v in g_all.items()}
+    e = oracle_init_ids(c, ids)
+    oshgb.advance(oracle_model(c), e, c["nsteps"], c["dt"], c["seed"])
+    errs, ties = compare_states(g, e, min_ok=0.9, label="qcle12d")
+    d = diag.cpu().numpy()
+    assert d[3] == 0 and d[4] == 0 and d[0] > c["n_beams"]
+    sums = gpu.populations(gpu_model(c), st).cpu().numpy()
+    mean, se = gpu.population_mean_se(sums, c["n_beams"])
+    assert abs(mean[0].real + mean[1].real - 1.0) < 4 * np.hypot(se[0].real, se[1].real)
+    assert abs(mean[1].imag) < 4 * se[1].imag + 1e-12
+    print("qcle12d errors", errs, "ties", ties, "hops", int(d[0]))
+
+
+def test_full_size_d12_field(gpu):
+    """Field of a 2^18-beam m = 24 ensemble at 16384 points (matrix-core path); 8 points by the oracle."""
+    c = workloads.config("qcle12d_2p18")
+    n, Q = c["n_beams"], c["n_points"]
+    a = workloads.synthetic_ensemble(n, 24, seed=21, q_range=(4.0, 6.0), p_range=(18.0, 22.0),
+                                     a0=(2 * np.pi * c["eps"]) ** -12)
+    pts = workloads.points_near(a["X"], 0.5 * c["eps"], Q, seed=4)
+    st = gpu.pack(a)
+    out = gpu.reconstruct(gpu_model(c), st, torch.from_numpy(pts).cuda()).cpu().numpy()
+    e = ensemble_from_arrays(a)
+    qs = np.array([0, 1, 777, 5000, 9999, 12345, Q - 2, Q - 1])
+    ref = observables.reconstruct(e, c["eps"], pts[qs], chunk=8192)
+    scale = observables.reconstruct_abs(e, c["eps"], pts[qs], chunk=8192)
+    assert (np.abs(out[:, qs] - ref) <= 1e-10 * scale + 1e-300).all()
+    assert np.abs(ref).max() > 0
