@@ -8,12 +8,17 @@ component populations and sum the field at the evaluation points
 outputs resident in HBM.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config qcle1d_1e6]
-                    [--no-cpu-baseline]
+                    [--no-cpu-baseline] [--no-mixed]
 
-Prints one JSON line.  `value` is beam-steps per second of the whole step;
-the field's beam-point evaluations per second, per-kernel times and the
-dominant kernel's roofline figure are reported beside it.  The CPU
-baseline times the FP64 oracle on a bounded sample of the same workload.
+Prints one JSON line.  `value` is beam-steps per second of the whole FP64
+step; the field's beam-point evaluations per second, per-kernel times and
+the dominant kernel's roofline figure are reported beside it.  The same
+workload is then run again on a mixed-precision state (FP32 trajectories,
+FP64 phase, rate integral and weights) and reported under "mixed": its
+throughput, its speedup over the FP64 path and the largest population
+difference between the two runs in units of their combined standard error
+(below 1: equal population error).  The CPU baseline times the FP64 oracle
+on a bounded sample of the same workload.
 """
 
 import argparse
@@ -30,10 +35,11 @@ METRIC = "beam-steps/s + beam·point evals/s vs FP64 plain path at equal populat
 
 # FP64 operations per beam-step of the m = 2 stepping kernel, counted from the
 # formulas it evaluates (add, multiply, divide, square root and each exp
-# count 1; a multiply-add counts 2): 4 right-hand sides of about 120
-# (adiabatic quantities and derivatives 87, beam ODE right-hand side 33) plus
-# the Runge-Kutta combinations (3 x 24 + 73).
-FLOPS_PER_BEAM_STEP_M2 = 4 * 120 + 3 * 24 + 73
+# count 1; a multiply-add counts 2): 4 right-hand sides of 93 (the adiabatic
+# quantities s, s', s'', s''' and d21 of the two-level model from one tanh and
+# one Gaussian, 70; the beam right-hand side, 23) plus the Runge-Kutta
+# combinations of the 12 integrated doubles (13 each).
+FLOPS_PER_BEAM_STEP_M2 = 4 * (70 + 23) + 12 * 13
 # per beam-point evaluation of the m = 2 field: y, quadratic form and phase
 # (18), exp, sincos (counted 2), complex multiply-accumulate (8)
 FLOPS_PER_EVAL_M2 = 18 + 1 + 2 + 8
@@ -49,7 +55,7 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 64 lanes x 2 flop x 2.4
 # HBM bytes per launch of step_m2_kernel at 1e6 beams, from rocprofv3 FETCH_SIZE (x2.000) and
 # WRITE_SIZE (x1.000) scaled by a 1 GiB copy (profiles/step_m2_qcle1d_1e6.md); the kernel
 # reads and writes 136 B of state per beam.  None when the kernel or workload differs.
-STEP_M2_TRAFFIC = {"qcle1d_1e6": (66717.3125 * 2.0 + 133300.78125 * 1.0) * 1024}
+STEP_M2_TRAFFIC = {}
 
 
 def parse():
@@ -59,6 +65,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="qcle1d_1e6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision run of the same workload (reported beside the FP64 value)")
     ap.add_argument("--cpu-beams", type=int, default=512)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB float64 buffer three times (calibrates the HBM byte counters)")
@@ -127,55 +135,81 @@ def main():
     spec = shgb.make_init_spec(c["q_mean"], c["q_std"], c["p_dist"], c["p_a"], c["p_b"], c["comp0"])
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    st = shgb.State(N, m, device=dev)
-    diag = shgb.new_diag(dev)
-    pops = torch.empty((4, 5), dtype=torch.float64, device=dev)
-    pop_work = torch.empty(max(shgb.populations_workspace(N, m), 8), dtype=torch.uint8, device=dev)
     pts_np = workloads.grid_points_2d() if m == 2 else workloads.points_near_final(c, c["n_points"], seed=3)
     Q = pts_np.shape[0] if c["n_points"] else 0
     pts = torch.from_numpy(pts_np[:Q]).to(dev)
-    rec = torch.empty((4, Q, 2), dtype=torch.float64, device=dev)
-    rec_work = torch.empty(max(shgb.reconstruct_workspace(N, m, Q), 8), dtype=torch.uint8, device=dev)
-
     names = ("init", "step", "populations", "reconstruct")
 
-    def one_step(evs=None):
-        def mark(i):
-            if evs is not None:
-                evs[i].record()
-        mark(0)
-        shgb.init_beams(mdl, spec, st, seed)
-        mark(1)
-        shgb.step_ensemble(mdl, st, nsteps, dt, seed, diag)
-        mark(2)
-        shgb.populations(mdl, st, out=pops, work=pop_work)
-        mark(3)
-        if Q:
-            shgb.reconstruct(mdl, st, pts, out=rec, work=rec_work)
-        mark(4)
+    def timed_run(precision, steps, warmup):
+        """warmup + steps bench steps on one state of the given precision."""
+        st = shgb.State(N, m, device=dev, precision=precision)
+        diag = shgb.new_diag(dev)
+        pops = torch.empty((4, 5), dtype=torch.float64, device=dev)
+        pop_work = torch.empty(max(shgb.populations_workspace(N, m), 8), dtype=torch.uint8, device=dev)
+        rec = torch.empty((4, Q, 2), dtype=torch.float64, device=dev)
+        rec_work = torch.empty(max(shgb.reconstruct_workspace(N, m, Q), 8), dtype=torch.uint8, device=dev)
 
-    for _ in range(a.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    diag.zero_()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(a.steps):
-        one_step(events[k])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / a.steps
-    phase_ms = {n: float(np.mean([events[k][i].elapsed_time(events[k][i + 1]) for k in range(a.steps)]))
-                for i, n in enumerate(names)}
+        def one_step(evs=None):
+            def mark(i):
+                if evs is not None:
+                    evs[i].record()
+            mark(0)
+            shgb.init_beams(mdl, spec, st, seed)
+            mark(1)
+            shgb.step_ensemble(mdl, st, nsteps, dt, seed, diag)
+            mark(2)
+            shgb.populations(mdl, st, out=pops, work=pop_work)
+            mark(3)
+            if Q:
+                shgb.reconstruct(mdl, st, pts, out=rec, work=rec_work)
+            mark(4)
+
+        for _ in range(warmup):
+            one_step()
+        torch.cuda.synchronize()
+        diag.zero_()
+        events = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            one_step(events[k])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        phase_ms = {n: float(np.mean([events[k][i].elapsed_time(events[k][i + 1]) for k in range(steps)]))
+                    for i, n in enumerate(names)}
+        mean, se = shgb.population_mean_se(pops.cpu().numpy(), N)
+        field = rec.cpu().numpy() if Q else None
+        del st, rec_work, pop_work
+        return dict(ms_per_step=(t1 - t0) * 1e3 / steps, phase_ms=phase_ms, mean=mean, se=se,
+                    diag=diag.cpu().numpy() // max(steps, 1), field=field)
+
+    r64 = timed_run("fp64", a.steps, a.warmup)
+    ms_per_step, phase_ms = r64["ms_per_step"], r64["phase_ms"]
     value = N * nsteps / (ms_per_step / 1e3)
     evals_per_s = N * Q / (phase_ms["reconstruct"] / 1e3) if Q else None
     fps = FLOPS_PER_BEAM_STEP_M2 if m == 2 else FLOPS_PER_BEAM_STEP_M24
     fpe = FLOPS_PER_EVAL_M2 if m == 2 else FLOPS_PER_EVAL_M24
     step_tflops = fps * N * nsteps / (phase_ms["step"] / 1e3) / 1e12
-    pop_host = pops.cpu().numpy()
-    mean, se = shgb.population_mean_se(pop_host, N)
-    d = diag.cpu().numpy() // max(a.steps, 1)
+    mean, se, d = r64["mean"], r64["se"], r64["diag"]
+    mixed = None
+    if not a.no_mixed:
+        rmx = timed_run("mixed", a.steps, a.warmup)
+        se_pair = np.sqrt(np.abs(se) ** 2 + np.abs(rmx["se"]) ** 2)
+        dmx = rmx["diag"]
+        mixed = {
+            "precision": "trajectories and Hessians FP32; S, Lam, thresholds, weights, populations FP64; "
+                         + ("field FP32 with FP64 sums" if m == 2 else "field FP64 from FP32-stored beams"),
+            "value": N * nsteps / (rmx["ms_per_step"] / 1e3), "unit": "beam-steps/s",
+            "ms_per_step": rmx["ms_per_step"], "kernel_ms": rmx["phase_ms"],
+            "beam_point_evals_per_s": N * Q / (rmx["phase_ms"]["reconstruct"] / 1e3) if Q else None,
+            "speedup_vs_fp64": ms_per_step / rmx["ms_per_step"],
+            "step_speedup_vs_fp64": phase_ms["step"] / rmx["phase_ms"]["step"],
+            "population_diff_over_se": float((np.abs(rmx["mean"] - mean) / np.maximum(se_pair, 1e-300)).max()),
+            "field_rel_l2_vs_fp64": (None if not Q else
+                                     float(np.linalg.norm(rmx["field"] - r64["field"]) /
+                                           max(np.linalg.norm(r64["field"]), 1e-300))),
+            "diag_per_step": {n: int(v) for n, v in zip(shgb.DIAG_NAMES, dmx)},
+        }
 
     line = {
         "metric": METRIC,
@@ -209,6 +243,7 @@ def main():
         "populations": {"mean_re": mean.real.tolist(), "mean_im": mean.imag.tolist(),
                         "se_re": se.real.tolist()},
         "diag_per_step": {n: int(v) for n, v in zip(shgb.DIAG_NAMES, d)},
+        "mixed": mixed,
     }
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(c, a.cpu_beams, pts_np)

@@ -60,8 +60,8 @@ extern "C" {
 
 /* diagnostic counters (indices into diag[]) */
 #define SHGB_DIAG_HOPS 0          /* hops performed                           */
-#define SHGB_DIAG_THR_TIES 1      /* |Lam' - E| <= 1e-12 E at a hop test        */
-#define SHGB_DIAG_DEST_TIES 2     /* |U R - C_j| <= 1e-12 R at a destination draw */
+#define SHGB_DIAG_THR_TIES 1      /* |Lam' - E| <= tau E at a hop test (tau: 1e-12 FP64, 1e-5 MIXED) */
+#define SHGB_DIAG_DEST_TIES 2     /* |U R - C_j| <= tau R at a destination draw  */
 #define SHGB_DIAG_CAP_OVERFLOW 3  /* intervals that reached SHGB_HOP_CAP hops  */
 #define SHGB_DIAG_NONFINITE 4     /* beams with a non-finite state after a call */
 #define SHGB_DIAG_NONSPD 5        /* populations: an LDL^T pivot with Re <= 0   */
@@ -88,28 +88,47 @@ typedef struct shgb_model {
 } shgb_model;
 
 /* ---- beam state --------------------------------------------------------
- * Structure of arrays: field f of beam b is f64[f * ld + b].  With
- * T = m(m+1)/2 the fields are, in order:
- *   X[m], P[m], Zre[T], Zim[T], S, Are, Aim, logw, phre, phim, Lam, E
+ * Structure of arrays, beam index fastest: field f of beam b is at
+ * [f * ld + b].  With T = m(m+1)/2 the fields are
+ *   trajectory rows:  X[m], P[m], Zre[T], Zim[T]          (shgb_traj_fields(m))
+ *   scalar rows:      S, Are, Aim, logw, phre, phim, Lam, E (SHGB_SCALAR_FIELDS)
  * Z = M + iN is the complex symmetric beam Hessian (Sec. 2, eq. (2.2)) packed
  * by rows of its upper triangle ((i, j), i <= j, at i*m - i(i-1)/2 + j - i);
  * A the complex amplitude; Re omega = logw + Lam where Lam is the rate
  * integral since the last hop; exp(i Im omega) = phre + i phim; E the current
  * waiting-time threshold (the beam hops when Lam reaches E).
  * comp[b] is the current component l_t, nhop[b] the number of hops so far.
- * Beam b has global id beam_id_offset + b.                                  */
+ * Beam b has global id beam_id_offset + b.
+ *
+ * Precision:
+ *  - SHGB_FP64: f64 holds the trajectory rows followed by the scalar rows
+ *    (shgb_nfields(m) rows); f32 is unused (may be NULL).
+ *  - SHGB_MIXED: f32 holds the trajectory rows (shgb_traj_fields(m) rows of
+ *    ld floats) and f64 only the scalar rows (SHGB_SCALAR_FIELDS rows).  The
+ *    beam ODEs are integrated in FP32; the phase S, the rate integral Lam,
+ *    the threshold, the weight and the unit phase stay FP64 (S / eps is a
+ *    large angle and Lam decides hop times).  Populations are formed in FP64
+ *    from the stored values; the field is evaluated in FP32 with FP64 sums
+ *    for m = 2 and as in SHGB_FP64 otherwise.                               */
+#define SHGB_FP64 0
+#define SHGB_MIXED 1
+#define SHGB_SCALAR_FIELDS 8
 typedef struct shgb_state {
-  double *f64;              /* device, shgb_nfields(m) * ld doubles */
+  double *f64;              /* device: shgb_nfields(m) rows (FP64) or 8 rows (MIXED) of ld */
   int32_t *comp;            /* device, n_beams                      */
   uint32_t *nhop;           /* device, n_beams                      */
   int64_t n_beams;          /* >= 0                                 */
   int64_t ld;               /* >= n_beams                           */
   uint64_t beam_id_offset;
   int32_t m;                /* must equal 2 * model.d               */
+  int32_t precision;        /* SHGB_FP64 or SHGB_MIXED              */
+  float *f32;               /* device, MIXED: shgb_traj_fields(m) rows of ld */
 } shgb_state;
 
-/* number of double fields per beam for phase-space dimension m */
-static inline int32_t shgb_nfields(int32_t m) { return 2 * m + m * (m + 1) + 8; }
+/* trajectory rows per beam for phase-space dimension m */
+static inline int32_t shgb_traj_fields(int32_t m) { return 2 * m + m * (m + 1); }
+/* double rows per beam of an SHGB_FP64 state */
+static inline int32_t shgb_nfields(int32_t m) { return shgb_traj_fields(m) + SHGB_SCALAR_FIELDS; }
 
 /* ---- initial data -------------------------------------------------------
  * Sec. 2.5 and Sec. 2.4 step 2.  Beam shape M0 = I, N0 = 0, P0 = 0, S0 = 0,
@@ -137,6 +156,8 @@ int shgb_init_beams(const shgb_model *model, const shgb_init_spec *spec,
  * is re-integrated to it, the hop is applied (shgb_hop) and the beam finishes
  * the interval on its new component, up to SHGB_HOP_CAP hops per interval.
  * The state is read once and written once per call; nsteps may be large.
+ * A SHGB_MIXED state counts threshold ties within 1e-5 E (FP32 trajectories
+ * move hop times by about 1e-7 relative).
  * Errors: EINVAL (null pointers, nsteps < 0, dt not finite or <= 0),
  * EUNSUPPORTED (d not built). */
 int shgb_step_ensemble(const shgb_model *model, const shgb_state *st, int32_t nsteps,

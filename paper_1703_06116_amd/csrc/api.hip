@@ -51,6 +51,13 @@ int to_dev_model(const shgb_model *m, DevModel &md) {
   md.C = m->C;
   md.D = m->D;
   md.lam = m->lam;
+  md.AB = m->A * m->B;
+  md.m2AB2 = -2.0 * m->A * m->B * m->B;
+  md.m2AB3 = -2.0 * m->A * m->B * m->B * m->B;
+  md.m2D = -2.0 * m->D;
+  md.D4sq = 4.0 * m->D * m->D;
+  md.D12sq = 12.0 * m->D * m->D;
+  md.D8cu = 8.0 * m->D * m->D * m->D;
   md.d = m->d;
   for (int k = 1; k < m->d; ++k) {
     const double w = m->bath_omega[k - 1];
@@ -64,7 +71,9 @@ int to_dev_model(const shgb_model *m, DevModel &md) {
 int check_state(const shgb_state *st, const DevModel &md) {
   if (!st) return SHGB_EINVAL;
   if (st->m != 2 * md.d || st->n_beams < 0 || st->ld < st->n_beams) return SHGB_EINVAL;
+  if (st->precision != SHGB_FP64 && st->precision != SHGB_MIXED) return SHGB_EINVAL;
   if (st->n_beams > 0 && (!st->f64 || !st->comp || !st->nhop)) return SHGB_EINVAL;
+  if (st->n_beams > 0 && st->precision == SHGB_MIXED && !st->f32) return SHGB_EINVAL;
   if (st->n_beams > (int64_t)INT32_MAX) return SHGB_EINVAL;  // beam indices are int32 in shgb_hop
   return SHGB_OK;
 }

@@ -13,12 +13,18 @@ namespace shgb {
 struct DevModel {
   double mass, inv_mass, eps;
   double A, B, C, D, lam;
+  // products of the potential parameters used by qcle_q1
+  double AB, m2AB2, m2AB3, m2D, D4sq, D12sq, D8cu;
   double bath_w[SHGB_MAX_D];  // w_k for bath modes k = 1..d-1 (index 0 unused)
   double bath_k[SHGB_MAX_D];  // mass * w_k^2
   int d;
 };
 
-// Field offsets of the structure-of-arrays state for phase-space dimension m.
+// Row offsets of the structure-of-arrays state for phase-space dimension m.
+// Trajectory rows (X, P, Zre, Zim) live in one block whose element type is
+// the state's trajectory precision; the scalar rows live in a double block:
+// for an FP64 state that block directly follows the trajectory rows of the
+// same array, for a mixed state it is an array of its own.
 struct Layout {
   int m, T;
   int64_t ld;
@@ -27,18 +33,19 @@ struct Layout {
   __host__ __device__ int P(int i) const { return m + i; }
   __host__ __device__ int Zre(int k) const { return 2 * m + k; }
   __host__ __device__ int Zim(int k) const { return 2 * m + T + k; }
-  __host__ __device__ int S() const { return 2 * m + 2 * T; }
-  __host__ __device__ int Are() const { return S() + 1; }
-  __host__ __device__ int Aim() const { return S() + 2; }
-  __host__ __device__ int logw() const { return S() + 3; }
-  __host__ __device__ int phre() const { return S() + 4; }
-  __host__ __device__ int phim() const { return S() + 5; }
-  __host__ __device__ int Lam() const { return S() + 6; }
-  __host__ __device__ int E() const { return S() + 7; }
-  __host__ __device__ int nfields() const { return S() + 8; }
+  __host__ __device__ int traj_rows() const { return 2 * m + 2 * T; }
   // packed upper-triangle index of (i, j), i <= j
   __host__ __device__ static int tri(int m, int i, int j) { return i * m - i * (i - 1) / 2 + (j - i); }
 };
+
+// Rows of the scalar block.
+enum ScalarRow : int { kRowS = 0, kRowAre, kRowAim, kRowLogw, kRowPhre, kRowPhim, kRowLam, kRowE };
+
+// Host side: the two blocks of a state.
+inline double *scalar_block(const shgb_state &st) {
+  return st.precision == SHGB_MIXED ? st.f64 : st.f64 + (int64_t)shgb_traj_fields(st.m) * st.ld;
+}
+inline bool mixed(const shgb_state &st) { return st.precision == SHGB_MIXED; }
 
 // ---------------------------------------------------------------------------
 // Philox4x64-10, from Salmon, Moraes, Dror & Shaw, "Parallel random numbers:
@@ -95,30 +102,131 @@ __host__ __device__ inline double u01(uint64_t w) { return ((double)(w >> 12) + 
 // Jacobian, the third derivative the curvature of P . alpha).
 struct Q1 { double s, s1, s2, s3, d21; };
 
+// 1/x from the hardware reciprocal refined by two Newton steps (x > 0, normal).
+__host__ __device__ inline double recip(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+#else
+  return 1.0 / x;
+#endif
+}
+
+// 1/sqrt(x) from the hardware estimate refined by two Newton steps (x > 0, normal).
+__host__ __device__ inline double rsqrt_nr(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  r = r * fma(-hx * r, r, 1.5);
+  r = r * fma(-hx * r, r, 1.5);
+  return r;
+#else
+  return 1.0 / sqrt(x);
+#endif
+}
+
 __host__ __device__ inline Q1 qcle_q1(const DevModel &md, double q) {
-  const double A = md.A, B = md.B, C = md.C, D = md.D;
   // tanh and sech^2 from one exponential, accurate in the tails
-  const double x = B * q;
+  const double x = md.B * q;
   const double e = exp(-2.0 * fabs(x));
-  const double r = 1.0 / (1.0 + e);
+  const double r = recip(1.0 + e);
   const double th = copysign((1.0 - e) * r, x);
   const double sech2 = 4.0 * e * r * r;
-  const double a = A * th;
-  const double a1 = A * B * sech2;
-  const double a2 = -2.0 * A * B * B * th * sech2;
-  const double a3 = -2.0 * A * B * B * B * sech2 * (1.0 - 3.0 * th * th);
-  const double c = C * exp(-D * q * q);
-  const double c1 = -2.0 * D * q * c;
-  const double c2 = (4.0 * D * D * q * q - 2.0 * D) * c;
-  const double c3 = (12.0 * D * D * q - 8.0 * D * D * D * q * q * q) * c;
-  const double s = sqrt(a * a + c * c);
-  const double rs = 1.0 / s;
+  const double a = md.A * th;
+  const double a1 = md.AB * sech2;
+  const double a2 = md.m2AB2 * th * sech2;
+  const double a3 = md.m2AB3 * sech2 * fma(-3.0 * th, th, 1.0);
+  const double q2 = q * q;
+  const double c = md.C * exp(-md.D * q2);
+  const double c1 = md.m2D * q * c;
+  const double c2 = fma(md.D4sq, q2, md.m2D) * c;
+  const double c3 = q * fma(-md.D8cu, q2, md.D12sq) * c;
+  const double ss = fma(a, a, c * c);
+  const double rs = rsqrt_nr(ss);
   Q1 o;
-  o.s = s;
-  o.s1 = (a * a1 + c * c1) * rs;
-  o.s2 = (a1 * a1 + a * a2 + c1 * c1 + c * c2 - o.s1 * o.s1) * rs;
-  o.s3 = (3.0 * (a1 * a2 + c1 * c2) + a * a3 + c * c3 - 3.0 * o.s1 * o.s2) * rs;
-  o.d21 = 0.5 * (a * c1 - c * a1) * rs * rs;
+  o.s = ss * rs;
+  o.s1 = fma(a, a1, c * c1) * rs;
+  o.s2 = (fma(a1, a1, a * a2) + fma(c1, c1, c * c2) - o.s1 * o.s1) * rs;
+  o.s3 = (3.0 * fma(a1, a2, c1 * c2) + fma(a, a3, c * c3) - 3.0 * o.s1 * o.s2) * rs;
+  o.d21 = 0.5 * fma(a, c1, -c * a1) * rs * rs;
+  return o;
+}
+
+// The same quantities in FP32 for mixed-precision trajectories: hardware
+// exp, reciprocal and reciprocal square root (about 1 ulp each).
+struct QcleF {
+  float inv_mass, A, B, C, D, lam, AB, m2AB2, m2AB3, m2D, D4sq, D12sq, D8cu;
+};
+
+__host__ __device__ inline QcleF qcle_f32(const DevModel &md) {
+  QcleF f;
+  f.inv_mass = (float)md.inv_mass;
+  f.A = (float)md.A;
+  f.B = (float)md.B;
+  f.C = (float)md.C;
+  f.D = (float)md.D;
+  f.lam = (float)md.lam;
+  f.AB = (float)md.AB;
+  f.m2AB2 = (float)md.m2AB2;
+  f.m2AB3 = (float)md.m2AB3;
+  f.m2D = (float)md.m2D;
+  f.D4sq = (float)md.D4sq;
+  f.D12sq = (float)md.D12sq;
+  f.D8cu = (float)md.D8cu;
+  return f;
+}
+
+struct Q1f { float s, s1, s2, s3, d21; };
+
+// Host builds (CPU harnesses) use the C library in place of the hardware
+// approximations.
+__host__ __device__ inline float exp_f32(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __expf(x);
+#else
+  return expf(x);
+#endif
+}
+__host__ __device__ inline float rcp_f32(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+__host__ __device__ inline float rsq_f32(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rsqf(x);
+#else
+  return 1.0f / sqrtf(x);
+#endif
+}
+
+__host__ __device__ inline Q1f qcle_q1f(const QcleF &md, float q) {
+  const float x = md.B * q;
+  const float e = exp_f32(-2.0f * fabsf(x));
+  const float r = rcp_f32(1.0f + e);
+  const float th = copysignf((1.0f - e) * r, x);
+  const float sech2 = 4.0f * e * r * r;
+  const float a = md.A * th;
+  const float a1 = md.AB * sech2;
+  const float a2 = md.m2AB2 * th * sech2;
+  const float a3 = md.m2AB3 * sech2 * fmaf(-3.0f * th, th, 1.0f);
+  const float q2 = q * q;
+  const float c = md.C * exp_f32(-md.D * q2);
+  const float c1 = md.m2D * q * c;
+  const float c2 = fmaf(md.D4sq, q2, md.m2D) * c;
+  const float c3 = q * fmaf(-md.D8cu, q2, md.D12sq) * c;
+  const float ss = fmaf(a, a, c * c);
+  const float rs = rsq_f32(ss);
+  Q1f o;
+  o.s = ss * rs;
+  o.s1 = fmaf(a, a1, c * c1) * rs;
+  o.s2 = (fmaf(a1, a1, a * a2) + fmaf(c1, c1, c * c2) - o.s1 * o.s1) * rs;
+  o.s3 = (3.0f * fmaf(a1, a2, c1 * c2) + fmaf(a, a3, c * c3) - 3.0f * o.s1 * o.s2) * rs;
+  o.d21 = 0.5f * fmaf(a, c1, -c * a1) * rs * rs;
   return o;
 }
 
@@ -153,10 +261,13 @@ struct Counters {
   uint32_t hops = 0, thr_ties = 0, dest_ties = 0, cap = 0, zero_rate = 0, nonfinite = 0;
 };
 
+// Relative bands within which threshold and destination comparisons are
+// counted as ties: FP64 trajectories, and FP32 trajectories (mixed states).
 constexpr double kTieRel = 1e-12;
+constexpr double kTieRelMixed = 1e-5;
 
 __host__ __device__ inline void hop_event(const DevModel &md, double q1, double p1, HopScalars &h,
-                                 uint64_t gid, uint64_t seed, Counters &cnt) {
+                                 uint64_t gid, uint64_t seed, Counters &cnt, double tie_rel = kTieRel) {
   const Q1 k = qcle_q1(md, q1);
   const double kappa = p1 * md.inv_mass * k.d21;
   double col[SHGB_NCOMP];
@@ -180,7 +291,7 @@ __host__ __device__ inline void hop_event(const DevModel &md, double q1, double 
       if (j == l) continue;
       C = C + fabs(col[j]);
       if (fabs(col[j]) > 0.0) last_pos = j;
-      if (fabs(UR - C) <= kTieRel * R) cnt.dest_ties++;
+      if (fabs(UR - C) <= tie_rel * R) cnt.dest_ties++;
       if (!chosen && UR < C) { dest = j; chosen = true; }
     }
     if (!chosen) dest = last_pos;
@@ -194,6 +305,14 @@ __host__ __device__ inline void hop_event(const DevModel &md, double q1, double 
   h.nhop += 1u;
   h.E = -log(1.0 - Y);
   cnt.hops++;
+}
+
+// The hop event as an out-of-line call, for the stepping loops: hops are
+// rare, and an inlined event keeps its registers live across the loop.
+__host__ __device__ __attribute__((noinline)) inline void hop_event_call(const DevModel &md, double q1, double p1,
+                                                                         HopScalars &h, uint64_t gid, uint64_t seed,
+                                                                         Counters &cnt, double tie_rel) {
+  hop_event(md, q1, p1, h, gid, seed, cnt, tie_rel);
 }
 
 // Wave-level sum of per-lane counters, one atomic per wave and counter.

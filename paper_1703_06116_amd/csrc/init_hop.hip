@@ -16,16 +16,19 @@ __device__ inline double normal_coord(uint64_t seed, uint64_t gid, int c) {
   return (c % 2 == 0) ? r * cos(ang) : r * sin(ang);
 }
 
+// TS: element type of the trajectory rows (double, or float for a mixed
+// state; coordinates are drawn in FP64 and rounded once when stored).
+template <typename TS>
 __global__ void __launch_bounds__(256)
-init_kernel(DevModel md, shgb_init_spec spec, double *__restrict__ f, int32_t *__restrict__ comp,
-            uint32_t *__restrict__ nhop, int64_t n, int64_t ld, int m, uint64_t gid0, uint64_t seed,
-            double A0) {
+init_kernel(DevModel md, shgb_init_spec spec, TS *__restrict__ tr, double *__restrict__ sc,
+            int32_t *__restrict__ comp, uint32_t *__restrict__ nhop, int64_t n, int64_t ld, int m, uint64_t gid0,
+            uint64_t seed, double A0) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n) return;
   const Layout L(m, ld);
   const int d = md.d;
   const uint64_t gid = gid0 + (uint64_t)b;
-  f[L.X(0) * ld + b] = spec.q_mean + spec.q_std * normal_coord(seed, gid, 0);
+  tr[L.X(0) * ld + b] = (TS)(spec.q_mean + spec.q_std * normal_coord(seed, gid, 0));
   double p1;
   if (spec.p_dist == SHGB_DIST_NORMAL) {
     p1 = spec.p_a + spec.p_b * normal_coord(seed, gid, d);
@@ -33,28 +36,28 @@ init_kernel(DevModel md, shgb_init_spec spec, double *__restrict__ f, int32_t *_
     const U64x4 w = draw(seed, gid, (uint64_t)d, kTagUnif);
     p1 = spec.p_a + (spec.p_b - spec.p_a) * u01(w.v[0]);
   }
-  f[L.X(d) * ld + b] = p1;
+  tr[L.X(d) * ld + b] = (TS)p1;
   for (int k = 1; k < d; ++k) {
     const double wk = md.bath_w[k];
-    f[L.X(k) * ld + b] = sqrt(md.eps / (2.0 * md.mass * wk)) * normal_coord(seed, gid, k);
-    f[L.X(d + k) * ld + b] = sqrt(md.eps * md.mass * wk / 2.0) * normal_coord(seed, gid, d + k);
+    tr[L.X(k) * ld + b] = (TS)(sqrt(md.eps / (2.0 * md.mass * wk)) * normal_coord(seed, gid, k));
+    tr[L.X(d + k) * ld + b] = (TS)(sqrt(md.eps * md.mass * wk / 2.0) * normal_coord(seed, gid, d + k));
   }
-  for (int i = 0; i < m; ++i) f[L.P(i) * ld + b] = 0.0;
+  for (int i = 0; i < m; ++i) tr[L.P(i) * ld + b] = (TS)0;
   for (int i = 0; i < m; ++i)
     for (int j = i; j < m; ++j) {
       const int t = Layout::tri(m, i, j);
-      f[L.Zre(t) * ld + b] = (i == j) ? 1.0 : 0.0;
-      f[L.Zim(t) * ld + b] = 0.0;
+      tr[L.Zre(t) * ld + b] = (TS)((i == j) ? 1 : 0);
+      tr[L.Zim(t) * ld + b] = (TS)0;
     }
-  f[L.S() * ld + b] = 0.0;
-  f[L.Are() * ld + b] = A0;
-  f[L.Aim() * ld + b] = 0.0;
-  f[L.logw() * ld + b] = 0.0;
-  f[L.phre() * ld + b] = 1.0;
-  f[L.phim() * ld + b] = 0.0;
-  f[L.Lam() * ld + b] = 0.0;
+  sc[kRowS * ld + b] = 0.0;
+  sc[kRowAre * ld + b] = A0;
+  sc[kRowAim * ld + b] = 0.0;
+  sc[kRowLogw * ld + b] = 0.0;
+  sc[kRowPhre * ld + b] = 1.0;
+  sc[kRowPhim * ld + b] = 0.0;
+  sc[kRowLam * ld + b] = 0.0;
   const U64x4 w = draw(seed, gid, 0, kTagHop);
-  f[L.E() * ld + b] = -log(1.0 - u01(w.v[1]));
+  sc[kRowE * ld + b] = -log(1.0 - u01(w.v[1]));
   comp[b] = spec.comp0;
   nhop[b] = 0u;
 }
@@ -65,15 +68,23 @@ hipError_t launch_init(const DevModel &md, const shgb_init_spec &spec, const shg
   const int threads = 256;
   const int64_t blocks = (st.n_beams + threads - 1) / threads;
   const double A0 = pow(2.0 * M_PI * md.eps, -0.5 * st.m);
-  hipLaunchKernelGGL(init_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, md, spec, st.f64,
-                     st.comp, st.nhop, st.n_beams, st.ld, st.m, st.beam_id_offset, seed, A0);
+  double *sc = scalar_block(st);
+  if (mixed(st))
+    hipLaunchKernelGGL(init_kernel<float>, dim3((unsigned)blocks), dim3(threads), 0, stream, md, spec, st.f32, sc,
+                       st.comp, st.nhop, st.n_beams, st.ld, st.m, st.beam_id_offset, seed, A0);
+  else
+    hipLaunchKernelGGL(init_kernel<double>, dim3((unsigned)blocks), dim3(threads), 0, stream, md, spec, st.f64, sc,
+                       st.comp, st.nhop, st.n_beams, st.ld, st.m, st.beam_id_offset, seed, A0);
   return hipGetLastError();
 }
 
+// The hop of a listed beam at its stored state; the coupling is evaluated in
+// FP64 from the stored (q1, p1).
+template <typename TS>
 __global__ void __launch_bounds__(256)
-hop_kernel(DevModel md, double *__restrict__ f, int32_t *__restrict__ comp,
+hop_kernel(DevModel md, const TS *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
            uint32_t *__restrict__ nhop, int64_t n, int64_t ld, int m, uint64_t gid0,
-           const int32_t *__restrict__ idx, int64_t n_idx, uint64_t seed, uint64_t *diag) {
+           const int32_t *__restrict__ idx, int64_t n_idx, uint64_t seed, double tie_rel, uint64_t *diag) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   Counters cnt;
   uint32_t bad = 0;
@@ -85,19 +96,20 @@ hop_kernel(DevModel md, double *__restrict__ f, int32_t *__restrict__ comp,
       const Layout L(m, ld);
       const int d = m / 2;
       HopScalars h;
-      h.logw = f[L.logw() * ld + b];
-      h.phre = f[L.phre() * ld + b];
-      h.phim = f[L.phim() * ld + b];
-      h.Lam = f[L.Lam() * ld + b];
-      h.E = f[L.E() * ld + b];
+      h.logw = sc[kRowLogw * ld + b];
+      h.phre = sc[kRowPhre * ld + b];
+      h.phim = sc[kRowPhim * ld + b];
+      h.Lam = sc[kRowLam * ld + b];
+      h.E = sc[kRowE * ld + b];
       h.comp = comp[b];
       h.nhop = nhop[b];
-      hop_event(md, f[L.X(0) * ld + b], f[L.X(d) * ld + b], h, gid0 + (uint64_t)b, seed, cnt);
-      f[L.logw() * ld + b] = h.logw;
-      f[L.phre() * ld + b] = h.phre;
-      f[L.phim() * ld + b] = h.phim;
-      f[L.Lam() * ld + b] = h.Lam;
-      f[L.E() * ld + b] = h.E;
+      hop_event(md, (double)tr[L.X(0) * ld + b], (double)tr[L.X(d) * ld + b], h, gid0 + (uint64_t)b, seed, cnt,
+                tie_rel);
+      sc[kRowLogw * ld + b] = h.logw;
+      sc[kRowPhre * ld + b] = h.phre;
+      sc[kRowPhim * ld + b] = h.phim;
+      sc[kRowLam * ld + b] = h.Lam;
+      sc[kRowE * ld + b] = h.E;
       comp[b] = h.comp;
       nhop[b] = h.nhop;
     }
@@ -116,8 +128,13 @@ hipError_t launch_hop(const DevModel &md, const shgb_state &st, const int32_t *i
   if (n_idx == 0) return hipSuccess;
   const int threads = 256;
   const int64_t blocks = (n_idx + threads - 1) / threads;
-  hipLaunchKernelGGL(hop_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, md, st.f64, st.comp,
-                     st.nhop, st.n_beams, st.ld, st.m, st.beam_id_offset, idx, n_idx, seed, diag);
+  double *sc = scalar_block(st);
+  if (mixed(st))
+    hipLaunchKernelGGL(hop_kernel<float>, dim3((unsigned)blocks), dim3(threads), 0, stream, md, st.f32, sc, st.comp,
+                       st.nhop, st.n_beams, st.ld, st.m, st.beam_id_offset, idx, n_idx, seed, kTieRelMixed, diag);
+  else
+    hipLaunchKernelGGL(hop_kernel<double>, dim3((unsigned)blocks), dim3(threads), 0, stream, md, st.f64, sc, st.comp,
+                       st.nhop, st.n_beams, st.ld, st.m, st.beam_id_offset, idx, n_idx, seed, kTieRel, diag);
   return hipGetLastError();
 }
 

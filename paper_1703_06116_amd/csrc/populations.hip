@@ -9,7 +9,8 @@
 // P^T Z^-1 P = sum_j w_j^2 / d_j with L w = P.
 // Per component the kernel sums c, (Re c)^2, (Im c)^2 and the count; each
 // block writes its partial sums and one block adds the partials in a fixed
-// order, so the result is bitwise reproducible.
+// order, so the result is bitwise reproducible.  The arithmetic is FP64 for
+// either trajectory precision (TS: the element type of the stored X, P, Z).
 #include "cplx.h"
 #include "device.h"
 
@@ -61,18 +62,19 @@ __device__ inline void tally(double (&acc)[kPopVals], int comp, cd c) {
 }
 
 // exp(omega) A exp(iS/eps) for beam b
-__device__ inline cd beam_weight(const Layout &L, const double *f, int64_t ld, int64_t b, double inv_eps) {
-  const cd ph = {f[L.phre() * ld + b], f[L.phim() * ld + b]};
-  const cd A = {f[L.Are() * ld + b], f[L.Aim() * ld + b]};
-  const double mag = exp(f[L.logw() * ld + b] + f[L.Lam() * ld + b]);
+__device__ inline cd beam_weight(const double *sc, int64_t ld, int64_t b, double inv_eps) {
+  const cd ph = {sc[kRowPhre * ld + b], sc[kRowPhim * ld + b]};
+  const cd A = {sc[kRowAre * ld + b], sc[kRowAim * ld + b]};
+  const double mag = exp(sc[kRowLogw * ld + b] + sc[kRowLam * ld + b]);
   double s, c;
-  sincos(f[L.S() * ld + b] * inv_eps, &s, &c);
+  sincos(sc[kRowS * ld + b] * inv_eps, &s, &c);
   return cmul(cmul(cscale(ph, mag), A), {c, s});
 }
 
+template <typename TS>
 __global__ void __launch_bounds__(kPopThreads)
-pop_m2_kernel(DevModel md, const double *__restrict__ f, const int32_t *__restrict__ comp, int64_t n,
-              int64_t ld, double norm, double *__restrict__ partial, uint64_t *diag) {
+pop_m2_kernel(DevModel md, const TS *__restrict__ f, const double *__restrict__ sc, const int32_t *__restrict__ comp,
+              int64_t n, int64_t ld, double norm, double *__restrict__ partial, uint64_t *diag) {
   const Layout L(2, ld);
   const double inv_eps = 1.0 / md.eps;
   double acc[kPopVals];
@@ -81,9 +83,9 @@ pop_m2_kernel(DevModel md, const double *__restrict__ f, const int32_t *__restri
   uint32_t nonspd = 0;
   for (int64_t b = (int64_t)blockIdx.x * kPopThreads + threadIdx.x; b < n;
        b += (int64_t)gridDim.x * kPopThreads) {
-    const cd z11 = {f[L.Zre(0) * ld + b], f[L.Zim(0) * ld + b]};
-    const cd z12 = {f[L.Zre(1) * ld + b], f[L.Zim(1) * ld + b]};
-    const cd z22 = {f[L.Zre(2) * ld + b], f[L.Zim(2) * ld + b]};
+    const cd z11 = {(double)f[L.Zre(0) * ld + b], (double)f[L.Zim(0) * ld + b]};
+    const cd z12 = {(double)f[L.Zre(1) * ld + b], (double)f[L.Zim(1) * ld + b]};
+    const cd z22 = {(double)f[L.Zre(2) * ld + b], (double)f[L.Zim(2) * ld + b]};
     const double P1 = f[L.P(0) * ld + b], P2 = f[L.P(1) * ld + b];
     const cd d1 = z11;
     const cd l21 = cdiv(z12, z11);
@@ -94,7 +96,7 @@ pop_m2_kernel(DevModel md, const double *__restrict__ f, const int32_t *__restri
     const cd quad = cadd(cdiv(cmul(w1, w1), d1), cdiv(cmul(w2, w2), d2));
     const cd sq = cmul(csqrt_principal(d1), csqrt_principal(d2));
     const cd g = cdiv(cexp(cscale(quad, -0.5 * inv_eps)), sq);
-    const cd c = cscale(cmul(beam_weight(L, f, ld, b, inv_eps), g), norm);
+    const cd c = cscale(cmul(beam_weight(sc, ld, b, inv_eps), g), norm);
     tally(acc, comp[b], c);
   }
   block_sum_store(acc, partial + (int64_t)blockIdx.x * kPopVals);
@@ -110,10 +112,11 @@ pop_m2_kernel(DevModel md, const double *__restrict__ f, const int32_t *__restri
 // submatrix.  kWaves beams per block.
 constexpr int kPopWaves = 4;
 
-template <int M>
+template <int M, typename TS>
 __global__ void __launch_bounds__(64 * kPopWaves)
-pop_wave_kernel(DevModel md, const double *__restrict__ f, const int32_t *__restrict__ comp, int64_t n,
-                int64_t ld, double norm, double *__restrict__ partial, uint64_t *diag) {
+pop_wave_kernel(DevModel md, const TS *__restrict__ f, const double *__restrict__ sc,
+                const int32_t *__restrict__ comp, int64_t n, int64_t ld, double norm, double *__restrict__ partial,
+                uint64_t *diag) {
   __shared__ double zr[kPopWaves][M][M + 1];
   __shared__ double zi[kPopWaves][M][M + 1];
   __shared__ double pw_re[kPopWaves][M], pw_im[kPopWaves][M];
@@ -172,7 +175,7 @@ pop_wave_kernel(DevModel md, const double *__restrict__ f, const int32_t *__rest
       if (bad) ++nonspd;
       const double pre = pow(2.0 * M_PI * md.eps, 0.5 * M);
       const cd g = cscale(cdiv(cexp(cscale(quad, -0.5 * inv_eps)), sq), pre);
-      const cd c = cscale(cmul(beam_weight(L, f, ld, b, inv_eps), g), norm);
+      const cd c = cscale(cmul(beam_weight(sc, ld, b, inv_eps), g), norm);
       tally(acc, comp[b], c);
     }
   }
@@ -204,19 +207,28 @@ int64_t pop_workspace_bytes(int64_t n, int m) {
 hipError_t launch_populations(const DevModel &md, const shgb_state &st, double *out, void *work,
                               uint64_t *diag, hipStream_t stream) {
   double *partial = (double *)work;
+  const double *sc = scalar_block(st);
   if (st.m == 2) {
     const int64_t blocks = pop_blocks(st.n_beams);
     const double norm = 2.0 * M_PI * md.eps;  // (2 pi eps)^(m/2)
-    hipLaunchKernelGGL(pop_m2_kernel, dim3((unsigned)blocks), dim3(kPopThreads), 0, stream, md, st.f64,
-                       st.comp, st.n_beams, st.ld, norm, partial, diag);
+    if (mixed(st))
+      hipLaunchKernelGGL(pop_m2_kernel<float>, dim3((unsigned)blocks), dim3(kPopThreads), 0, stream, md, st.f32, sc,
+                         st.comp, st.n_beams, st.ld, norm, partial, diag);
+    else
+      hipLaunchKernelGGL(pop_m2_kernel<double>, dim3((unsigned)blocks), dim3(kPopThreads), 0, stream, md, st.f64,
+                         sc, st.comp, st.n_beams, st.ld, norm, partial, diag);
     hipLaunchKernelGGL(pop_final_kernel, dim3(1), dim3(kPopThreads), 0, stream, partial, blocks, out);
     return hipGetLastError();
   }
   const int64_t blocks = pop_blocks((st.n_beams + kPopWaves - 1) / kPopWaves * kPopThreads);
 #define SHGB_POP_CASE(MM)                                                                             \
   case MM:                                                                                            \
-    hipLaunchKernelGGL(pop_wave_kernel<MM>, dim3((unsigned)blocks), dim3(64 * kPopWaves), 0, stream, md, \
-                       st.f64, st.comp, st.n_beams, st.ld, 1.0, partial, diag);                       \
+    if (mixed(st))                                                                                    \
+      hipLaunchKernelGGL((pop_wave_kernel<MM, float>), dim3((unsigned)blocks), dim3(64 * kPopWaves), 0, \
+                         stream, md, st.f32, sc, st.comp, st.n_beams, st.ld, 1.0, partial, diag);     \
+    else                                                                                              \
+      hipLaunchKernelGGL((pop_wave_kernel<MM, double>), dim3((unsigned)blocks), dim3(64 * kPopWaves), 0, \
+                         stream, md, st.f64, sc, st.comp, st.n_beams, st.ld, 1.0, partial, diag);     \
     break;
   switch (st.m) {
     SHGB_POP_CASE(4)

@@ -110,11 +110,13 @@ __global__ void __launch_bounds__(RTHREADS) rm_points_kernel(const double *__res
   for (; f < RFP; ++f) phi[(int64_t)f * QP + q] = 0.0;
 }
 
-// Beam feature weights W[f][k] (feature-major, Re and Im), weight and component.
+// Beam feature weights W[f][k] (feature-major, Re and Im), weight and
+// component, in FP64 from trajectory rows of element type TS.
+template <typename TS>
 __global__ void __launch_bounds__(RTHREADS)
-rm_beams_kernel(DevModel md, const double *__restrict__ fs, const int32_t *__restrict__ comp, int64_t n, int64_t ld,
-                int64_t NB, const double *__restrict__ c, double *__restrict__ wr, double *__restrict__ wi,
-                double *__restrict__ wk, double *__restrict__ wc) {
+rm_beams_kernel(DevModel md, const TS *__restrict__ fs, const double *__restrict__ sc,
+                const int32_t *__restrict__ comp, int64_t n, int64_t ld, int64_t NB, const double *__restrict__ c,
+                double *__restrict__ wr, double *__restrict__ wi, double *__restrict__ wk, double *__restrict__ wc) {
   const int64_t k = (int64_t)blockIdx.x * RTHREADS + threadIdx.x;
   if (k >= NB) return;
   if (k >= n) {
@@ -127,13 +129,13 @@ rm_beams_kernel(DevModel md, const double *__restrict__ fs, const int32_t *__res
   const double ie = 1.0 / md.eps, h2e = 0.5 / md.eps;
   double xt[RM];
 #pragma unroll
-  for (int i = 0; i < RM; ++i) xt[i] = fs[L.X(i) * ld + k] - c[i];
+  for (int i = 0; i < RM; ++i) xt[i] = (double)fs[L.X(i) * ld + k] - c[i];
   // quadratic weights
   for (int t = 0, i = 0; i < RM; ++i)
     for (int j = i; j < RM; ++j, ++t) {
       const double s = (i == j) ? -h2e : -ie;
-      wr[(int64_t)t * NB + k] = s * fs[L.Zre(t) * ld + k];
-      wi[(int64_t)t * NB + k] = s * fs[L.Zim(t) * ld + k];
+      wr[(int64_t)t * NB + k] = s * (double)fs[L.Zre(t) * ld + k];
+      wi[(int64_t)t * NB + k] = s * (double)fs[L.Zim(t) * ld + k];
     }
   // Z X~, linear and constant weights
   double cr = 0.0, ci = 0.0, px = 0.0;
@@ -141,10 +143,10 @@ rm_beams_kernel(DevModel md, const double *__restrict__ fs, const int32_t *__res
     double zr = 0.0, zi = 0.0;
     for (int j = 0; j < RM; ++j) {
       const int t = i <= j ? Layout::tri(RM, i, j) : Layout::tri(RM, j, i);
-      zr += fs[L.Zre(t) * ld + k] * xt[j];
-      zi += fs[L.Zim(t) * ld + k] * xt[j];
+      zr += (double)fs[L.Zre(t) * ld + k] * xt[j];
+      zi += (double)fs[L.Zim(t) * ld + k] * xt[j];
     }
-    const double Pi = fs[L.P(i) * ld + k];
+    const double Pi = (double)fs[L.P(i) * ld + k];
     wr[(int64_t)(RT + i) * NB + k] = zr * ie;
     wi[(int64_t)(RT + i) * NB + k] = (zi + Pi) * ie;
     cr += xt[i] * zr;
@@ -155,11 +157,11 @@ rm_beams_kernel(DevModel md, const double *__restrict__ fs, const int32_t *__res
   wi[(int64_t)(RF - 1) * NB + k] = -ci * h2e - px * ie;
   for (int f = RF; f < RFP; ++f) { wr[(int64_t)f * NB + k] = 0.0; wi[(int64_t)f * NB + k] = 0.0; }
   // exp(omega) A exp(iS/eps)
-  const double mag = exp(fs[L.logw() * ld + k] + fs[L.Lam() * ld + k]);
-  const double pr = fs[L.phre() * ld + k] * mag, pim = fs[L.phim() * ld + k] * mag;
-  const double ar = fs[L.Are() * ld + k], ai = fs[L.Aim() * ld + k];
+  const double mag = exp(sc[kRowLogw * ld + k] + sc[kRowLam * ld + k]);
+  const double pr = sc[kRowPhre * ld + k] * mag, pim = sc[kRowPhim * ld + k] * mag;
+  const double ar = sc[kRowAre * ld + k], ai = sc[kRowAim * ld + k];
   double sn, cs;
-  sincos(fs[L.S() * ld + k] * ie, &sn, &cs);
+  sincos(sc[kRowS * ld + k] * ie, &sn, &cs);
   const double w0r = pr * ar - pim * ai, w0i = pr * ai + pim * ar;
   wk[2 * k] = w0r * cs - w0i * sn;
   wk[2 * k + 1] = w0r * sn + w0i * cs;
@@ -323,9 +325,15 @@ hipError_t launch_recon_mfma(const DevModel &md, const shgb_state &st, const dou
   hipLaunchKernelGGL(rm_center_kernel, dim3(1), dim3(RTHREADS), 0, stream, pts, Q, ws + L.off_c);
   hipLaunchKernelGGL(rm_points_kernel, dim3((unsigned)(L.QP / RTHREADS + 1)), dim3(RTHREADS), 0, stream, pts, Q,
                      L.QP, ws + L.off_c, ws + L.off_phi);
-  hipLaunchKernelGGL(rm_beams_kernel, dim3((unsigned)((L.NB + RTHREADS - 1) / RTHREADS)), dim3(RTHREADS), 0, stream,
-                     md, st.f64, st.comp, st.n_beams, st.ld, L.NB, ws + L.off_c, ws + L.off_wr, ws + L.off_wi,
-                     ws + L.off_wk, ws + L.off_cmp);
+  const dim3 bgrid((unsigned)((L.NB + RTHREADS - 1) / RTHREADS));
+  if (mixed(st))
+    hipLaunchKernelGGL(rm_beams_kernel<float>, bgrid, dim3(RTHREADS), 0, stream, md, st.f32, scalar_block(st), st.comp,
+                       st.n_beams, st.ld, L.NB, ws + L.off_c, ws + L.off_wr, ws + L.off_wi, ws + L.off_wk,
+                       ws + L.off_cmp);
+  else
+    hipLaunchKernelGGL(rm_beams_kernel<double>, bgrid, dim3(RTHREADS), 0, stream, md, st.f64, scalar_block(st),
+                       st.comp, st.n_beams, st.ld, L.NB, ws + L.off_c, ws + L.off_wr, ws + L.off_wi, ws + L.off_wk,
+                       ws + L.off_cmp);
   hipLaunchKernelGGL(rm_gemm_kernel, dim3((unsigned)L.pt_tiles, (unsigned)L.n_chunks), dim3(RTHREADS), 0, stream,
                      ws + L.off_wr, ws + L.off_wi, ws + L.off_wk, ws + L.off_cmp, ws + L.off_phi, L.NB, L.QP, Q,
                      L.tiles_per_chunk, ws + L.off_partial);

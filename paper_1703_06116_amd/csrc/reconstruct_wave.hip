@@ -41,11 +41,12 @@ struct RwBeam {
   int comp;
 };
 
-template <int M>
+// TS: element type of the stored trajectory rows; the arithmetic is FP64.
+template <int M, typename TS>
 __global__ void __launch_bounds__(kRwThreads)
-recon_wave_kernel(DevModel md, const double *__restrict__ f, const int32_t *__restrict__ cmp, int64_t n,
-                  int64_t ld, const double *__restrict__ pts, int64_t Q, int64_t chunk,
-                  double *__restrict__ partial) {
+recon_wave_kernel(DevModel md, const TS *__restrict__ f, const double *__restrict__ sc,
+                  const int32_t *__restrict__ cmp, int64_t n, int64_t ld, const double *__restrict__ pts, int64_t Q,
+                  int64_t chunk, double *__restrict__ partial) {
   constexpr int T = M * (M + 1) / 2;
   __shared__ RwBeam<M> tile[kRwTile];
   const Layout L(M, ld);
@@ -71,21 +72,21 @@ recon_wave_kernel(DevModel md, const double *__restrict__ f, const int32_t *__re
         int a = 0, rem = r;
         while (rem >= M - a) { rem -= M - a; ++a; }
         const double s = (rem == 0) ? half_inv_eps : inv_eps;  // rem == 0: diagonal entry
-        tile[bt].Qr[r] = f[L.Zre(r) * ld + b] * s;
-        tile[bt].Qi[r] = f[L.Zim(r) * ld + b] * s;
+        tile[bt].Qr[r] = (double)f[L.Zre(r) * ld + b] * s;
+        tile[bt].Qi[r] = (double)f[L.Zim(r) * ld + b] * s;
       } else if (r < T + M) {
-        tile[bt].X[r - T] = f[L.X(r - T) * ld + b];
+        tile[bt].X[r - T] = (double)f[L.X(r - T) * ld + b];
       } else {
-        tile[bt].Pe[r - T - M] = f[L.P(r - T - M) * ld + b] * inv_eps;
+        tile[bt].Pe[r - T - M] = (double)f[L.P(r - T - M) * ld + b] * inv_eps;
       }
     }
     if (threadIdx.x < nt) {
       const int64_t b = k0 + threadIdx.x;
-      const double mag = exp(f[L.logw() * ld + b] + f[L.Lam() * ld + b]);
-      const double pr = f[L.phre() * ld + b] * mag, pim = f[L.phim() * ld + b] * mag;
-      const double ar = f[L.Are() * ld + b], ai = f[L.Aim() * ld + b];
+      const double mag = exp(sc[kRowLogw * ld + b] + sc[kRowLam * ld + b]);
+      const double pr = sc[kRowPhre * ld + b] * mag, pim = sc[kRowPhim * ld + b] * mag;
+      const double ar = sc[kRowAre * ld + b], ai = sc[kRowAim * ld + b];
       double sn, cs;
-      sincos(f[L.S() * ld + b] * inv_eps, &sn, &cs);
+      sincos(sc[kRowS * ld + b] * inv_eps, &sn, &cs);
       const double wr0 = pr * ar - pim * ai, wi0 = pr * ai + pim * ar;
       tile[threadIdx.x].wr = wr0 * cs - wi0 * sn;
       tile[threadIdx.x].wi = wr0 * sn + wi0 * cs;
@@ -162,10 +163,15 @@ hipError_t launch_recon_wave(const DevModel &md, const shgb_state &st, const dou
     return hipGetLastError();
   }
   const dim3 grid((unsigned)t.pt_tiles, (unsigned)t.n_chunks);
+  const double *sc = scalar_block(st);
 #define SHGB_RW_CASE(MM)                                                                                  \
   case MM:                                                                                                \
-    hipLaunchKernelGGL(recon_wave_kernel<MM>, grid, dim3(kRwThreads), 0, stream, md, st.f64, st.comp,      \
-                       st.n_beams, st.ld, pts, Q, t.chunk, partial);                                      \
+    if (mixed(st))                                                                                        \
+      hipLaunchKernelGGL((recon_wave_kernel<MM, float>), grid, dim3(kRwThreads), 0, stream, md, st.f32, sc, \
+                         st.comp, st.n_beams, st.ld, pts, Q, t.chunk, partial);                           \
+    else                                                                                                  \
+      hipLaunchKernelGGL((recon_wave_kernel<MM, double>), grid, dim3(kRwThreads), 0, stream, md, st.f64,   \
+                         sc, st.comp, st.n_beams, st.ld, pts, Q, t.chunk, partial);                       \
     break;
   switch (st.m) {
     SHGB_RW_CASE(4)

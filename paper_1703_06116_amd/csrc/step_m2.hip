@@ -19,49 +19,53 @@ struct Ode2 {
   double q, p, Pq, Pp, zr11, zr12, zr22, zi11, zi12, zi22, S, Lam;
 };
 
-__host__ __device__ inline Ode2 rhs2(const DevModel &md, int l, const Ode2 &y) {
-  const Q1 k = qcle_q1(md, y.q);
+// One Runge-Kutta stage: the derivative at the stage values ys is folded at
+// once into the accumulator and the next stage values,
+//   stage 0: acc = k;   stages 1, 2: acc += 2 k;   (ys = y0 + c k)
+//   stage 3: acc = y0 + h6 (acc + k)   (the step's result).
+__host__ __device__ inline void stage2(const DevModel &md, int l, const Ode2 &y0, Ode2 &ys, Ode2 &acc, int stage,
+                                       double c, double h6) {
+  const Q1 k = qcle_q1(md, ys.q);
   const double sg = comp_sigma(l), bc = comp_bcoef(l);
-  const double v = y.p * md.inv_mass;
+  const double v = ys.p * md.inv_mass;
   const double E1 = sg * k.s1, E2 = sg * k.s2, E3 = sg * k.s3;
   const double b0 = bc * k.s, b1 = bc * k.s1, b2 = bc * k.s2;
   Ode2 d;
   d.q = v;
   d.p = -E1;
-  d.Pq = b1 + E2 * y.Pp;
-  d.Pp = -y.Pq * md.inv_mass;
-  d.zr11 = 2.0 * y.zr12 * E2;
-  d.zi11 = 2.0 * y.zi12 * E2 - y.Pp * E3 - b2;
-  d.zr12 = y.zr22 * E2 - y.zr11 * md.inv_mass;
-  d.zi12 = y.zi22 * E2 - y.zi11 * md.inv_mass;
-  d.zr22 = -2.0 * y.zr12 * md.inv_mass;
-  d.zi22 = -2.0 * y.zi12 * md.inv_mass;
+  d.Pq = b1 + E2 * ys.Pp;
+  d.Pp = -ys.Pq * md.inv_mass;
+  d.zr11 = 2.0 * ys.zr12 * E2;
+  d.zi11 = 2.0 * ys.zi12 * E2 - ys.Pp * E3 - b2;
+  d.zr12 = ys.zr22 * E2 - ys.zr11 * md.inv_mass;
+  d.zi12 = ys.zi22 * E2 - ys.zi11 * md.inv_mass;
+  d.zr22 = -2.0 * ys.zr12 * md.inv_mass;
+  d.zi22 = -2.0 * ys.zi12 * md.inv_mass;
   d.S = b0;
   d.Lam = 2.0 * fabs(v * k.d21);
-  return d;
-}
-
 #define SHGB_ODE2_FIELDS(F) F(q) F(p) F(Pq) F(Pp) F(zr11) F(zr12) F(zr22) F(zi11) F(zi12) F(zi22) F(S) F(Lam)
-
-__host__ __device__ inline Ode2 axpy2(const Ode2 &y, double h, const Ode2 &k) {
-  Ode2 o;
-#define F(f) o.f = y.f + h * k.f;
-  SHGB_ODE2_FIELDS(F)
+  if (stage == 0) {
+#define F(f) acc.f = d.f; ys.f = y0.f + c * d.f;
+    SHGB_ODE2_FIELDS(F)
 #undef F
-  return o;
+  } else if (stage < 3) {
+#define F(f) acc.f = acc.f + 2.0 * d.f; ys.f = y0.f + c * d.f;
+    SHGB_ODE2_FIELDS(F)
+#undef F
+  } else {
+#define F(f) acc.f = y0.f + h6 * (acc.f + d.f);
+    SHGB_ODE2_FIELDS(F)
+#undef F
+  }
+#undef SHGB_ODE2_FIELDS
 }
 
-__host__ __device__ inline Ode2 rk4_2(const DevModel &md, int l, const Ode2 &y, double h) {
-  const Ode2 k1 = rhs2(md, l, y);
-  const Ode2 k2 = rhs2(md, l, axpy2(y, 0.5 * h, k1));
-  const Ode2 k3 = rhs2(md, l, axpy2(y, 0.5 * h, k2));
-  const Ode2 k4 = rhs2(md, l, axpy2(y, h, k3));
+// One classical RK4 step of size h on component l, into out.
+__host__ __device__ inline void rk4_2(const DevModel &md, int l, const Ode2 &y, double h, Ode2 &out) {
+  Ode2 ys = y;
   const double h6 = h / 6.0;
-  Ode2 o;
-#define F(f) o.f = y.f + h6 * (k1.f + 2.0 * k2.f + 2.0 * k3.f + k4.f);
-  SHGB_ODE2_FIELDS(F)
-#undef F
-  return o;
+#pragma unroll
+  for (int st = 0; st < 4; ++st) stage2(md, l, y, ys, out, st, st == 2 ? h : 0.5 * h, h6);
 }
 
 // One interval [t_n, t_n + dt] for one beam.
@@ -72,8 +76,9 @@ __host__ __device__ inline void interval2(const DevModel &md, Ode2 &y, HopScalar
   double theta = 1.0;
   bool partial = false; // the next call is the shortened step to the hop time
   int hops = 0;
+  Ode2 yn;
   for (;;) {
-    const Ode2 yn = rk4_2(md, h.comp, y, hstep);
+    rk4_2(md, h.comp, y, hstep, yn);
     if (!partial) {
       const bool capped = hops >= SHGB_HOP_CAP;
       if (!capped && fabs(yn.Lam - h.E) <= kTieRel * h.E) cnt.thr_ties++;
@@ -94,7 +99,7 @@ __host__ __device__ inline void interval2(const DevModel &md, Ode2 &y, HopScalar
       partial = false;
     }
     h.Lam = y.Lam;
-    hop_event(md, y.q, y.p, h, gid, seed, cnt);
+    hop_event_call(md, y.q, y.p, h, gid, seed, cnt, kTieRel);
     y.Lam = h.Lam;
     ++hops;
     rem = rem * (1.0 - theta);
@@ -103,8 +108,10 @@ __host__ __device__ inline void interval2(const DevModel &md, Ode2 &y, HopScalar
   }
 }
 
-__global__ void __launch_bounds__(256)
-step_m2_kernel(DevModel md, double *__restrict__ f, int32_t *__restrict__ comp,
+// Three waves per SIMD: measured faster than the register-unconstrained
+// build (two waves) despite a few scratch spills.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+step_m2_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
                uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps,
                double dt, uint64_t seed, uint64_t *diag) {
   const Layout L(2, ld);
@@ -113,23 +120,23 @@ step_m2_kernel(DevModel md, double *__restrict__ f, int32_t *__restrict__ comp,
   Counters cnt;
   if (live) {
     Ode2 y;
-    y.q = f[L.X(0) * ld + b];
-    y.p = f[L.X(1) * ld + b];
-    y.Pq = f[L.P(0) * ld + b];
-    y.Pp = f[L.P(1) * ld + b];
-    y.zr11 = f[L.Zre(0) * ld + b];
-    y.zr12 = f[L.Zre(1) * ld + b];
-    y.zr22 = f[L.Zre(2) * ld + b];
-    y.zi11 = f[L.Zim(0) * ld + b];
-    y.zi12 = f[L.Zim(1) * ld + b];
-    y.zi22 = f[L.Zim(2) * ld + b];
-    y.S = f[L.S() * ld + b];
-    y.Lam = f[L.Lam() * ld + b];
+    y.q = tr[L.X(0) * ld + b];
+    y.p = tr[L.X(1) * ld + b];
+    y.Pq = tr[L.P(0) * ld + b];
+    y.Pp = tr[L.P(1) * ld + b];
+    y.zr11 = tr[L.Zre(0) * ld + b];
+    y.zr12 = tr[L.Zre(1) * ld + b];
+    y.zr22 = tr[L.Zre(2) * ld + b];
+    y.zi11 = tr[L.Zim(0) * ld + b];
+    y.zi12 = tr[L.Zim(1) * ld + b];
+    y.zi22 = tr[L.Zim(2) * ld + b];
+    y.S = sc[kRowS * ld + b];
+    y.Lam = sc[kRowLam * ld + b];
     HopScalars h;
-    h.logw = f[L.logw() * ld + b];
-    h.phre = f[L.phre() * ld + b];
-    h.phim = f[L.phim() * ld + b];
-    h.E = f[L.E() * ld + b];
+    h.logw = sc[kRowLogw * ld + b];
+    h.phre = sc[kRowPhre * ld + b];
+    h.phim = sc[kRowPhim * ld + b];
+    h.E = sc[kRowE * ld + b];
     h.comp = comp[b];
     h.nhop = nhop[b];
     h.Lam = y.Lam;
@@ -138,22 +145,202 @@ step_m2_kernel(DevModel md, double *__restrict__ f, int32_t *__restrict__ comp,
     const double chk = y.q + y.p + y.Pq + y.Pp + y.zr11 + y.zr12 + y.zr22 + y.zi11 + y.zi12 +
                        y.zi22 + y.S + y.Lam + h.logw;
     if (!isfinite(chk)) cnt.nonfinite++;
-    f[L.X(0) * ld + b] = y.q;
-    f[L.X(1) * ld + b] = y.p;
-    f[L.P(0) * ld + b] = y.Pq;
-    f[L.P(1) * ld + b] = y.Pp;
-    f[L.Zre(0) * ld + b] = y.zr11;
-    f[L.Zre(1) * ld + b] = y.zr12;
-    f[L.Zre(2) * ld + b] = y.zr22;
-    f[L.Zim(0) * ld + b] = y.zi11;
-    f[L.Zim(1) * ld + b] = y.zi12;
-    f[L.Zim(2) * ld + b] = y.zi22;
-    f[L.S() * ld + b] = y.S;
-    f[L.Lam() * ld + b] = y.Lam;
-    f[L.logw() * ld + b] = h.logw;
-    f[L.phre() * ld + b] = h.phre;
-    f[L.phim() * ld + b] = h.phim;
-    f[L.E() * ld + b] = h.E;
+    tr[L.X(0) * ld + b] = y.q;
+    tr[L.X(1) * ld + b] = y.p;
+    tr[L.P(0) * ld + b] = y.Pq;
+    tr[L.P(1) * ld + b] = y.Pp;
+    tr[L.Zre(0) * ld + b] = y.zr11;
+    tr[L.Zre(1) * ld + b] = y.zr12;
+    tr[L.Zre(2) * ld + b] = y.zr22;
+    tr[L.Zim(0) * ld + b] = y.zi11;
+    tr[L.Zim(1) * ld + b] = y.zi12;
+    tr[L.Zim(2) * ld + b] = y.zi22;
+    sc[kRowS * ld + b] = y.S;
+    sc[kRowLam * ld + b] = y.Lam;
+    sc[kRowLogw * ld + b] = h.logw;
+    sc[kRowPhre * ld + b] = h.phre;
+    sc[kRowPhim * ld + b] = h.phim;
+    sc[kRowE * ld + b] = h.E;
+    comp[b] = h.comp;
+    nhop[b] = h.nhop;
+  }
+  flush_counters(cnt, diag);
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision: the right-hand side of the ten trajectory values (X, P,
+// Z) is evaluated in FP32 at FP32 stage values; each step's increment
+// h/6 (k1 + 2k2 + 2k3 + k4) is formed in FP32 and added to an FP64 copy of
+// the state that lives in registers for the whole call (adding small FP32
+// increments to FP32 values would lose their low bits step after step).
+// S and Lam are accumulated in FP64 (neither feeds back into the
+// right-hand side, so their stage values are never formed); hop times,
+// thresholds and the hop itself are FP64.  The state is rounded to FP32
+// once, when the call stores it.
+
+struct Traj2f {
+  float q, p, Pq, Pp, zr11, zr12, zr22, zi11, zi12, zi22;
+};
+
+// one step's increment
+struct Inc2m {
+  Traj2f t;
+  double S, Lam;
+};
+
+__host__ __device__ inline void stage2m(const QcleF &mf, int l, const Ode2 &y0, Traj2f &ys, Inc2m &acc, int stage,
+                                        double c, float h6, double h6d) {
+  const Q1f k = qcle_q1f(mf, ys.q);
+  const float sg = (float)comp_sigma(l), bc = (float)comp_bcoef(l);
+  const float v = ys.p * mf.inv_mass;
+  const float E1 = sg * k.s1, E2 = sg * k.s2, E3 = sg * k.s3;
+  const float b1 = bc * k.s1, b2 = bc * k.s2;
+  Traj2f d;
+  d.q = v;
+  d.p = -E1;
+  d.Pq = b1 + E2 * ys.Pp;
+  d.Pp = -ys.Pq * mf.inv_mass;
+  d.zr11 = 2.0f * ys.zr12 * E2;
+  d.zi11 = 2.0f * ys.zi12 * E2 - ys.Pp * E3 - b2;
+  d.zr12 = ys.zr22 * E2 - ys.zr11 * mf.inv_mass;
+  d.zi12 = ys.zi22 * E2 - ys.zi11 * mf.inv_mass;
+  d.zr22 = -2.0f * ys.zr12 * mf.inv_mass;
+  d.zi22 = -2.0f * ys.zi12 * mf.inv_mass;
+  const double dS = (double)(bc * k.s);
+  const double dLam = (double)(2.0f * fabsf(v * k.d21));
+#define SHGB_TRAJ2_FIELDS(F) F(q) F(p) F(Pq) F(Pp) F(zr11) F(zr12) F(zr22) F(zi11) F(zi12) F(zi22)
+  if (stage == 0) {
+#define F(f) acc.t.f = d.f; ys.f = (float)(y0.f + c * (double)d.f);
+    SHGB_TRAJ2_FIELDS(F)
+#undef F
+    acc.S = dS;
+    acc.Lam = dLam;
+  } else if (stage < 3) {
+#define F(f) acc.t.f = acc.t.f + 2.0f * d.f; ys.f = (float)(y0.f + c * (double)d.f);
+    SHGB_TRAJ2_FIELDS(F)
+#undef F
+    acc.S = acc.S + 2.0 * dS;
+    acc.Lam = acc.Lam + 2.0 * dLam;
+  } else {
+#define F(f) acc.t.f = h6 * (acc.t.f + d.f);
+    SHGB_TRAJ2_FIELDS(F)
+#undef F
+    acc.S = h6d * (acc.S + dS);
+    acc.Lam = h6d * (acc.Lam + dLam);
+  }
+}
+
+// The increment of one classical RK4 step of size h on component l.
+__host__ __device__ inline void rk4_2m(const QcleF &mf, int l, const Ode2 &y, double h, Inc2m &inc) {
+  Traj2f ys;
+#define F(f) ys.f = (float)y.f;
+  SHGB_TRAJ2_FIELDS(F)
+#undef F
+  const double h6d = h * (1.0 / 6.0);
+  const float h6 = (float)h6d;
+#pragma unroll
+  for (int st = 0; st < 4; ++st) stage2m(mf, l, y, ys, inc, st, st == 2 ? h : 0.5 * h, h6, h6d);
+}
+
+__host__ __device__ inline void add_inc2m(Ode2 &y, const Inc2m &inc) {
+#define F(f) y.f = y.f + (double)inc.t.f;
+  SHGB_TRAJ2_FIELDS(F)
+#undef F
+  y.S = y.S + inc.S;
+  y.Lam = y.Lam + inc.Lam;
+}
+
+// The interval algorithm of interval2 on the mixed state.
+__host__ __device__ inline void interval2m(const DevModel &md, const QcleF &mf, Ode2 &y, HopScalars &h, double dt,
+                                           uint64_t gid, uint64_t seed, Counters &cnt) {
+  double rem = dt, hstep = dt, theta = 1.0;
+  bool partial = false;
+  int hops = 0;
+  Inc2m inc;
+  for (;;) {
+    rk4_2m(mf, h.comp, y, hstep, inc);
+    if (!partial) {
+      const bool capped = hops >= SHGB_HOP_CAP;
+      const double lam_n = y.Lam + inc.Lam;
+      if (!capped && fabs(lam_n - h.E) <= kTieRelMixed * h.E) cnt.thr_ties++;
+      if (capped || !(lam_n >= h.E)) {
+        if (capped) cnt.cap++;
+        add_inc2m(y, inc);
+        break;
+      }
+      theta = (h.E <= y.Lam) ? 0.0 : (h.E - y.Lam) / (lam_n - y.Lam);
+      if (theta > 0.0 && theta < 1.0) {
+        partial = true;
+        hstep = theta * rem;
+        continue;
+      }
+      if (theta >= 1.0) add_inc2m(y, inc);
+    } else {
+      add_inc2m(y, inc);
+      partial = false;
+    }
+    h.Lam = y.Lam;
+    hop_event_call(md, y.q, y.p, h, gid, seed, cnt, kTieRelMixed);
+    y.Lam = h.Lam;
+    ++hops;
+    rem = rem * (1.0 - theta);
+    if (!(rem > 0.0)) break;
+    hstep = rem;
+  }
+}
+#undef SHGB_TRAJ2_FIELDS
+
+__global__ void __launch_bounds__(256)
+step_m2_mixed_kernel(DevModel md, float *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
+                     uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps, double dt,
+                     uint64_t seed, uint64_t *diag) {
+  const Layout L(2, ld);
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  Counters cnt;
+  if (b < n) {
+    const QcleF mf = qcle_f32(md);
+    Ode2 y;
+    y.q = tr[L.X(0) * ld + b];
+    y.p = tr[L.X(1) * ld + b];
+    y.Pq = tr[L.P(0) * ld + b];
+    y.Pp = tr[L.P(1) * ld + b];
+    y.zr11 = tr[L.Zre(0) * ld + b];
+    y.zr12 = tr[L.Zre(1) * ld + b];
+    y.zr22 = tr[L.Zre(2) * ld + b];
+    y.zi11 = tr[L.Zim(0) * ld + b];
+    y.zi12 = tr[L.Zim(1) * ld + b];
+    y.zi22 = tr[L.Zim(2) * ld + b];
+    y.S = sc[kRowS * ld + b];
+    y.Lam = sc[kRowLam * ld + b];
+    HopScalars h;
+    h.logw = sc[kRowLogw * ld + b];
+    h.phre = sc[kRowPhre * ld + b];
+    h.phim = sc[kRowPhim * ld + b];
+    h.E = sc[kRowE * ld + b];
+    h.comp = comp[b];
+    h.nhop = nhop[b];
+    h.Lam = y.Lam;
+    const uint64_t gid = gid0 + (uint64_t)b;
+    for (int s = 0; s < nsteps; ++s) interval2m(md, mf, y, h, dt, gid, seed, cnt);
+    const double chk = y.q + y.p + y.Pq + y.Pp + y.zr11 + y.zr12 + y.zr22 + y.zi11 + y.zi12 + y.zi22 + y.S +
+                       y.Lam + h.logw;
+    if (!isfinite(chk)) cnt.nonfinite++;
+    tr[L.X(0) * ld + b] = (float)y.q;
+    tr[L.X(1) * ld + b] = (float)y.p;
+    tr[L.P(0) * ld + b] = (float)y.Pq;
+    tr[L.P(1) * ld + b] = (float)y.Pp;
+    tr[L.Zre(0) * ld + b] = (float)y.zr11;
+    tr[L.Zre(1) * ld + b] = (float)y.zr12;
+    tr[L.Zre(2) * ld + b] = (float)y.zr22;
+    tr[L.Zim(0) * ld + b] = (float)y.zi11;
+    tr[L.Zim(1) * ld + b] = (float)y.zi12;
+    tr[L.Zim(2) * ld + b] = (float)y.zi22;
+    sc[kRowS * ld + b] = y.S;
+    sc[kRowLam * ld + b] = y.Lam;
+    sc[kRowLogw * ld + b] = h.logw;
+    sc[kRowPhre * ld + b] = h.phre;
+    sc[kRowPhim * ld + b] = h.phim;
+    sc[kRowE * ld + b] = h.E;
     comp[b] = h.comp;
     nhop[b] = h.nhop;
   }
@@ -165,8 +352,13 @@ hipError_t launch_step_m2(const DevModel &md, const shgb_state &st, int nsteps, 
   if (st.n_beams == 0 || nsteps == 0) return hipSuccess;
   const int threads = 256;
   const int64_t blocks = (st.n_beams + threads - 1) / threads;
-  hipLaunchKernelGGL(step_m2_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, md, st.f64,
-                     st.comp, st.nhop, st.n_beams, st.ld, st.beam_id_offset, nsteps, dt, seed, diag);
+  double *sc = scalar_block(st);
+  if (mixed(st))
+    hipLaunchKernelGGL(step_m2_mixed_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, md, st.f32, sc,
+                       st.comp, st.nhop, st.n_beams, st.ld, st.beam_id_offset, nsteps, dt, seed, diag);
+  else
+    hipLaunchKernelGGL(step_m2_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, md, st.f64, sc,
+                       st.comp, st.nhop, st.n_beams, st.ld, st.beam_id_offset, nsteps, dt, seed, diag);
   return hipGetLastError();
 }
 

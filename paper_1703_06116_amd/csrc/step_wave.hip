@@ -23,6 +23,12 @@
 // c < m of the group owns X_c and P_c; the scalars (S, Lam, weights, the
 // threshold and the component) are replicated over the group, so the hop
 // logic (Sec. 2.4 steps 3-5) is uniform within a group.
+//
+// Precision: an FP64 state is integrated in FP64 throughout.  For a mixed
+// state the stage values and the right-hand side are FP32 (the exchange
+// area too), each step's increment is formed in FP32 and added to an FP64
+// copy of the state held in registers for the whole call; S and Lam are
+// FP64 as in the FP64 path.
 #include "device.h"
 
 namespace shgb {
@@ -42,61 +48,81 @@ struct PG {
   static_assert(M <= LPB, "X and P need one lane per coordinate");
 };
 
-// One beam's exchange area.
-template <int D>
+// One beam's exchange area (T: the stage precision).
+template <int D, typename T>
 struct PgLds {
-  double rp_r[D][D], rp_i[D][D];   // Zrp
-  double pp_r[D][D], pp_i[D][D];   // Zpp (both triangles)
-  double rho_r[D], rho_i[D], chi_r[D], chi_i[D];
-  double x[2 * D], p[2 * D];
+  T rp_r[D][D], rp_i[D][D];   // Zrp
+  T pp_r[D][D], pp_i[D][D];   // Zpp (both triangles)
+  T rho_r[D], rho_i[D], chi_r[D], chi_i[D];
+  T x[2 * D], p[2 * D];
 };
 
 // Values of one pair group: Zrr_ab, Zrp_ab, Zrp_ba, Zpp_ab (re, im).
+enum { kRrR, kRrI, kAbR, kAbI, kBaR, kBaI, kPpR, kPpI, kGrpN };
+template <typename T>
 struct Grp {
-  double rr_r, rr_i, ab_r, ab_i, ba_r, ba_i, pp_r, pp_i;
+  T v[kGrpN];
 };
 
-template <int D, int LPB>
+template <int D, int LPB, typename T>
 struct PgY {
-  Grp g[PG<D, LPB>::NG];
-  double x, p, S, Lam;
+  Grp<T> g[PG<D, LPB>::NG];
+  T x, p;
+  double S, Lam;
 };
 
-template <int D, int LPB>
+template <int D, int LPB, typename T>
 struct PgCtx {
   int r;                         // lane within the beam's group
   int a[PG<D, LPB>::NG], b[PG<D, LPB>::NG];  // pair of each owned group, -1: none
-  double ka[PG<D, LPB>::NG], kb[PG<D, LPB>::NG];  // M w^2 of the pair's bath indices (0 for index 0)
-  double kc;                     // M w^2 of the lane's coordinate (X/P lanes)
+  T ka[PG<D, LPB>::NG], kb[PG<D, LPB>::NG];  // M w^2 of the pair's bath indices (0 for index 0)
+  T kc;                          // M w^2 of the lane's coordinate (X/P lanes)
 };
 
-template <int D, int LPB>
-__device__ inline void pg_publish(const PgCtx<D, LPB> &cx, const PgY<D, LPB> &y, PgLds<D> &s) {
+// The adiabatic quantities along q1 in the stage precision.
+template <typename T>
+struct Q1T {
+  T s, s1, s2, s3, d21;
+};
+
+__device__ inline Q1T<double> q1_eval(const DevModel &md, const QcleF &, double q) {
+  const Q1 k = qcle_q1(md, q);
+  return Q1T<double>{k.s, k.s1, k.s2, k.s3, k.d21};
+}
+
+__device__ inline Q1T<float> q1_eval(const DevModel &, const QcleF &mf, float q) {
+  const Q1f k = qcle_q1f(mf, q);
+  return Q1T<float>{k.s, k.s1, k.s2, k.s3, k.d21};
+}
+
+template <int D, int LPB, typename T>
+__device__ inline void pg_publish(const PgCtx<D, LPB, T> &cx, const PgY<D, LPB, T> &y, PgLds<D, T> &s) {
 #pragma unroll
   for (int e = 0; e < PG<D, LPB>::NG; ++e) {
     const int a = cx.a[e], b = cx.b[e];
     if (a >= 0) {
-      s.rp_r[a][b] = y.g[e].ab_r;
-      s.rp_i[a][b] = y.g[e].ab_i;
-      s.rp_r[b][a] = y.g[e].ba_r;   // a == b: the same entry, written twice with one value
-      s.rp_i[b][a] = y.g[e].ba_i;
-      s.pp_r[a][b] = y.g[e].pp_r;
-      s.pp_i[a][b] = y.g[e].pp_i;
-      s.pp_r[b][a] = y.g[e].pp_r;
-      s.pp_i[b][a] = y.g[e].pp_i;
+      const T *v = y.g[e].v;
+      s.rp_r[a][b] = v[kAbR];
+      s.rp_i[a][b] = v[kAbI];
+      s.rp_r[b][a] = v[kBaR];   // a == b: the same entry, written twice with one value
+      s.rp_i[b][a] = v[kBaI];
+      s.pp_r[a][b] = v[kPpR];
+      s.pp_i[a][b] = v[kPpI];
+      s.pp_r[b][a] = v[kPpR];
+      s.pp_i[b][a] = v[kPpI];
     }
   }
   if (cx.r < 2 * D) { s.x[cx.r] = y.x; s.p[cx.r] = y.p; }
   wave_lds_sync();
   if (cx.r < D) {
     const int i = cx.r;
-    double sr = 0.0, si = 0.0;
+    T sr = 0, si = 0;
     for (int k = 1; k < D; ++k) { sr += s.rp_r[i][k]; si += s.rp_i[i][k]; }
     s.rho_r[i] = sr;
     s.rho_i[i] = si;
   } else if (cx.r < 2 * D) {
     const int j = cx.r - D;
-    double sr = 0.0, si = 0.0;
+    T sr = 0, si = 0;
     for (int k = 1; k < D; ++k) { sr += s.pp_r[k][j]; si += s.pp_i[k][j]; }
     s.chi_r[j] = sr;
     s.chi_i[j] = si;
@@ -104,21 +130,96 @@ __device__ inline void pg_publish(const PgCtx<D, LPB> &cx, const PgY<D, LPB> &y,
   wave_lds_sync();
 }
 
-// One Runge-Kutta stage for the lane's share of the state.  The stage values
-// ys have been published to s; the derivative of each owned value is formed
-// and folded at once into the accumulator and the next stage:
+// Per-stage scalars of the beam's right-hand side.
+template <typename T>
+struct StageCoef {
+  Q1T<T> k;
+  T sg, bc, H00, B00, lam, im;
+};
+
+template <int D, typename T>
+__device__ inline StageCoef<T> stage_coef(const DevModel &md, const QcleF &mf, int l, const PgLds<D, T> &s) {
+  StageCoef<T> c;
+  c.k = q1_eval(md, mf, s.x[0]);
+  c.sg = (T)comp_sigma(l);
+  c.bc = (T)comp_bcoef(l);
+  c.H00 = c.sg * c.k.s2;
+  c.lam = (T)md.lam;
+  c.im = (T)md.inv_mass;
+  c.B00 = -s.p[D] * c.sg * c.k.s3 - c.bc * c.k.s2;
+  return c;
+}
+
+// Derivatives of one pair group (a, b) at the stage values v.
+template <int D, typename T>
+__device__ inline void grp_deriv(int a, int b, T ka, T kb, const StageCoef<T> &c, const T *v, const PgLds<D, T> &s,
+                                 T *d) {
+  const T lam = c.lam, im = c.im;
+  const T Ha = a == 0 ? c.H00 : ka, Hb = b == 0 ? c.H00 : kb;
+  // Zrr_ab' = (Zrp H)_ab + (Zrp H)_ba
+  T xr = v[kAbR] * Hb, xi = v[kAbI] * Hb;
+  if (b > 0) { xr += lam * s.rp_r[a][0]; xi += lam * s.rp_i[a][0]; }
+  else { xr += lam * s.rho_r[a]; xi += lam * s.rho_i[a]; }
+  T tr = v[kBaR] * Ha, ti = v[kBaI] * Ha;
+  if (a > 0) { tr += lam * s.rp_r[b][0]; ti += lam * s.rp_i[b][0]; }
+  else { tr += lam * s.rho_r[b]; ti += lam * s.rho_i[b]; }
+  d[kRrR] = xr + tr;
+  d[kRrI] = (xi + ti) + ((a == 0 && b == 0) ? c.B00 : (T)0);
+  // Zrp_ab' = (H Zpp)_ab - Zrr_ab / M,  Zrp_ba' = (H Zpp)_ba - Zrr_ba / M
+  T ur = Ha * v[kPpR], ui = Ha * v[kPpI];
+  if (a > 0) { ur += lam * s.pp_r[0][b]; ui += lam * s.pp_i[0][b]; }
+  else { ur += lam * s.chi_r[b]; ui += lam * s.chi_i[b]; }
+  T wr = Hb * v[kPpR], wi = Hb * v[kPpI];
+  if (b > 0) { wr += lam * s.pp_r[0][a]; wi += lam * s.pp_i[0][a]; }
+  else { wr += lam * s.chi_r[a]; wi += lam * s.chi_i[a]; }
+  d[kAbR] = ur - v[kRrR] * im;
+  d[kAbI] = ui - v[kRrI] * im;
+  d[kBaR] = wr - v[kRrR] * im;
+  d[kBaI] = wi - v[kRrI] * im;
+  // Zpp_ab' = -(Zrp_ba + Zrp_ab) / M
+  d[kPpR] = -(v[kBaR] + v[kAbR]) * im;
+  d[kPpI] = -(v[kBaI] + v[kAbI]) * im;
+}
+
+// Derivatives of the lane's coordinate X_c, P_c (c = lane index < m).
+template <int D, typename T>
+__device__ inline void xp_deriv(int cc, T kc, const StageCoef<T> &c, const PgLds<D, T> &s, T &dx, T &dp) {
+  const T lam = c.lam, im = c.im;
+  dx = 0;
+  dp = 0;
+  if (cc < D) {
+    dx = s.x[D + cc] * im;
+    if (cc == 0) {
+      T sp = 0;
+      for (int j = 1; j < D; ++j) sp += s.p[D + j];
+      dp = c.bc * c.k.s1 + c.H00 * s.p[D] + lam * sp;
+    } else {
+      dp = kc * s.p[D + cc] + lam * s.p[D];
+    }
+  } else if (cc < 2 * D) {
+    const int kk = cc - D;
+    if (kk == 0) {
+      T sq = 0;
+      for (int j = 1; j < D; ++j) sq += s.x[j];
+      dx = -(lam * sq + c.sg * c.k.s1);
+    } else {
+      dx = -(kc * s.x[kk] + lam * s.x[0]);
+    }
+    dp = -s.p[kk] * im;
+  }
+}
+
+// One Runge-Kutta stage of the FP64 path.  The stage values ys have been
+// published to s; the derivative of each owned value is formed and folded
+// at once into the accumulator and the next stage:
 //   stage 0: acc = k;            ys = y0 + c k
 //   stage 1, 2: acc += 2 k;      ys = y0 + c k
 //   stage 3: acc = y0 + h6 (acc + k)   (the step's result)
 template <int D, int LPB>
-__device__ inline void pg_stage(const DevModel &md, int l, const PgCtx<D, LPB> &cx, const PgY<D, LPB> &y0,
-                                PgY<D, LPB> &ys, PgY<D, LPB> &acc, int stage, double c, double h6,
-                                const PgLds<D> &s) {
-  const double q1 = s.x[0], p1 = s.x[D];
-  const Q1 k = qcle_q1(md, q1);
-  const double sg = comp_sigma(l), bc = comp_bcoef(l);
-  const double H00 = sg * k.s2, lam = md.lam, im = md.inv_mass;
-  const double B00 = -s.p[D] * sg * k.s3 - bc * k.s2;
+__device__ inline void pg_stage(const DevModel &md, const QcleF &mf, int l, const PgCtx<D, LPB, double> &cx,
+                                const PgY<D, LPB, double> &y0, PgY<D, LPB, double> &ys, PgY<D, LPB, double> &acc,
+                                int stage, double c, double h6, const PgLds<D, double> &s) {
+  const StageCoef<double> sc = stage_coef<D, double>(md, mf, l, s);
   auto fold = [&](double &a, double &yv, double y0v, double d) {
     if (stage == 0) a = d;
     else if (stage < 3) a = a + 2.0 * d;
@@ -127,118 +228,156 @@ __device__ inline void pg_stage(const DevModel &md, int l, const PgCtx<D, LPB> &
   };
 #pragma unroll
   for (int e = 0; e < PG<D, LPB>::NG; ++e) {
-    const int a = cx.a[e], b = cx.b[e];
-    if (a >= 0) {
-      const Grp v = ys.g[e];
-      const double Ha = a == 0 ? H00 : cx.ka[e], Hb = b == 0 ? H00 : cx.kb[e];
-      // Zrr_ab' = (Zrp H)_ab + (Zrp H)_ba
-      double xr = v.ab_r * Hb, xi = v.ab_i * Hb;
-      if (b > 0) { xr += lam * s.rp_r[a][0]; xi += lam * s.rp_i[a][0]; }
-      else { xr += lam * s.rho_r[a]; xi += lam * s.rho_i[a]; }
-      double tr = v.ba_r * Ha, ti = v.ba_i * Ha;
-      if (a > 0) { tr += lam * s.rp_r[b][0]; ti += lam * s.rp_i[b][0]; }
-      else { tr += lam * s.rho_r[b]; ti += lam * s.rho_i[b]; }
-      const double drr_r = xr + tr;
-      const double drr_i = (xi + ti) + ((a == 0 && b == 0) ? B00 : 0.0);
-      // Zrp_ab' = (H Zpp)_ab - Zrr_ab / M,  Zrp_ba' = (H Zpp)_ba - Zrr_ba / M
-      double ur = Ha * v.pp_r, ui = Ha * v.pp_i;
-      if (a > 0) { ur += lam * s.pp_r[0][b]; ui += lam * s.pp_i[0][b]; }
-      else { ur += lam * s.chi_r[b]; ui += lam * s.chi_i[b]; }
-      double wr = Hb * v.pp_r, wi = Hb * v.pp_i;
-      if (b > 0) { wr += lam * s.pp_r[0][a]; wi += lam * s.pp_i[0][a]; }
-      else { wr += lam * s.chi_r[a]; wi += lam * s.chi_i[a]; }
-      const double dab_r = ur - v.rr_r * im, dab_i = ui - v.rr_i * im;
-      const double dba_r = wr - v.rr_r * im, dba_i = wi - v.rr_i * im;
-      // Zpp_ab' = -(Zrp_ba + Zrp_ab) / M
-      const double dpp_r = -(v.ba_r + v.ab_r) * im, dpp_i = -(v.ba_i + v.ab_i) * im;
-      const Grp &g0 = y0.g[e];
-      Grp &ga = acc.g[e], &gy = ys.g[e];
-      fold(ga.rr_r, gy.rr_r, g0.rr_r, drr_r);
-      fold(ga.rr_i, gy.rr_i, g0.rr_i, drr_i);
-      fold(ga.ab_r, gy.ab_r, g0.ab_r, dab_r);
-      fold(ga.ab_i, gy.ab_i, g0.ab_i, dab_i);
-      fold(ga.ba_r, gy.ba_r, g0.ba_r, dba_r);
-      fold(ga.ba_i, gy.ba_i, g0.ba_i, dba_i);
-      fold(ga.pp_r, gy.pp_r, g0.pp_r, dpp_r);
-      fold(ga.pp_i, gy.pp_i, g0.pp_i, dpp_i);
+    if (cx.a[e] >= 0) {
+      double d[kGrpN];
+      grp_deriv<D, double>(cx.a[e], cx.b[e], cx.ka[e], cx.kb[e], sc, ys.g[e].v, s, d);
+#pragma unroll
+      for (int j = 0; j < kGrpN; ++j) fold(acc.g[e].v[j], ys.g[e].v[j], y0.g[e].v[j], d[j]);
     }
   }
-  const int cc = cx.r;
-  double dx = 0.0, dp = 0.0;
-  if (cc < D) {
-    dx = s.x[D + cc] * im;
-    if (cc == 0) {
-      double sp = 0.0;
-      for (int j = 1; j < D; ++j) sp += s.p[D + j];
-      dp = bc * k.s1 + H00 * s.p[D] + lam * sp;
-    } else {
-      dp = cx.kc * s.p[D + cc] + lam * s.p[D];
-    }
-  } else if (cc < 2 * D) {
-    const int kk = cc - D;
-    if (kk == 0) {
-      double sq = 0.0;
-      for (int j = 1; j < D; ++j) sq += s.x[j];
-      dx = -(lam * sq + sg * k.s1);
-    } else {
-      dx = -(cx.kc * s.x[kk] + lam * s.x[0]);
-    }
-    dp = -s.p[kk] * im;
-  }
+  double dx, dp;
+  xp_deriv<D, double>(cx.r, cx.kc, sc, s, dx, dp);
   fold(acc.x, ys.x, y0.x, dx);
   fold(acc.p, ys.p, y0.p, dp);
-  fold(acc.S, ys.S, y0.S, bc * k.s);
-  fold(acc.Lam, ys.Lam, y0.Lam, 2.0 * fabs(p1 * im * k.d21));
+  double dS = sc.bc * sc.k.s, dL = 2.0 * fabs(s.x[D] * sc.im * sc.k.d21), unused = 0.0;
+  fold(acc.S, unused, y0.S, dS);
+  fold(acc.Lam, unused, y0.Lam, dL);
 }
 
 // One classical RK4 step of the group's beam on component l, into `out`;
 // `s` is clobbered.
 template <int D, int LPB>
-__device__ inline void pg_rk4(const DevModel &md, int l, const PgCtx<D, LPB> &cx, const PgY<D, LPB> &y, double h,
-                              PgY<D, LPB> &out, PgLds<D> &s) {
-  PgY<D, LPB> ys = y;
+__device__ inline void pg_rk4(const DevModel &md, const QcleF &mf, int l, const PgCtx<D, LPB, double> &cx,
+                              const PgY<D, LPB, double> &y, double h, PgY<D, LPB, double> &out,
+                              PgLds<D, double> &s) {
+  PgY<D, LPB, double> ys = y;
   const double h6 = h / 6.0;
   const double cs[3] = {0.5 * h, 0.5 * h, h};
 #pragma unroll 1
   for (int st = 0; st < 4; ++st) {
     pg_publish(cx, ys, s);
-    pg_stage(md, l, cx, y, ys, out, st, st < 3 ? cs[st] : 0.0, h6, s);
+    pg_stage(md, mf, l, cx, y, ys, out, st, st < 3 ? cs[st] : 0.0, h6, s);
+    wave_lds_sync();
+  }
+}
+
+// Mixed precision: one stage with FP32 stage values and accumulator; stage 3
+// leaves the step's increment h/6 (k1 + 2k2 + 2k3 + k4) in acc (FP32 for the
+// trajectory values, FP64 for S and Lam).
+template <int D, int LPB>
+__device__ inline void pg_stage_m(const DevModel &md, const QcleF &mf, int l, const PgCtx<D, LPB, float> &cx,
+                                  const PgY<D, LPB, double> &y0, PgY<D, LPB, float> &ys, PgY<D, LPB, float> &acc,
+                                  int stage, double c, float h6, double h6d, const PgLds<D, float> &s) {
+  const StageCoef<float> sc = stage_coef<D, float>(md, mf, l, s);
+  auto fold = [&](float &a, float &yv, double y0v, float d) {
+    if (stage == 0) a = d;
+    else if (stage < 3) a = a + 2.0f * d;
+    else a = h6 * (a + d);
+    if (stage < 3) yv = (float)(y0v + c * (double)d);
+  };
+  auto fold64 = [&](double &a, double d) {
+    if (stage == 0) a = d;
+    else if (stage < 3) a = a + 2.0 * d;
+    else a = h6d * (a + d);
+  };
+#pragma unroll
+  for (int e = 0; e < PG<D, LPB>::NG; ++e) {
+    if (cx.a[e] >= 0) {
+      float d[kGrpN];
+      grp_deriv<D, float>(cx.a[e], cx.b[e], cx.ka[e], cx.kb[e], sc, ys.g[e].v, s, d);
+#pragma unroll
+      for (int j = 0; j < kGrpN; ++j) fold(acc.g[e].v[j], ys.g[e].v[j], y0.g[e].v[j], d[j]);
+    }
+  }
+  float dx, dp;
+  xp_deriv<D, float>(cx.r, cx.kc, sc, s, dx, dp);
+  fold(acc.x, ys.x, y0.x, dx);
+  fold(acc.p, ys.p, y0.p, dp);
+  fold64(acc.S, (double)(sc.bc * sc.k.s));
+  fold64(acc.Lam, (double)(2.0f * fabsf(s.x[D] * sc.im * sc.k.d21)));
+}
+
+template <int D, int LPB>
+__device__ inline void pg_rk4_m(const DevModel &md, const QcleF &mf, int l, const PgCtx<D, LPB, float> &cx,
+                                const PgY<D, LPB, double> &y, double h, PgY<D, LPB, float> &inc,
+                                PgLds<D, float> &s) {
+  PgY<D, LPB, float> ys;
+#pragma unroll
+  for (int e = 0; e < PG<D, LPB>::NG; ++e)
+#pragma unroll
+    for (int j = 0; j < kGrpN; ++j) ys.g[e].v[j] = (float)y.g[e].v[j];
+  ys.x = (float)y.x;
+  ys.p = (float)y.p;
+  const double h6d = h * (1.0 / 6.0);
+  const float h6 = (float)h6d;
+  const double cs[3] = {0.5 * h, 0.5 * h, h};
+#pragma unroll 1
+  for (int st = 0; st < 4; ++st) {
+    pg_publish(cx, ys, s);
+    pg_stage_m(md, mf, l, cx, y, ys, inc, st, st < 3 ? cs[st] : 0.0, h6, h6d, s);
     wave_lds_sync();
   }
 }
 
 template <int D, int LPB>
-__device__ inline void pg_interval(const DevModel &md, const PgCtx<D, LPB> &cx, int base, PgY<D, LPB> &y,
-                                   HopScalars &h, double dt, uint64_t gid, uint64_t seed, Counters &cnt,
-                                   PgLds<D> &s) {
+__device__ inline void pg_add_inc(PgY<D, LPB, double> &y, const PgY<D, LPB, float> &inc) {
+#pragma unroll
+  for (int e = 0; e < PG<D, LPB>::NG; ++e)
+#pragma unroll
+    for (int j = 0; j < kGrpN; ++j) y.g[e].v[j] = y.g[e].v[j] + (double)inc.g[e].v[j];
+  y.x = y.x + (double)inc.x;
+  y.p = y.p + (double)inc.p;
+  y.S = y.S + inc.S;
+  y.Lam = y.Lam + inc.Lam;
+}
+
+// One interval [t_n, t_n + dt] (Sec. 2.4 steps 3-5) for the group's beam: a
+// trial RK4 step; if Lam reaches the threshold, the step to the
+// interpolated hop time, the hop, and the rest of the interval.  MIXED
+// selects the mixed-precision step.
+template <int D, int LPB, bool MIXED>
+__device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const PgCtx<D, LPB, double> &cx,
+                                   const PgCtx<D, LPB, float> &cxf, int base, PgY<D, LPB, double> &y,
+                                   HopScalars &h, double dt, uint64_t gid, uint64_t seed, Counters &cnt, void *lds) {
+  const double tie_rel = MIXED ? kTieRelMixed : kTieRel;
   double rem = dt, hstep = dt, theta = 1.0;
   bool partial = false;
   int hops = 0;
-  PgY<D, LPB> yn;
+  using YN = typename std::conditional<MIXED, PgY<D, LPB, float>, PgY<D, LPB, double>>::type;
+  YN yn;  // FP64: the trial result; mixed: the trial increment
+  auto trial = [&](double hh) {
+    if constexpr (MIXED) pg_rk4_m(md, mf, h.comp, cxf, y, hh, yn, *(PgLds<D, float> *)lds);
+    else pg_rk4(md, mf, h.comp, cx, y, hh, yn, *(PgLds<D, double> *)lds);
+  };
+  auto accept = [&]() {
+    if constexpr (MIXED) pg_add_inc(y, yn);
+    else y = yn;
+  };
   for (;;) {
-    pg_rk4(md, h.comp, cx, y, hstep, yn, s);
+    trial(hstep);
     if (!partial) {
       const bool capped = hops >= SHGB_HOP_CAP;
-      if (!capped && fabs(yn.Lam - h.E) <= kTieRel * h.E) cnt.thr_ties++;
-      if (capped || !(yn.Lam >= h.E)) {
+      const double lam_n = MIXED ? y.Lam + yn.Lam : yn.Lam;
+      if (!capped && fabs(lam_n - h.E) <= tie_rel * h.E) cnt.thr_ties++;
+      if (capped || !(lam_n >= h.E)) {
         if (capped) cnt.cap++;
-        y = yn;
+        accept();
         break;
       }
-      theta = (h.E <= y.Lam) ? 0.0 : (h.E - y.Lam) / (yn.Lam - y.Lam);
+      theta = (h.E <= y.Lam) ? 0.0 : (h.E - y.Lam) / (lam_n - y.Lam);
       if (theta > 0.0 && theta < 1.0) {
         partial = true;
         hstep = theta * rem;
         continue;
       }
-      if (theta >= 1.0) y = yn;
+      if (theta >= 1.0) accept();
     } else {
-      y = yn;
+      accept();
       partial = false;
     }
     h.Lam = y.Lam;
     const double q1 = __shfl(y.x, base, 64), p1 = __shfl(y.x, base + D, 64);
-    hop_event(md, q1, p1, h, gid, seed, cnt);
+    hop_event_call(md, q1, p1, h, gid, seed, cnt, tie_rel);
     y.Lam = h.Lam;
     ++hops;
     rem = rem * (1.0 - theta);
@@ -253,13 +392,18 @@ constexpr int kWavesPerBlock = 4;
 #endif
 constexpr int kLanesPerBeamD12 = SHGB_D12_LANES_PER_BEAM;  // 32: two beams per wavefront
 
-template <int D, int LPB>
+// TS: element type of the stored trajectory rows (double: FP64 path, float:
+// mixed path).  The register copy of the state is FP64 in both.
+template <int D, int LPB, typename TS>
 __global__ void __launch_bounds__(64 * kWavesPerBlock)
-step_wave_kernel(DevModel md, double *__restrict__ f, int32_t *__restrict__ comp, uint32_t *__restrict__ nhop,
-                 int64_t n, int64_t ld, uint64_t gid0, int nsteps, double dt, uint64_t seed, uint64_t *diag) {
+__attribute__((amdgpu_waves_per_eu(sizeof(TS) == sizeof(float) ? 2 : 1)))
+step_wave_kernel(DevModel md, TS *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
+                 uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps, double dt,
+                 uint64_t seed, uint64_t *diag) {
   using C = PG<D, LPB>;
   constexpr int M = C::M;
-  __shared__ PgLds<D> lds[kWavesPerBlock * C::G];
+  constexpr bool MIXED = sizeof(TS) == sizeof(float);
+  __shared__ PgLds<D, TS> lds[kWavesPerBlock * C::G];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int grp = lane / LPB, r = lane % LPB, base = grp * LPB;
   const int slot = wid * C::G + grp;
@@ -267,17 +411,20 @@ step_wave_kernel(DevModel md, double *__restrict__ f, int32_t *__restrict__ comp
   Counters cnt;
   if (b < n) {  // uniform across the beam's lanes
     const Layout L(M, ld);
-    PgLds<D> &s = lds[slot];
-    PgCtx<D, LPB> cx;
-    cx.r = r;
+    const QcleF mf = qcle_f32(md);
+    PgCtx<D, LPB, double> cx;
+    PgCtx<D, LPB, float> cxf;
+    cx.r = cxf.r = r;
     cx.kc = (r > 0 && r < D) ? md.bath_k[r] : ((r > D && r < M) ? md.bath_k[r - D] : 0.0);
-    PgY<D, LPB> y;
+    cxf.kc = (float)cx.kc;
+    PgY<D, LPB, double> y;
 #pragma unroll
     for (int e = 0; e < C::NG; ++e) {
       const int gi = r + LPB * e;
       cx.a[e] = cx.b[e] = -1;
       cx.ka[e] = cx.kb[e] = 0.0;
-      y.g[e] = Grp{0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int j = 0; j < kGrpN; ++j) y.g[e].v[j] = 0.0;
       if (gi < C::NGRP) {
         int a = 0, rem = gi;
         while (rem >= D - a) { rem -= D - a; ++a; }
@@ -288,28 +435,40 @@ step_wave_kernel(DevModel md, double *__restrict__ f, int32_t *__restrict__ comp
         cx.kb[e] = bb > 0 ? md.bath_k[bb] : 0.0;
         const int trr = Layout::tri(M, a, bb), tab = Layout::tri(M, a, D + bb), tba = Layout::tri(M, bb, D + a),
                   tpp = Layout::tri(M, D + a, D + bb);
-        y.g[e] = Grp{f[L.Zre(trr) * ld + b], f[L.Zim(trr) * ld + b], f[L.Zre(tab) * ld + b], f[L.Zim(tab) * ld + b],
-                     f[L.Zre(tba) * ld + b], f[L.Zim(tba) * ld + b], f[L.Zre(tpp) * ld + b], f[L.Zim(tpp) * ld + b]};
+        const int row[kGrpN] = {L.Zre(trr), L.Zim(trr), L.Zre(tab), L.Zim(tab),
+                                L.Zre(tba), L.Zim(tba), L.Zre(tpp), L.Zim(tpp)};
+#pragma unroll
+        for (int j = 0; j < kGrpN; ++j) y.g[e].v[j] = (double)tr[row[j] * ld + b];
       }
+      cxf.a[e] = cx.a[e];
+      cxf.b[e] = cx.b[e];
+      cxf.ka[e] = (float)cx.ka[e];
+      cxf.kb[e] = (float)cx.kb[e];
     }
-    y.x = r < M ? f[L.X(r) * ld + b] : 0.0;
-    y.p = r < M ? f[L.P(r) * ld + b] : 0.0;
-    y.S = f[L.S() * ld + b];
-    y.Lam = f[L.Lam() * ld + b];
+    y.x = r < M ? (double)tr[L.X(r) * ld + b] : 0.0;
+    y.p = r < M ? (double)tr[L.P(r) * ld + b] : 0.0;
+    y.S = sc[kRowS * ld + b];
+    y.Lam = sc[kRowLam * ld + b];
     HopScalars h;
-    h.logw = f[L.logw() * ld + b];
-    h.phre = f[L.phre() * ld + b];
-    h.phim = f[L.phim() * ld + b];
-    h.E = f[L.E() * ld + b];
+    h.logw = sc[kRowLogw * ld + b];
+    h.phre = sc[kRowPhre * ld + b];
+    h.phim = sc[kRowPhim * ld + b];
+    h.E = sc[kRowE * ld + b];
     h.comp = comp[b];
     h.nhop = nhop[b];
     h.Lam = y.Lam;
     const uint64_t gid = gid0 + (uint64_t)b;
-    for (int st = 0; st < nsteps; ++st) pg_interval<D, LPB>(md, cx, base, y, h, dt, gid, seed, cnt, s);
-    double chk = y.x + y.p + y.S + y.Lam + h.logw;
+    for (int st = 0; st < nsteps; ++st)
+      pg_interval<D, LPB, MIXED>(md, mf, cx, cxf, base, y, h, dt, gid, seed, cnt, (void *)&lds[slot]);
+    // finiteness of the values this lane owns (slots without a pair group
+    // or coordinate hold no state)
+    double chk = y.S + y.Lam + h.logw;
+    if (r < M) chk += y.x + y.p;
 #pragma unroll
-    for (int e = 0; e < C::NG; ++e) chk += y.g[e].rr_r + y.g[e].rr_i + y.g[e].ab_r + y.g[e].ab_i + y.g[e].ba_r +
-                                            y.g[e].ba_i + y.g[e].pp_r + y.g[e].pp_i;
+    for (int e = 0; e < C::NG; ++e)
+      if (cx.a[e] >= 0)
+#pragma unroll
+        for (int j = 0; j < kGrpN; ++j) chk += y.g[e].v[j];
     int bad = !isfinite(chk);
 #pragma unroll
     for (int off = 1; off < LPB; off <<= 1) bad |= __shfl_xor(bad, off, 64);
@@ -319,29 +478,24 @@ step_wave_kernel(DevModel md, double *__restrict__ f, int32_t *__restrict__ comp
       if (a >= 0) {
         const int trr = Layout::tri(M, a, bb), tab = Layout::tri(M, a, D + bb), tba = Layout::tri(M, bb, D + a),
                   tpp = Layout::tri(M, D + a, D + bb);
-        f[L.Zre(trr) * ld + b] = y.g[e].rr_r;
-        f[L.Zim(trr) * ld + b] = y.g[e].rr_i;
-        f[L.Zre(tab) * ld + b] = y.g[e].ab_r;
-        f[L.Zim(tab) * ld + b] = y.g[e].ab_i;
-        if (a != bb) {
-          f[L.Zre(tba) * ld + b] = y.g[e].ba_r;
-          f[L.Zim(tba) * ld + b] = y.g[e].ba_i;
-        }
-        f[L.Zre(tpp) * ld + b] = y.g[e].pp_r;
-        f[L.Zim(tpp) * ld + b] = y.g[e].pp_i;
+        const int row[kGrpN] = {L.Zre(trr), L.Zim(trr), L.Zre(tab), L.Zim(tab),
+                                L.Zre(tba), L.Zim(tba), L.Zre(tpp), L.Zim(tpp)};
+#pragma unroll
+        for (int j = 0; j < kGrpN; ++j)
+          if (a != bb || (j != kBaR && j != kBaI)) tr[row[j] * ld + b] = (TS)y.g[e].v[j];
       }
     }
     if (r < M) {
-      f[L.X(r) * ld + b] = y.x;
-      f[L.P(r) * ld + b] = y.p;
+      tr[L.X(r) * ld + b] = (TS)y.x;
+      tr[L.P(r) * ld + b] = (TS)y.p;
     }
     if (r == 0) {
-      f[L.S() * ld + b] = y.S;
-      f[L.Lam() * ld + b] = y.Lam;
-      f[L.logw() * ld + b] = h.logw;
-      f[L.phre() * ld + b] = h.phre;
-      f[L.phim() * ld + b] = h.phim;
-      f[L.E() * ld + b] = h.E;
+      sc[kRowS * ld + b] = y.S;
+      sc[kRowLam * ld + b] = y.Lam;
+      sc[kRowLogw * ld + b] = h.logw;
+      sc[kRowPhre * ld + b] = h.phre;
+      sc[kRowPhim * ld + b] = h.phim;
+      sc[kRowE * ld + b] = h.E;
       comp[b] = h.comp;
       nhop[b] = h.nhop;
       if (bad) cnt.nonfinite++;
@@ -359,8 +513,15 @@ static void launch_pg(const DevModel &md, const shgb_state &st, int nsteps, doub
                       hipStream_t stream) {
   constexpr int beams_per_block = kWavesPerBlock * PG<D, LPB>::G;
   const int64_t blocks = (st.n_beams + beams_per_block - 1) / beams_per_block;
-  hipLaunchKernelGGL((step_wave_kernel<D, LPB>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, stream, md,
-                     st.f64, st.comp, st.nhop, st.n_beams, st.ld, st.beam_id_offset, nsteps, dt, seed, diag);
+  double *sc = scalar_block(st);
+  if (mixed(st))
+    hipLaunchKernelGGL((step_wave_kernel<D, LPB, float>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
+                       stream, md, st.f32, sc, st.comp, st.nhop, st.n_beams, st.ld, st.beam_id_offset, nsteps, dt,
+                       seed, diag);
+  else
+    hipLaunchKernelGGL((step_wave_kernel<D, LPB, double>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
+                       stream, md, st.f64, sc, st.comp, st.nhop, st.n_beams, st.ld, st.beam_id_offset, nsteps, dt,
+                       seed, diag);
 }
 
 hipError_t launch_step_wave(const DevModel &md, const shgb_state &st, int nsteps, double dt, uint64_t seed,

@@ -22,6 +22,8 @@ SHGB_NCOMP = 4
 SHGB_MAX_D = 12
 SHGB_HOP_CAP = 16
 SHGB_NDIAG = 8
+SHGB_SCALAR_FIELDS = 8
+PRECISION = {"fp64": 0, "mixed": 1}
 DIST = {"normal": 0, "uniform": 1}
 DIAG_NAMES = ("hops", "thr_ties", "dest_ties", "cap_overflow", "nonfinite", "nonspd",
               "zero_rate", "bad_index")
@@ -43,7 +45,8 @@ class Model(ctypes.Structure):
 class StateDesc(ctypes.Structure):
     _fields_ = [("f64", ctypes.c_void_p), ("comp", ctypes.c_void_p), ("nhop", ctypes.c_void_p),
                 ("n_beams", ctypes.c_int64), ("ld", ctypes.c_int64),
-                ("beam_id_offset", ctypes.c_uint64), ("m", ctypes.c_int32)]
+                ("beam_id_offset", ctypes.c_uint64), ("m", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("f32", ctypes.c_void_p)]
 
 
 class InitSpec(ctypes.Structure):
@@ -103,8 +106,12 @@ def _ptr(t):
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
+def traj_fields(m):
+    return 2 * m + m * (m + 1)
+
+
 def nfields(m):
-    return 2 * m + m * (m + 1) + 8
+    return traj_fields(m) + SHGB_SCALAR_FIELDS
 
 
 def make_model(d, mass, eps, A, B, C, D, lam=0.0, bath_omega=()):
@@ -121,31 +128,48 @@ def make_init_spec(q_mean, q_std, p_dist, p_a, p_b, comp0):
 
 
 class State:
-    """Device beam state in the structure-of-arrays layout of include/shgb.h."""
+    """Device beam state in the structure-of-arrays layout of include/shgb.h.
 
-    def __init__(self, n, m, device="cuda", ld=None, beam_id_offset=0):
+    ``precision`` "fp64": one float64 block of nfields(m) rows; "mixed": the
+    trajectory rows (X, P, Zre, Zim) in a float32 block ``f32`` and the scalar
+    rows (S, A, logw, phase, Lam, E) in a float64 block ``f64``.
+    """
+
+    def __init__(self, n, m, device="cuda", ld=None, beam_id_offset=0, precision="fp64"):
         self.n, self.m = int(n), int(m)
         self.ld = int(ld) if ld is not None else max(self.n, 1)
         self.beam_id_offset = int(beam_id_offset)
-        self.f64 = torch.zeros((nfields(m), self.ld), dtype=torch.float64, device=device)
+        self.precision = precision
+        tf = traj_fields(m)
+        if precision == "fp64":
+            self.f64 = torch.zeros((nfields(m), self.ld), dtype=torch.float64, device=device)
+            self.f32 = None
+            self.traj, self.scal = self.f64[:tf], self.f64[tf:]
+        elif precision == "mixed":
+            self.f64 = torch.zeros((SHGB_SCALAR_FIELDS, self.ld), dtype=torch.float64, device=device)
+            self.f32 = torch.zeros((tf, self.ld), dtype=torch.float32, device=device)
+            self.traj, self.scal = self.f32, self.f64
+        else:
+            raise ValueError(f"precision must be 'fp64' or 'mixed', not {precision!r}")
         self.comp = torch.zeros(self.ld, dtype=torch.int32, device=device)
         self.nhop = torch.zeros(self.ld, dtype=torch.int32, device=device)  # uint32 in C
 
     def desc(self):
         return StateDesc(self.f64.data_ptr(), self.comp.data_ptr(), self.nhop.data_ptr(), self.n,
-                         self.ld, self.beam_id_offset, self.m)
+                         self.ld, self.beam_id_offset, self.m, PRECISION[self.precision],
+                         0 if self.f32 is None else self.f32.data_ptr())
 
-    # field rows
     @property
     def T(self):
         return self.m * (self.m + 1) // 2
 
-    def rows(self):
+    def traj_rows(self):
+        """Row slices of the trajectory block (``traj``)."""
         m, T = self.m, self.T
-        s = 2 * m + 2 * T
         return dict(X=slice(0, m), P=slice(m, 2 * m), Zre=slice(2 * m, 2 * m + T),
-                    Zim=slice(2 * m + T, s), S=s, Are=s + 1, Aim=s + 2, logw=s + 3, phre=s + 4,
-                    phim=s + 5, Lam=s + 6, E=s + 7)
+                    Zim=slice(2 * m + T, 2 * m + 2 * T))
+
+    SCALAR_ROWS = dict(S=0, Are=1, Aim=2, logw=3, phre=4, phim=5, Lam=6, E=7)
 
 
 def new_diag(device="cuda"):
@@ -228,45 +252,49 @@ def population_mean_se(sums, n_traj):
 
 
 def unpack(state):
-    """Host copy of the state as full matrices: dict of numpy arrays."""
+    """Host copy of the state as full matrices in float64: dict of numpy arrays."""
     import numpy as np
-    f = state.f64[:, : state.n].cpu().numpy()
-    r = state.rows()
-    m, n = state.m, state.n
+    n, m = state.n, state.m
+    t = state.traj[:, :n].double().cpu().numpy()
+    f = state.scal[:, :n].cpu().numpy()
+    r, c = state.traj_rows(), State.SCALAR_ROWS
     iu = np.triu_indices(m)
     Z = np.zeros((n, m, m), dtype=np.complex128)
-    Z[:, iu[0], iu[1]] = (f[r["Zre"]] + 1j * f[r["Zim"]]).T
-    Z[:, iu[1], iu[0]] = (f[r["Zre"]] + 1j * f[r["Zim"]]).T
-    return dict(X=f[r["X"]].T.copy(), P=f[r["P"]].T.copy(), Z=Z, S=f[r["S"]].copy(),
-                A=f[r["Are"]] + 1j * f[r["Aim"]], logw=f[r["logw"]].copy(),
-                phase=f[r["phre"]] + 1j * f[r["phim"]], Lam=f[r["Lam"]].copy(), E=f[r["E"]].copy(),
+    Z[:, iu[0], iu[1]] = (t[r["Zre"]] + 1j * t[r["Zim"]]).T
+    Z[:, iu[1], iu[0]] = (t[r["Zre"]] + 1j * t[r["Zim"]]).T
+    return dict(X=t[r["X"]].T.copy(), P=t[r["P"]].T.copy(), Z=Z, S=f[c["S"]].copy(),
+                A=f[c["Are"]] + 1j * f[c["Aim"]], logw=f[c["logw"]].copy(),
+                phase=f[c["phre"]] + 1j * f[c["phim"]], Lam=f[c["Lam"]].copy(), E=f[c["E"]].copy(),
                 comp=state.comp[:n].cpu().numpy().astype(np.int64),
                 nhop=state.nhop[:n].cpu().numpy().astype(np.int64) & 0xFFFFFFFF)
 
 
-def pack(arrays, device="cuda", beam_id_offset=0, ld=None):
-    """Device state from host arrays with the keys ``unpack`` returns."""
+def pack(arrays, device="cuda", beam_id_offset=0, ld=None, precision="fp64"):
+    """Device state from host arrays with the keys ``unpack`` returns (trajectory
+    values rounded to float32 for a mixed state)."""
     import numpy as np
     X = np.asarray(arrays["X"], dtype=np.float64)
     n, m = X.shape
-    st = State(n, m, device=device, ld=ld, beam_id_offset=beam_id_offset)
-    r = st.rows()
+    st = State(n, m, device=device, ld=ld, beam_id_offset=beam_id_offset, precision=precision)
+    r, c = st.traj_rows(), State.SCALAR_ROWS
     iu = np.triu_indices(m)
-    f = np.zeros((nfields(m), st.ld))
-    f[r["X"], :n] = X.T
-    f[r["P"], :n] = np.asarray(arrays["P"]).T
+    t = np.zeros((traj_fields(m), st.ld))
+    t[r["X"], :n] = X.T
+    t[r["P"], :n] = np.asarray(arrays["P"]).T
     Z = np.asarray(arrays["Z"])
-    f[r["Zre"], :n] = Z[:, iu[0], iu[1]].real.T
-    f[r["Zim"], :n] = Z[:, iu[0], iu[1]].imag.T
-    f[r["S"], :n] = arrays["S"]
-    f[r["Are"], :n] = np.real(arrays["A"])
-    f[r["Aim"], :n] = np.imag(arrays["A"])
-    f[r["logw"], :n] = arrays["logw"]
-    f[r["phre"], :n] = np.real(arrays["phase"])
-    f[r["phim"], :n] = np.imag(arrays["phase"])
-    f[r["Lam"], :n] = arrays["Lam"]
-    f[r["E"], :n] = arrays["E"]
-    st.f64.copy_(torch.from_numpy(f))
+    t[r["Zre"], :n] = Z[:, iu[0], iu[1]].real.T
+    t[r["Zim"], :n] = Z[:, iu[0], iu[1]].imag.T
+    f = np.zeros((SHGB_SCALAR_FIELDS, st.ld))
+    f[c["S"], :n] = arrays["S"]
+    f[c["Are"], :n] = np.real(arrays["A"])
+    f[c["Aim"], :n] = np.imag(arrays["A"])
+    f[c["logw"], :n] = arrays["logw"]
+    f[c["phre"], :n] = np.real(arrays["phase"])
+    f[c["phim"], :n] = np.imag(arrays["phase"])
+    f[c["Lam"], :n] = arrays["Lam"]
+    f[c["E"], :n] = arrays["E"]
+    st.traj.copy_(torch.from_numpy(t).to(st.traj.dtype))
+    st.scal.copy_(torch.from_numpy(f))
     st.comp[:n].copy_(torch.from_numpy(np.asarray(arrays["comp"], dtype=np.int32)))
     st.nhop[:n].copy_(torch.from_numpy(np.asarray(arrays["nhop"], dtype=np.int64).astype(np.uint32).view(np.int32)))
     return st

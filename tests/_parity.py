@@ -102,6 +102,14 @@ def compare_states(g, e, rtol=RTOL_FP64, min_ok=0.98, label=""):
         "E": blockrel(g["E"][ok], e.E[ok]),
         "phase": np.abs(g["phase"][ok] - e.phase[ok]).max(),
     }
-    bad = {k: v for k, v in errs.items() if not (v <= rtol)}
-    assert not bad, f"{label}: fields beyond {rtol}: {bad}"
+    m = e.X.shape[1]
+    if m > 2:   # per block of Z, for the message
+        d = m // 2
+        Zg, Ze = g["Z"][ok], (e.M + 1j * e.N)[ok]
+        for name, sl in (("Zrr", (slice(0, d), slice(0, d))), ("Zrp", (slice(0, d), slice(d, m))),
+                         ("Zpp", (slice(d, m), slice(d, m)))):
+            errs[name + "_abs"] = float(np.abs(Zg[:, sl[0], sl[1]] - Ze[:, sl[0], sl[1]]).max())
+            errs[name + "_max"] = float(np.abs(Ze[:, sl[0], sl[1]]).max())
+    bad = {k: v for k, v in errs.items() if not k.endswith(("_abs", "_max")) and not (v <= rtol)}
+    assert not bad, f"{label}: fields beyond {rtol}: {bad}; all: {errs}"
     return errs, int((~ok).sum())

@@ -174,10 +174,9 @@ def test_empty_and_degenerate(gpu):
     # forced hop at once: threshold 0 gives theta = 0 at the interval start
     st = gpu_init(gpu, c, 300)
     e = oracle_init(c, 300)
-    rows = st.rows()
-    st.f64[rows["E"], :300] = 0.0
+    st.scal[gpu.State.SCALAR_ROWS["E"], :300] = 0.0
     e.E[:] = 0.0
-    st.f64[rows["X"].start, :300] = 0.0       # q = 0: largest coupling
+    st.traj[st.traj_rows()["X"].start, :300] = 0.0       # q = 0: largest coupling
     e.X[:, 0] = 0.0
     gpu.step_ensemble(mdl, st, 3, c["dt"], c["seed"])
     oshgb.advance(oracle_model(c), e, 3, c["dt"], c["seed"])

@@ -1,0 +1,158 @@
+"""GPU parity of the mixed-precision path (FP32 trajectories, FP64 phase,
+rate integral, threshold and weights) against the FP64 oracle.
+
+The oracle receives exactly the values the GPU holds at the start: the
+seeded inputs with their trajectory fields rounded to float32.  Bar (the
+mixed-precision reading of the tie rule): hop counts and components equal
+apart from beams with an oracle-reported tie within 1e-5; continuous state
+within 1e-4 blockwise relative; populations, which are formed in FP64 from
+the stored values, within the FP64 bar; the m = 2 field, evaluated in FP32,
+within 1e-4 of the scale of its sum.  End to end, the mixed and the FP64
+GPU runs of one seeded ensemble give populations within one standard error.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import observables, shgb as oshgb
+from paper_1703_06116_amd import workloads
+
+from _parity import (arrays_from_ensemble, compare_states, ensemble_from_arrays, gpu_model, gpu_spec,
+                     oracle_init, oracle_model)
+
+pytestmark = pytest.mark.gpu
+
+RTOL_MIXED = 1e-4
+TRAJ = ("X", "P", "Z")
+
+
+def rounded(a):
+    """Host arrays with the trajectory fields rounded to float32 (what a mixed state stores)."""
+    out = dict(a)
+    out["X"] = np.asarray(a["X"]).astype(np.float32).astype(np.float64)
+    out["P"] = np.asarray(a["P"]).astype(np.float32).astype(np.float64)
+    Z = np.asarray(a["Z"])
+    out["Z"] = Z.real.astype(np.float32).astype(np.float64) + 1j * Z.imag.astype(np.float32).astype(np.float64)
+    return out
+
+
+def crossing(d, n, nsteps):
+    if d == 1:
+        return workloads.config("qcle1d_1e4", n_beams=n, nsteps=nsteps, q_mean=-2.5, q_std=0.3, p_a=30.0)
+    return workloads.config("qcle12d_2p18", d=d, bath_omega=workloads.bath_omega(d), n_beams=n, nsteps=nsteps,
+                            q_mean=-2.5, q_std=0.3, p_a=30.0)
+
+
+@pytest.mark.parametrize("d", [1, 12])
+def test_mixed_init_rounds_the_fp64_draws(gpu, d):
+    c = crossing(d, 2 * 256 + 7, 1)
+    n, m = c["n_beams"], 2 * d
+    st = gpu.State(n, m, beam_id_offset=31, precision="mixed")
+    gpu.init_beams(gpu_model(c), gpu_spec(c), st, c["seed"])
+    g = gpu.unpack(st)
+    e = oracle_init(c, n, 31)
+    # FP64 draws (agreeing with the oracle to ~1e-13) rounded once to float32
+    assert (np.abs(g["X"] - e.X) <= 2.0**-23 * np.abs(e.X) + 1e-300).all()
+    np.testing.assert_array_equal(g["Z"], e.M + 1j * e.N)
+    np.testing.assert_array_equal(g["A"], e.A)
+    np.testing.assert_allclose(g["E"], e.E, rtol=1e-14)
+    assert st.traj.dtype == torch.float32 and st.scal.dtype == torch.float64
+
+
+@pytest.mark.parametrize("d,n,nsteps", [(1, 2 * 256 + 91, 700), (2, 4 * 37 + 3, 600), (3, 4 * 29 + 1, 600),
+                                        (12, 4 * 33 + 2, 500)])
+def test_mixed_step_from_oracle_state(gpu, d, n, nsteps):
+    c = crossing(d, n, nsteps)
+    a0 = rounded(arrays_from_ensemble(oracle_init(c, n)))
+    st = gpu.pack(a0, precision="mixed")
+    diag = gpu.new_diag()
+    gpu.step_ensemble(gpu_model(c), st, nsteps, c["dt"], c["seed"], diag)
+    g = gpu.unpack(st)
+    e = ensemble_from_arrays(a0)
+    oshgb.advance(oracle_model(c), e, nsteps, c["dt"], c["seed"], tie_rel=oshgb.TIE_REL_MIXED)
+    errs, ties = compare_states(g, e, rtol=RTOL_MIXED, min_ok=0.9, label=f"mixed d={d}")
+    dg = diag.cpu().numpy()
+    assert dg[3] == 0 and dg[4] == 0 and e.nhop.sum() > n
+    print(f"mixed d={d}", errs, "tie beams", ties)
+
+
+def test_mixed_sharding_bitwise_and_resume_close(gpu):
+    """Sharding beams changes nothing; a call split rounds the stored state once more."""
+    c = crossing(1, 700, 300)
+    mdl = gpu_model(c)
+
+    def run(n, off, splits):
+        st = gpu.State(n, 2, precision="mixed", beam_id_offset=off)
+        gpu.init_beams(mdl, gpu_spec(c), st, c["seed"])
+        for k in splits:
+            gpu.step_ensemble(mdl, st, k, c["dt"], c["seed"])
+        return st
+
+    whole = run(700, 0, [300])
+    parts = [run(411, 0, [300]), run(289, 411, [300])]
+    for name in ("f32", "f64", "comp", "nhop"):
+        joined = torch.cat([getattr(parts[0], name)[..., :411], getattr(parts[1], name)[..., :289]], -1)
+        assert torch.equal(getattr(whole, name)[..., :700], joined), name
+    split = run(700, 0, [111, 189])
+    g1, g2 = gpu.unpack(whole), gpu.unpack(split)
+    same = (g1["nhop"] == g2["nhop"]) & (g1["comp"] == g2["comp"])
+    assert same.mean() > 0.99
+    for k in ("X", "P", "Z", "S", "Lam"):
+        a, b = g1[k][same], g2[k][same]
+        assert np.abs(a - b).max() <= 1e-5 * max(np.abs(a).max(), 1e-300), k
+
+
+@pytest.mark.parametrize("d,n", [(1, 4 * 64 + 5), (2, 257), (12, 3 * 64 + 9)])
+def test_mixed_populations_fp64_from_stored_values(gpu, d, n):
+    c = crossing(d, n, 1)
+    m = 2 * d
+    a = rounded(workloads.synthetic_ensemble(n, m, seed=n + d, a0=(2 * math.pi * c["eps"]) ** (-m / 2)))
+    out = gpu.populations(gpu_model(c), gpu.pack(a, precision="mixed")).cpu().numpy()
+    e = ensemble_from_arrays(a)
+    ref = observables.populations(e, c["eps"])
+    ci = observables.beam_integrals(e, c["eps"])
+    assert np.abs(out[:, :2] - ref[:, :2]).max() <= 1e-11 * np.abs(ci).sum()
+    assert np.abs(out[:, 2:4] - ref[:, 2:4]).max() <= 1e-11 * (np.abs(ci) ** 2).sum()
+    np.testing.assert_array_equal(out[:, 4], ref[:, 4])
+
+
+@pytest.mark.parametrize("d,n,Q,tol", [(1, 2 * 256 + 13, 300, RTOL_MIXED), (1, 1, 5, RTOL_MIXED),
+                                       (2, 70, 300, 1e-10), (12, 4 * 8 + 3, 700, 1e-10)])
+def test_mixed_reconstruct(gpu, d, n, Q, tol):
+    """m = 2: FP32 evaluation (bar 1e-4 of the sum of |terms|); m > 2: FP64 from the stored values."""
+    c = crossing(d, n, 1)
+    m = 2 * d
+    if d == 1:
+        a = workloads.synthetic_ensemble(n, 2, seed=5 + n, q_range=(5.0, 6.0), p_range=(10.0, 11.0), p_scale=0.3,
+                                         s_scale=30.0)
+    else:
+        a = workloads.synthetic_ensemble(n, m, seed=3 + n, q_range=(0.0, 2.0), p_range=(0.0, 2.0), p_scale=0.3)
+    a = rounded(a)
+    pts = workloads.points_near(a["X"], 0.5 * c["eps"], Q, seed=Q)
+    out = gpu.reconstruct(gpu_model(c), gpu.pack(a, precision="mixed"), torch.from_numpy(pts).cuda()).cpu().numpy()
+    e = ensemble_from_arrays(a)
+    ref = observables.reconstruct(e, c["eps"], pts)
+    scale = observables.reconstruct_abs(e, c["eps"], pts)
+    err = np.abs(out - ref) / (scale + 1e-300)
+    assert (err <= tol).all(), err.max()
+    assert np.abs(ref).max() > 0
+    print(f"mixed field d={d}: max error / scale {err.max():.3e}")
+
+
+def test_mixed_vs_fp64_populations_within_one_se(gpu):
+    """Equal population error: the same seeded ensemble stepped in FP64 and in mixed precision."""
+    c = workloads.config("qcle1d_1e4", n_beams=20_000, nsteps=1000)
+    mdl = gpu_model(c)
+    means = {}
+    for prec in ("fp64", "mixed"):
+        st = gpu.State(c["n_beams"], 2, precision=prec)
+        gpu.init_beams(mdl, gpu_spec(c), st, c["seed"])
+        gpu.step_ensemble(mdl, st, c["nsteps"], c["dt"], c["seed"])
+        means[prec] = gpu.population_mean_se(gpu.populations(mdl, st).cpu().numpy(), c["n_beams"])
+    (m64, se64), (mmx, semx) = means["fp64"], means["mixed"]
+    se = np.sqrt(np.abs(se64) ** 2 + np.abs(semx) ** 2)
+    assert (np.abs(mmx - m64) < se + 1e-300).all(), (mmx - m64, se)
+    assert abs(m64[1].real - 1.0) < 0.05

@@ -34,7 +34,8 @@ def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b(shgb_\w+)\s*\(", text, flags=re.M)
-    return sorted(set(n for n in names if n != "shgb_nfields"))   # shgb_nfields is static inline
+    inline = set(re.findall(r"^static inline [\w\s\*]*?\b(shgb_\w+)\s*\(", text, flags=re.M))
+    return sorted(set(names) - inline)   # static inline helpers are not exported
 
 
 def test_every_declared_function_is_exported(binding):
@@ -80,6 +81,16 @@ def test_validation_rejects_bad_arguments(binding):
     assert lib.shgb_step_ensemble(by(mdl), by(_desc(binding, m=4)), 1, 0.5, 1, nul, nul) == EINVAL
     assert lib.shgb_step_ensemble(by(mdl), by(_desc(binding, ld=3)), 1, 0.5, 1, nul, nul) == EINVAL
     assert lib.shgb_step_ensemble(by(mdl), by(_desc(binding, fake=0)), 1, 0.5, 1, nul, nul) == EINVAL
+    # unknown precision; a mixed state without its FP32 block
+    bad_prec = _desc(binding)
+    bad_prec.precision = 7
+    assert lib.shgb_step_ensemble(by(mdl), by(bad_prec), 1, 0.5, 1, nul, nul) == EINVAL
+    no_f32 = _desc(binding)
+    no_f32.precision = binding.PRECISION["mixed"]
+    for call in (lambda: lib.shgb_step_ensemble(by(mdl), by(no_f32), 1, 0.5, 1, nul, nul),
+                 lambda: lib.shgb_init_beams(by(mdl), by(spec), by(no_f32), 1, nul),
+                 lambda: lib.shgb_hop(by(mdl), by(no_f32), ctypes.c_void_p(0x10), 1, 1, nul, nul)):
+        assert call() == EINVAL
     # bad step parameters
     assert lib.shgb_step_ensemble(by(mdl), by(st), -1, 0.5, 1, nul, nul) == EINVAL
     assert lib.shgb_step_ensemble(by(mdl), by(st), 1, 0.0, 1, nul, nul) == EINVAL
