@@ -266,10 +266,12 @@ struct Counters {
 constexpr double kTieRel = 1e-12;
 constexpr double kTieRelMixed = 1e-5;
 
-__host__ __device__ inline void hop_event(const DevModel &md, double q1, double p1, HopScalars &h,
-                                 uint64_t gid, uint64_t seed, Counters &cnt, double tie_rel = kTieRel) {
-  const Q1 k = qcle_q1(md, q1);
-  const double kappa = p1 * md.inv_mass * k.d21;
+// The part of the hop that needs the coupling kappa = (p/M).d21 at the hop
+// state: destination, phase jump, component, hop count, next threshold.
+// The weight update (logw += Lam, Lam = 0) does not depend on kappa and is
+// left to the caller.
+__host__ __device__ inline void hop_choose(double kappa, HopScalars &h, uint64_t gid, uint64_t seed, Counters &cnt,
+                                           double tie_rel = kTieRel) {
   double col[SHGB_NCOMP];
   qcle_gamma_col(h.comp, kappa, col);
   const U64x4 w = draw(seed, gid, (uint64_t)h.nhop + 1u, kTagHop);
@@ -299,20 +301,44 @@ __host__ __device__ inline void hop_event(const DevModel &md, double q1, double 
   } else {
     cnt.zero_rate++;
   }
-  h.logw += h.Lam;
-  h.Lam = 0.0;
   h.comp = dest;
   h.nhop += 1u;
   h.E = -log(1.0 - Y);
   cnt.hops++;
 }
 
-// The hop event as an out-of-line call, for the stepping loops: hops are
-// rare, and an inlined event keeps its registers live across the loop.
-__host__ __device__ __attribute__((noinline)) inline void hop_event_call(const DevModel &md, double q1, double p1,
-                                                                         HopScalars &h, uint64_t gid, uint64_t seed,
-                                                                         Counters &cnt, double tie_rel) {
-  hop_event(md, q1, p1, h, gid, seed, cnt, tie_rel);
+// hop_choose as an out-of-line call, for a loop whose registers are too
+// tight to hold the draw inline (the call is made only when a beam hops).
+__host__ __device__ __attribute__((noinline)) inline void hop_choose_call(double kappa, HopScalars &h, uint64_t gid,
+                                                                          uint64_t seed, Counters &cnt,
+                                                                          double tie_rel) {
+  hop_choose(kappa, h, gid, seed, cnt, tie_rel);
+}
+
+// The whole hop event at phase-space point (q1, p1).
+__host__ __device__ inline void hop_event(const DevModel &md, double q1, double p1, HopScalars &h,
+                                 uint64_t gid, uint64_t seed, Counters &cnt, double tie_rel = kTieRel) {
+  const Q1 k = qcle_q1(md, q1);
+  h.logw += h.Lam;
+  h.Lam = 0.0;
+  hop_choose(p1 * md.inv_mass * k.d21, h, gid, seed, cnt, tie_rel);
+}
+
+// Hop state of one beam inside a stepping call.  A stepping loop starts a
+// hop where the threshold is reached (the weight update, which needs no
+// coupling) and completes it (hop_choose) where the coupling at the same
+// state is next evaluated: stage 0 of the following RK4 step.
+struct HopCtx {
+  HopScalars h;
+  bool pending;
+  uint64_t gid, seed;
+};
+
+__host__ __device__ inline void hop_start(HopCtx &hc, double &Lam) {
+  hc.h.logw += Lam;
+  Lam = 0.0;
+  hc.h.Lam = 0.0;
+  hc.pending = true;
 }
 
 // Wave-level sum of per-lane counters, one atomic per wave and counter.

@@ -10,7 +10,12 @@
 // The interval algorithm (Sec. 2.4 steps 3-5) runs one RK4 call site in a
 // loop: a trial over the rest of the interval, then, if Lam crosses the
 // threshold, the shortened step to the interpolated hop time, the hop, and a
-// new trial on the new component.
+// new trial on the new component.  The hop needs the coupling at the hop
+// state, which is exactly where the next RK4 step starts: its stage 0
+// evaluates the two-level quantities there anyway (they do not depend on
+// the component), so the hop is completed inside that stage.  The weight
+// update (logw += Lam, Lam = 0) is done at once; a hop still pending when
+// the call ends is completed before the state is stored.
 #include "device.h"
 
 namespace shgb {
@@ -23,11 +28,17 @@ struct Ode2 {
 // once into the accumulator and the next stage values,
 //   stage 0: acc = k;   stages 1, 2: acc += 2 k;   (ys = y0 + c k)
 //   stage 3: acc = y0 + h6 (acc + k)   (the step's result).
-__host__ __device__ inline void stage2(const DevModel &md, int l, const Ode2 &y0, Ode2 &ys, Ode2 &acc, int stage,
-                                       double c, double h6) {
+// Stage 0 first completes a pending hop at ys = y0.
+__host__ __device__ inline void stage2(const DevModel &md, HopCtx &hc, Counters &cnt, const Ode2 &y0, Ode2 &ys,
+                                       Ode2 &acc, int stage, double c, double h6) {
   const Q1 k = qcle_q1(md, ys.q);
-  const double sg = comp_sigma(l), bc = comp_bcoef(l);
   const double v = ys.p * md.inv_mass;
+  if (stage == 0 && hc.pending) {
+    hop_choose(v * k.d21, hc.h, hc.gid, hc.seed, cnt, kTieRel);
+    hc.pending = false;
+  }
+  const int l = hc.h.comp;
+  const double sg = comp_sigma(l), bc = comp_bcoef(l);
   const double E1 = sg * k.s1, E2 = sg * k.s2, E3 = sg * k.s3;
   const double b0 = bc * k.s, b1 = bc * k.s1, b2 = bc * k.s2;
   Ode2 d;
@@ -60,17 +71,26 @@ __host__ __device__ inline void stage2(const DevModel &md, int l, const Ode2 &y0
 #undef SHGB_ODE2_FIELDS
 }
 
-// One classical RK4 step of size h on component l, into out.
-__host__ __device__ inline void rk4_2(const DevModel &md, int l, const Ode2 &y, double h, Ode2 &out) {
+// One classical RK4 step of size h on the current component, into out.
+__host__ __device__ inline void rk4_2(const DevModel &md, HopCtx &hc, Counters &cnt, const Ode2 &y, double h,
+                                      Ode2 &out) {
   Ode2 ys = y;
   const double h6 = h / 6.0;
 #pragma unroll
-  for (int st = 0; st < 4; ++st) stage2(md, l, y, ys, out, st, st == 2 ? h : 0.5 * h, h6);
+  for (int st = 0; st < 4; ++st) stage2(md, hc, cnt, y, ys, out, st, st == 2 ? h : 0.5 * h, h6);
+}
+
+// Complete a hop still pending at the end of a call.
+__host__ __device__ inline void hop_finish(const DevModel &md, HopCtx &hc, double q, double p, Counters &cnt,
+                                           double tie_rel) {
+  if (!hc.pending) return;
+  const Q1 k = qcle_q1(md, q);
+  hop_choose(p * md.inv_mass * k.d21, hc.h, hc.gid, hc.seed, cnt, tie_rel);
+  hc.pending = false;
 }
 
 // One interval [t_n, t_n + dt] for one beam.
-__host__ __device__ inline void interval2(const DevModel &md, Ode2 &y, HopScalars &h, double dt,
-                                 uint64_t gid, uint64_t seed, Counters &cnt) {
+__host__ __device__ inline void interval2(const DevModel &md, Ode2 &y, HopCtx &hc, double dt, Counters &cnt) {
   double rem = dt;      // time left in the interval
   double hstep = dt;    // size of the next RK4 call
   double theta = 1.0;
@@ -78,16 +98,17 @@ __host__ __device__ inline void interval2(const DevModel &md, Ode2 &y, HopScalar
   int hops = 0;
   Ode2 yn;
   for (;;) {
-    rk4_2(md, h.comp, y, hstep, yn);
+    rk4_2(md, hc, cnt, y, hstep, yn);
+    const double E = hc.h.E;
     if (!partial) {
       const bool capped = hops >= SHGB_HOP_CAP;
-      if (!capped && fabs(yn.Lam - h.E) <= kTieRel * h.E) cnt.thr_ties++;
-      if (capped || !(yn.Lam >= h.E)) {  // no hop in the rest of the interval
+      if (!capped && fabs(yn.Lam - E) <= kTieRel * E) cnt.thr_ties++;
+      if (capped || !(yn.Lam >= E)) {  // no hop in the rest of the interval
         if (capped) cnt.cap++;
         y = yn;
         break;
       }
-      theta = (h.E <= y.Lam) ? 0.0 : (h.E - y.Lam) / (yn.Lam - y.Lam);
+      theta = (E <= y.Lam) ? 0.0 : (E - y.Lam) / (yn.Lam - y.Lam);
       if (theta > 0.0 && theta < 1.0) {
         partial = true;
         hstep = theta * rem;
@@ -98,9 +119,7 @@ __host__ __device__ inline void interval2(const DevModel &md, Ode2 &y, HopScalar
       y = yn;
       partial = false;
     }
-    h.Lam = y.Lam;
-    hop_event_call(md, y.q, y.p, h, gid, seed, cnt, kTieRel);
-    y.Lam = h.Lam;
+    hop_start(hc, y.Lam);
     ++hops;
     rem = rem * (1.0 - theta);
     if (!(rem > 0.0)) break;
@@ -108,9 +127,10 @@ __host__ __device__ inline void interval2(const DevModel &md, Ode2 &y, HopScalar
   }
 }
 
-// Three waves per SIMD: measured faster than the register-unconstrained
-// build (two waves) despite a few scratch spills.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+// Two waves per SIMD (197 registers, no spills): the state moves through
+// HBM exactly once each way.  A three-wave build spills to scratch, doubling
+// the traffic for a 2 % gain.
+__global__ void __launch_bounds__(256)
 step_m2_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
                uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps,
                double dt, uint64_t seed, uint64_t *diag) {
@@ -132,7 +152,8 @@ step_m2_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ sc, in
     y.zi22 = tr[L.Zim(2) * ld + b];
     y.S = sc[kRowS * ld + b];
     y.Lam = sc[kRowLam * ld + b];
-    HopScalars h;
+    HopCtx hc;
+    HopScalars &h = hc.h;
     h.logw = sc[kRowLogw * ld + b];
     h.phre = sc[kRowPhre * ld + b];
     h.phim = sc[kRowPhim * ld + b];
@@ -140,8 +161,11 @@ step_m2_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ sc, in
     h.comp = comp[b];
     h.nhop = nhop[b];
     h.Lam = y.Lam;
-    const uint64_t gid = gid0 + (uint64_t)b;
-    for (int s = 0; s < nsteps; ++s) interval2(md, y, h, dt, gid, seed, cnt);
+    hc.pending = false;
+    hc.gid = gid0 + (uint64_t)b;
+    hc.seed = seed;
+    for (int s = 0; s < nsteps; ++s) interval2(md, y, hc, dt, cnt);
+    hop_finish(md, hc, y.q, y.p, cnt, kTieRel);
     const double chk = y.q + y.p + y.Pq + y.Pp + y.zr11 + y.zr12 + y.zr22 + y.zi11 + y.zi12 +
                        y.zi22 + y.S + y.Lam + h.logw;
     if (!isfinite(chk)) cnt.nonfinite++;
@@ -169,7 +193,8 @@ step_m2_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ sc, in
 
 // ---------------------------------------------------------------------------
 // Mixed precision: the right-hand side of the ten trajectory values (X, P,
-// Z) is evaluated in FP32 at FP32 stage values; each step's increment
+// Z) is evaluated in FP32 at FP32 stage values (formed from the FP32
+// rounding of the step's start); each step's increment
 // h/6 (k1 + 2k2 + 2k3 + k4) is formed in FP32 and added to an FP64 copy of
 // the state that lives in registers for the whole call (adding small FP32
 // increments to FP32 values would lose their low bits step after step).
@@ -188,11 +213,16 @@ struct Inc2m {
   double S, Lam;
 };
 
-__host__ __device__ inline void stage2m(const QcleF &mf, int l, const Ode2 &y0, Traj2f &ys, Inc2m &acc, int stage,
-                                        double c, float h6, double h6d) {
+__host__ __device__ inline void stage2m(const QcleF &mf, HopCtx &hc, Counters &cnt, const Traj2f &y0, Traj2f &ys,
+                                        Inc2m &acc, int stage, float c, float h6, double h6d) {
   const Q1f k = qcle_q1f(mf, ys.q);
-  const float sg = (float)comp_sigma(l), bc = (float)comp_bcoef(l);
   const float v = ys.p * mf.inv_mass;
+  if (stage == 0 && hc.pending) {  // the coupling from the FP32 quantities; ties within 1e-5
+    hop_choose((double)(v * k.d21), hc.h, hc.gid, hc.seed, cnt, kTieRelMixed);
+    hc.pending = false;
+  }
+  const int l = hc.h.comp;
+  const float sg = (float)comp_sigma(l), bc = (float)comp_bcoef(l);
   const float E1 = sg * k.s1, E2 = sg * k.s2, E3 = sg * k.s3;
   const float b1 = bc * k.s1, b2 = bc * k.s2;
   Traj2f d;
@@ -210,13 +240,13 @@ __host__ __device__ inline void stage2m(const QcleF &mf, int l, const Ode2 &y0, 
   const double dLam = (double)(2.0f * fabsf(v * k.d21));
 #define SHGB_TRAJ2_FIELDS(F) F(q) F(p) F(Pq) F(Pp) F(zr11) F(zr12) F(zr22) F(zi11) F(zi12) F(zi22)
   if (stage == 0) {
-#define F(f) acc.t.f = d.f; ys.f = (float)(y0.f + c * (double)d.f);
+#define F(f) acc.t.f = d.f; ys.f = y0.f + c * d.f;
     SHGB_TRAJ2_FIELDS(F)
 #undef F
     acc.S = dS;
     acc.Lam = dLam;
   } else if (stage < 3) {
-#define F(f) acc.t.f = acc.t.f + 2.0f * d.f; ys.f = (float)(y0.f + c * (double)d.f);
+#define F(f) acc.t.f = acc.t.f + 2.0f * d.f; ys.f = y0.f + c * d.f;
     SHGB_TRAJ2_FIELDS(F)
 #undef F
     acc.S = acc.S + 2.0 * dS;
@@ -230,16 +260,19 @@ __host__ __device__ inline void stage2m(const QcleF &mf, int l, const Ode2 &y0, 
   }
 }
 
-// The increment of one classical RK4 step of size h on component l.
-__host__ __device__ inline void rk4_2m(const QcleF &mf, int l, const Ode2 &y, double h, Inc2m &inc) {
-  Traj2f ys;
-#define F(f) ys.f = (float)y.f;
+// The increment of one classical RK4 step of size h on component l.  The
+// stage values are formed in FP32 from the FP32 rounding of the step's start.
+__host__ __device__ inline void rk4_2m(const QcleF &mf, HopCtx &hc, Counters &cnt, const Ode2 &y, double h,
+                                       Inc2m &inc) {
+  Traj2f y0;
+#define F(f) y0.f = (float)y.f;
   SHGB_TRAJ2_FIELDS(F)
 #undef F
+  Traj2f ys = y0;
   const double h6d = h * (1.0 / 6.0);
-  const float h6 = (float)h6d;
+  const float h6 = (float)h6d, hf = (float)h;
 #pragma unroll
-  for (int st = 0; st < 4; ++st) stage2m(mf, l, y, ys, inc, st, st == 2 ? h : 0.5 * h, h6, h6d);
+  for (int st = 0; st < 4; ++st) stage2m(mf, hc, cnt, y0, ys, inc, st, st == 2 ? hf : 0.5f * hf, h6, h6d);
 }
 
 __host__ __device__ inline void add_inc2m(Ode2 &y, const Inc2m &inc) {
@@ -251,24 +284,24 @@ __host__ __device__ inline void add_inc2m(Ode2 &y, const Inc2m &inc) {
 }
 
 // The interval algorithm of interval2 on the mixed state.
-__host__ __device__ inline void interval2m(const DevModel &md, const QcleF &mf, Ode2 &y, HopScalars &h, double dt,
-                                           uint64_t gid, uint64_t seed, Counters &cnt) {
+__host__ __device__ inline void interval2m(const QcleF &mf, Ode2 &y, HopCtx &hc, double dt, Counters &cnt) {
   double rem = dt, hstep = dt, theta = 1.0;
   bool partial = false;
   int hops = 0;
   Inc2m inc;
   for (;;) {
-    rk4_2m(mf, h.comp, y, hstep, inc);
+    rk4_2m(mf, hc, cnt, y, hstep, inc);
+    const double E = hc.h.E;
     if (!partial) {
       const bool capped = hops >= SHGB_HOP_CAP;
       const double lam_n = y.Lam + inc.Lam;
-      if (!capped && fabs(lam_n - h.E) <= kTieRelMixed * h.E) cnt.thr_ties++;
-      if (capped || !(lam_n >= h.E)) {
+      if (!capped && fabs(lam_n - E) <= kTieRelMixed * E) cnt.thr_ties++;
+      if (capped || !(lam_n >= E)) {
         if (capped) cnt.cap++;
         add_inc2m(y, inc);
         break;
       }
-      theta = (h.E <= y.Lam) ? 0.0 : (h.E - y.Lam) / (lam_n - y.Lam);
+      theta = (E <= y.Lam) ? 0.0 : (E - y.Lam) / (lam_n - y.Lam);
       if (theta > 0.0 && theta < 1.0) {
         partial = true;
         hstep = theta * rem;
@@ -279,9 +312,7 @@ __host__ __device__ inline void interval2m(const DevModel &md, const QcleF &mf, 
       add_inc2m(y, inc);
       partial = false;
     }
-    h.Lam = y.Lam;
-    hop_event_call(md, y.q, y.p, h, gid, seed, cnt, kTieRelMixed);
-    y.Lam = h.Lam;
+    hop_start(hc, y.Lam);
     ++hops;
     rem = rem * (1.0 - theta);
     if (!(rem > 0.0)) break;
@@ -290,7 +321,7 @@ __host__ __device__ inline void interval2m(const DevModel &md, const QcleF &mf, 
 }
 #undef SHGB_TRAJ2_FIELDS
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 step_m2_mixed_kernel(DevModel md, float *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
                      uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps, double dt,
                      uint64_t seed, uint64_t *diag) {
@@ -312,7 +343,8 @@ step_m2_mixed_kernel(DevModel md, float *__restrict__ tr, double *__restrict__ s
     y.zi22 = tr[L.Zim(2) * ld + b];
     y.S = sc[kRowS * ld + b];
     y.Lam = sc[kRowLam * ld + b];
-    HopScalars h;
+    HopCtx hc;
+    HopScalars &h = hc.h;
     h.logw = sc[kRowLogw * ld + b];
     h.phre = sc[kRowPhre * ld + b];
     h.phim = sc[kRowPhim * ld + b];
@@ -320,8 +352,15 @@ step_m2_mixed_kernel(DevModel md, float *__restrict__ tr, double *__restrict__ s
     h.comp = comp[b];
     h.nhop = nhop[b];
     h.Lam = y.Lam;
-    const uint64_t gid = gid0 + (uint64_t)b;
-    for (int s = 0; s < nsteps; ++s) interval2m(md, mf, y, h, dt, gid, seed, cnt);
+    hc.pending = false;
+    hc.gid = gid0 + (uint64_t)b;
+    hc.seed = seed;
+    for (int s = 0; s < nsteps; ++s) interval2m(mf, y, hc, dt, cnt);
+    if (hc.pending) {  // FP32 coupling at the stored (rounded) state, as inside the loop
+      const Q1f k = qcle_q1f(mf, (float)y.q);
+      hop_choose((double)((float)y.p * mf.inv_mass * k.d21), h, hc.gid, hc.seed, cnt, kTieRelMixed);
+      hc.pending = false;
+    }
     const double chk = y.q + y.p + y.Pq + y.Pp + y.zr11 + y.zr12 + y.zr22 + y.zi11 + y.zi12 + y.zi22 + y.S +
                        y.Lam + h.logw;
     if (!isfinite(chk)) cnt.nonfinite++;

@@ -137,15 +137,24 @@ struct StageCoef {
   T sg, bc, H00, B00, lam, im;
 };
 
+// FP64: stage 0 first completes a pending hop at the stage values (the
+// step's start), from the coupling (p1/M) d21(q1) it evaluates anyway.  The
+// mixed kernel completes its hops where they start (see pg_interval).
 template <int D, typename T>
-__device__ inline StageCoef<T> stage_coef(const DevModel &md, const QcleF &mf, int l, const PgLds<D, T> &s) {
+__device__ inline StageCoef<T> stage_coef(const DevModel &md, const QcleF &mf, HopCtx &hc, Counters &cnt, int stage,
+                                          const PgLds<D, T> &s) {
   StageCoef<T> c;
   c.k = q1_eval(md, mf, s.x[0]);
+  c.im = (T)md.inv_mass;
+  if (sizeof(T) == sizeof(double) && stage == 0 && hc.pending) {
+    hop_choose((double)(s.x[D] * c.im * c.k.d21), hc.h, hc.gid, hc.seed, cnt, kTieRel);
+    hc.pending = false;
+  }
+  const int l = hc.h.comp;
   c.sg = (T)comp_sigma(l);
   c.bc = (T)comp_bcoef(l);
   c.H00 = c.sg * c.k.s2;
   c.lam = (T)md.lam;
-  c.im = (T)md.inv_mass;
   c.B00 = -s.p[D] * c.sg * c.k.s3 - c.bc * c.k.s2;
   return c;
 }
@@ -216,10 +225,11 @@ __device__ inline void xp_deriv(int cc, T kc, const StageCoef<T> &c, const PgLds
 //   stage 1, 2: acc += 2 k;      ys = y0 + c k
 //   stage 3: acc = y0 + h6 (acc + k)   (the step's result)
 template <int D, int LPB>
-__device__ inline void pg_stage(const DevModel &md, const QcleF &mf, int l, const PgCtx<D, LPB, double> &cx,
-                                const PgY<D, LPB, double> &y0, PgY<D, LPB, double> &ys, PgY<D, LPB, double> &acc,
-                                int stage, double c, double h6, const PgLds<D, double> &s) {
-  const StageCoef<double> sc = stage_coef<D, double>(md, mf, l, s);
+__device__ inline void pg_stage(const DevModel &md, const QcleF &mf, HopCtx &hc, Counters &cnt,
+                                const PgCtx<D, LPB, double> &cx, const PgY<D, LPB, double> &y0,
+                                PgY<D, LPB, double> &ys, PgY<D, LPB, double> &acc, int stage, double c, double h6,
+                                const PgLds<D, double> &s) {
+  const StageCoef<double> sc = stage_coef<D, double>(md, mf, hc, cnt, stage, s);
   auto fold = [&](double &a, double &yv, double y0v, double d) {
     if (stage == 0) a = d;
     else if (stage < 3) a = a + 2.0 * d;
@@ -247,16 +257,16 @@ __device__ inline void pg_stage(const DevModel &md, const QcleF &mf, int l, cons
 // One classical RK4 step of the group's beam on component l, into `out`;
 // `s` is clobbered.
 template <int D, int LPB>
-__device__ inline void pg_rk4(const DevModel &md, const QcleF &mf, int l, const PgCtx<D, LPB, double> &cx,
-                              const PgY<D, LPB, double> &y, double h, PgY<D, LPB, double> &out,
-                              PgLds<D, double> &s) {
+__device__ inline void pg_rk4(const DevModel &md, const QcleF &mf, HopCtx &hc, Counters &cnt,
+                              const PgCtx<D, LPB, double> &cx, const PgY<D, LPB, double> &y, double h,
+                              PgY<D, LPB, double> &out, PgLds<D, double> &s) {
   PgY<D, LPB, double> ys = y;
   const double h6 = h / 6.0;
   const double cs[3] = {0.5 * h, 0.5 * h, h};
 #pragma unroll 1
   for (int st = 0; st < 4; ++st) {
     pg_publish(cx, ys, s);
-    pg_stage(md, mf, l, cx, y, ys, out, st, st < 3 ? cs[st] : 0.0, h6, s);
+    pg_stage(md, mf, hc, cnt, cx, y, ys, out, st, st < 3 ? cs[st] : 0.0, h6, s);
     wave_lds_sync();
   }
 }
@@ -265,10 +275,11 @@ __device__ inline void pg_rk4(const DevModel &md, const QcleF &mf, int l, const 
 // leaves the step's increment h/6 (k1 + 2k2 + 2k3 + k4) in acc (FP32 for the
 // trajectory values, FP64 for S and Lam).
 template <int D, int LPB>
-__device__ inline void pg_stage_m(const DevModel &md, const QcleF &mf, int l, const PgCtx<D, LPB, float> &cx,
-                                  const PgY<D, LPB, double> &y0, PgY<D, LPB, float> &ys, PgY<D, LPB, float> &acc,
-                                  int stage, double c, float h6, double h6d, const PgLds<D, float> &s) {
-  const StageCoef<float> sc = stage_coef<D, float>(md, mf, l, s);
+__device__ inline void pg_stage_m(const DevModel &md, const QcleF &mf, HopCtx &hc, Counters &cnt,
+                                  const PgCtx<D, LPB, float> &cx, const PgY<D, LPB, double> &y0,
+                                  PgY<D, LPB, float> &ys, PgY<D, LPB, float> &acc, int stage, double c, float h6,
+                                  double h6d, const PgLds<D, float> &s) {
+  const StageCoef<float> sc = stage_coef<D, float>(md, mf, hc, cnt, stage, s);
   auto fold = [&](float &a, float &yv, double y0v, float d) {
     if (stage == 0) a = d;
     else if (stage < 3) a = a + 2.0f * d;
@@ -298,9 +309,9 @@ __device__ inline void pg_stage_m(const DevModel &md, const QcleF &mf, int l, co
 }
 
 template <int D, int LPB>
-__device__ inline void pg_rk4_m(const DevModel &md, const QcleF &mf, int l, const PgCtx<D, LPB, float> &cx,
-                                const PgY<D, LPB, double> &y, double h, PgY<D, LPB, float> &inc,
-                                PgLds<D, float> &s) {
+__device__ inline void pg_rk4_m(const DevModel &md, const QcleF &mf, HopCtx &hc, Counters &cnt,
+                                const PgCtx<D, LPB, float> &cx, const PgY<D, LPB, double> &y, double h,
+                                PgY<D, LPB, float> &inc, PgLds<D, float> &s) {
   PgY<D, LPB, float> ys;
 #pragma unroll
   for (int e = 0; e < PG<D, LPB>::NG; ++e)
@@ -314,7 +325,7 @@ __device__ inline void pg_rk4_m(const DevModel &md, const QcleF &mf, int l, cons
 #pragma unroll 1
   for (int st = 0; st < 4; ++st) {
     pg_publish(cx, ys, s);
-    pg_stage_m(md, mf, l, cx, y, ys, inc, st, st < 3 ? cs[st] : 0.0, h6, h6d, s);
+    pg_stage_m(md, mf, hc, cnt, cx, y, ys, inc, st, st < 3 ? cs[st] : 0.0, h6, h6d, s);
     wave_lds_sync();
   }
 }
@@ -333,12 +344,13 @@ __device__ inline void pg_add_inc(PgY<D, LPB, double> &y, const PgY<D, LPB, floa
 
 // One interval [t_n, t_n + dt] (Sec. 2.4 steps 3-5) for the group's beam: a
 // trial RK4 step; if Lam reaches the threshold, the step to the
-// interpolated hop time, the hop, and the rest of the interval.  MIXED
-// selects the mixed-precision step.
+// interpolated hop time, the hop (started here, completed in the next
+// stage 0), and the rest of the interval.  MIXED selects the
+// mixed-precision step.
 template <int D, int LPB, bool MIXED>
 __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const PgCtx<D, LPB, double> &cx,
-                                   const PgCtx<D, LPB, float> &cxf, int base, PgY<D, LPB, double> &y,
-                                   HopScalars &h, double dt, uint64_t gid, uint64_t seed, Counters &cnt, void *lds) {
+                                   const PgCtx<D, LPB, float> &cxf, int base, PgY<D, LPB, double> &y, HopCtx &hc,
+                                   double dt, Counters &cnt, void *lds) {
   const double tie_rel = MIXED ? kTieRelMixed : kTieRel;
   double rem = dt, hstep = dt, theta = 1.0;
   bool partial = false;
@@ -346,8 +358,8 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const Pg
   using YN = typename std::conditional<MIXED, PgY<D, LPB, float>, PgY<D, LPB, double>>::type;
   YN yn;  // FP64: the trial result; mixed: the trial increment
   auto trial = [&](double hh) {
-    if constexpr (MIXED) pg_rk4_m(md, mf, h.comp, cxf, y, hh, yn, *(PgLds<D, float> *)lds);
-    else pg_rk4(md, mf, h.comp, cx, y, hh, yn, *(PgLds<D, double> *)lds);
+    if constexpr (MIXED) pg_rk4_m(md, mf, hc, cnt, cxf, y, hh, yn, *(PgLds<D, float> *)lds);
+    else pg_rk4(md, mf, hc, cnt, cx, y, hh, yn, *(PgLds<D, double> *)lds);
   };
   auto accept = [&]() {
     if constexpr (MIXED) pg_add_inc(y, yn);
@@ -355,16 +367,17 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const Pg
   };
   for (;;) {
     trial(hstep);
+    const double E = hc.h.E;
     if (!partial) {
       const bool capped = hops >= SHGB_HOP_CAP;
       const double lam_n = MIXED ? y.Lam + yn.Lam : yn.Lam;
-      if (!capped && fabs(lam_n - h.E) <= tie_rel * h.E) cnt.thr_ties++;
-      if (capped || !(lam_n >= h.E)) {
+      if (!capped && fabs(lam_n - E) <= tie_rel * E) cnt.thr_ties++;
+      if (capped || !(lam_n >= E)) {
         if (capped) cnt.cap++;
         accept();
         break;
       }
-      theta = (h.E <= y.Lam) ? 0.0 : (h.E - y.Lam) / (lam_n - y.Lam);
+      theta = (E <= y.Lam) ? 0.0 : (E - y.Lam) / (lam_n - y.Lam);
       if (theta > 0.0 && theta < 1.0) {
         partial = true;
         hstep = theta * rem;
@@ -375,10 +388,13 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const Pg
       accept();
       partial = false;
     }
-    h.Lam = y.Lam;
-    const double q1 = __shfl(y.x, base, 64), p1 = __shfl(y.x, base + D, 64);
-    hop_event_call(md, q1, p1, h, gid, seed, cnt, tie_rel);
-    y.Lam = h.Lam;
+    hop_start(hc, y.Lam);
+    if constexpr (MIXED) {  // FP32 coupling at once, the draw and choice out of line (fewer spills)
+      const float q1 = (float)__shfl(y.x, base, 64), p1 = (float)__shfl(y.x, base + D, 64);
+      const Q1f k = qcle_q1f(mf, q1);
+      hop_choose_call((double)(p1 * mf.inv_mass * k.d21), hc.h, hc.gid, hc.seed, cnt, kTieRelMixed);
+      hc.pending = false;
+    }
     ++hops;
     rem = rem * (1.0 - theta);
     if (!(rem > 0.0)) break;
@@ -449,7 +465,8 @@ step_wave_kernel(DevModel md, TS *__restrict__ tr, double *__restrict__ sc, int3
     y.p = r < M ? (double)tr[L.P(r) * ld + b] : 0.0;
     y.S = sc[kRowS * ld + b];
     y.Lam = sc[kRowLam * ld + b];
-    HopScalars h;
+    HopCtx hc;
+    HopScalars &h = hc.h;
     h.logw = sc[kRowLogw * ld + b];
     h.phre = sc[kRowPhre * ld + b];
     h.phim = sc[kRowPhim * ld + b];
@@ -457,9 +474,24 @@ step_wave_kernel(DevModel md, TS *__restrict__ tr, double *__restrict__ sc, int3
     h.comp = comp[b];
     h.nhop = nhop[b];
     h.Lam = y.Lam;
-    const uint64_t gid = gid0 + (uint64_t)b;
+    hc.pending = false;
+    hc.gid = gid0 + (uint64_t)b;
+    hc.seed = seed;
     for (int st = 0; st < nsteps; ++st)
-      pg_interval<D, LPB, MIXED>(md, mf, cx, cxf, base, y, h, dt, gid, seed, cnt, (void *)&lds[slot]);
+      pg_interval<D, LPB, MIXED>(md, mf, cx, cxf, base, y, hc, dt, cnt, (void *)&lds[slot]);
+    // a hop still pending at the end of the call: its coupling at the state
+    // reached, in the stage precision as inside the loop
+    const double q1 = __shfl(y.x, base, 64), p1 = __shfl(y.x, base + D, 64);
+    if (hc.pending) {
+      if constexpr (MIXED) {
+        const Q1f k = qcle_q1f(mf, (float)q1);
+        hop_choose((double)((float)p1 * mf.inv_mass * k.d21), h, hc.gid, hc.seed, cnt, kTieRelMixed);
+      } else {
+        const Q1 k = qcle_q1(md, q1);
+        hop_choose(p1 * md.inv_mass * k.d21, h, hc.gid, hc.seed, cnt, kTieRel);
+      }
+      hc.pending = false;
+    }
     // finiteness of the values this lane owns (slots without a pair group
     // or coordinate hold no state)
     double chk = y.S + y.Lam + h.logw;
