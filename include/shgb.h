@@ -51,7 +51,8 @@ extern "C" {
 
 /* ---- fixed sizes -------------------------------------------------------- */
 #define SHGB_MODEL_QCLE 1
-#define SHGB_NCOMP 4      /* components of the QCLE system                    */
+#define SHGB_MODEL_LINQUAD 2
+#define SHGB_NCOMP 4      /* components (at most, for SHGB_MODEL_LINQUAD)     */
 #define SHGB_MAX_D 12     /* nuclear dimensions: phase space m = 2d <= 24     */
 #define SHGB_HOP_CAP 16   /* hops per beam per interval; later ones deferred  */
 
@@ -77,14 +78,37 @@ extern "C" {
  * adiabatic energies and coupling d21 by eq. (3.6); transport fields
  * alpha_l = (p/mass, -grad E_l), phases beta = (0, 0, E1-E2, E2-E1), couplings
  * gamma from (p/mass).d21 as in eq. (3.5).  eps is the semiclassical
- * parameter: it enters only the beam shape G, never the beam ODEs.       */
+ * parameter: it enters only the beam shape G, never the beam ODEs.
+ *
+ * Linear-quadratic systems (the class of Sec. 3.1, eq. (3.1) among them):
+ * x in R^2 (m = 2, d = 1), n_comp <= SHGB_NCOMP components with
+ *   alpha_l(x) = a_l + J_l x,   beta_l(x) = b0_l + b_l.x + x^T H_l x / 2,
+ *   gamma_jl constant complex,
+ * for which the beam ODEs of Sec. 2.3 are exact (no O(eps^1/2) residual).
+ * gamma_ll may be nonzero (then dA/dt = gamma_ll A); a hop from l goes to
+ * j != l with probability |gamma_jl| / sum_{k != l} |gamma_kl| and
+ * multiplies the phase by gamma_jl / |gamma_jl|.  With x-independent
+ * coefficients (a = J = b = H = 0) this is the system of Sec. 2.1.
+ * Stepping and hops of this kind are FP64 only.                           */
+typedef struct shgb_linquad {
+  int32_t n_comp;                          /* 1..SHGB_NCOMP                  */
+  double a[SHGB_NCOMP][2];
+  double J[SHGB_NCOMP][2][2];              /* J_l[i][k] = d alpha_l,i / d x_k */
+  double b0[SHGB_NCOMP];
+  double b[SHGB_NCOMP][2];
+  double H[SHGB_NCOMP][2][2];              /* symmetric                      */
+  double gamma_re[SHGB_NCOMP][SHGB_NCOMP]; /* [j][l]: from component l to j  */
+  double gamma_im[SHGB_NCOMP][SHGB_NCOMP];
+} shgb_linquad;
+
 typedef struct shgb_model {
-  int32_t kind;                       /* SHGB_MODEL_QCLE                    */
-  int32_t d;                          /* 1..SHGB_MAX_D                      */
-  double mass, eps;                   /* > 0                                */
-  double A, B, C, D;                  /* potential parameters (C != 0)      */
-  double lam;                         /* bath coupling (unused when d == 1) */
-  double bath_omega[SHGB_MAX_D - 1];  /* w_2..w_d (> 0), unused when d == 1  */
+  int32_t kind;                       /* SHGB_MODEL_QCLE or SHGB_MODEL_LINQUAD */
+  int32_t d;                          /* 1..SHGB_MAX_D (1 for LINQUAD)      */
+  double mass, eps;                   /* > 0 (mass unused by LINQUAD)       */
+  double A, B, C, D;                  /* QCLE potential parameters (C != 0) */
+  double lam;                         /* QCLE bath coupling (unused when d == 1) */
+  double bath_omega[SHGB_MAX_D - 1];  /* QCLE w_2..w_d (> 0), unused when d == 1 */
+  shgb_linquad lq;                    /* LINQUAD coefficients (unused by QCLE) */
 } shgb_model;
 
 /* ---- beam state --------------------------------------------------------
@@ -132,7 +156,8 @@ static inline int32_t shgb_nfields(int32_t m) { return shgb_traj_fields(m) + SHG
 
 /* ---- initial data -------------------------------------------------------
  * Sec. 2.5 and Sec. 2.4 step 2.  Beam shape M0 = I, N0 = 0, P0 = 0, S0 = 0,
- * A0 = (2 pi eps)^(-m/2) (each beam integrates to one), omega = 0, phase 1,
+ * A0 = a0, or (2 pi eps)^(-m/2) (each beam integrates to one) when a0 == 0,
+ * omega = 0, phase 1,
  * all beams on component comp0, a fresh threshold from draw 0.  Centres:
  *   q1 ~ N(q_mean, q_std^2);  p1 ~ N(p_a, p_b^2) or U[p_a, p_b);
  *   bath k >= 2: q_k ~ N(0, eps/(2 mass w_k)), p_k ~ N(0, eps mass w_k / 2)
@@ -141,7 +166,8 @@ typedef struct shgb_init_spec {
   double q_mean, q_std;
   int32_t p_dist;           /* SHGB_DIST_NORMAL or SHGB_DIST_UNIFORM */
   double p_a, p_b;
-  int32_t comp0;            /* 0..SHGB_NCOMP-1 */
+  int32_t comp0;            /* 0..n_comp-1 */
+  double a0;                /* initial amplitude; 0: (2 pi eps)^(-m/2) */
 } shgb_init_spec;
 
 /* Sample every beam of `st` (Sec. 2.5).  Errors: EINVAL for null pointers,

@@ -7,7 +7,10 @@
 #include "device.h"
 
 namespace shgb {
-hipError_t launch_init(const DevModel &, const shgb_init_spec &, const shgb_state &, uint64_t, hipStream_t);
+hipError_t launch_init(const DevModel &, const shgb_init_spec &, const shgb_state &, uint64_t, double, hipStream_t);
+hipError_t launch_step_lq(const DevLQ &, const shgb_state &, int, double, uint64_t, uint64_t *, hipStream_t);
+hipError_t launch_hop_lq(const DevLQ &, const shgb_state &, const int32_t *, int64_t, uint64_t, uint64_t *,
+                         hipStream_t);
 hipError_t launch_step_m2(const DevModel &, const shgb_state &, int, double, uint64_t, uint64_t *, hipStream_t);
 hipError_t launch_step_wave(const DevModel &, const shgb_state &, int, double, uint64_t, uint64_t *, hipStream_t);
 bool step_wave_supported(int d);
@@ -34,8 +37,65 @@ namespace {
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
-int to_dev_model(const shgb_model *m, DevModel &md) {
+bool all_finite(const double *v, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+// Linear-quadratic coefficients with the host-side hop constants.
+int to_dev_lq(const shgb_linquad &q, DevLQ &lq) {
+  if (q.n_comp < 1 || q.n_comp > SHGB_NCOMP) return SHGB_EINVAL;
+  std::memset(&lq, 0, sizeof(lq));
+  lq.n_comp = q.n_comp;
+  const int n = q.n_comp;
+  for (int l = 0; l < n; ++l) {
+    if (!all_finite(q.a[l], 2) || !all_finite(&q.J[l][0][0], 4) || !std::isfinite(q.b0[l]) ||
+        !all_finite(q.b[l], 2) || !all_finite(&q.H[l][0][0], 4) || q.H[l][0][1] != q.H[l][1][0])
+      return SHGB_EINVAL;
+    std::memcpy(lq.a[l], q.a[l], sizeof(lq.a[l]));
+    std::memcpy(lq.J[l], q.J[l], sizeof(lq.J[l]));
+    lq.b0[l] = q.b0[l];
+    std::memcpy(lq.b[l], q.b[l], sizeof(lq.b[l]));
+    std::memcpy(lq.H[l], q.H[l], sizeof(lq.H[l]));
+    for (int j = 0; j < n; ++j) {
+      const double gr = q.gamma_re[j][l], gi = q.gamma_im[j][l];
+      if (!std::isfinite(gr) || !std::isfinite(gi)) return SHGB_EINVAL;
+      const double r = std::hypot(gr, gi);
+      lq.absg[j][l] = r;
+      lq.ure[j][l] = r > 0.0 ? gr / r : 0.0;
+      lq.uim[j][l] = r > 0.0 ? gi / r : 0.0;
+    }
+    lq.gll_re[l] = q.gamma_re[l][l];
+    lq.gll_im[l] = q.gamma_im[l][l];
+    double R = 0.0, all = 0.0;
+    for (int j = 0; j < n; ++j) {
+      if (j != l) R = R + lq.absg[j][l];
+      all = all + lq.absg[j][l];
+    }
+    lq.hop_rate[l] = R;
+    lq.lam_rate[l] = all - lq.absg[l][l];
+  }
+  return SHGB_OK;
+}
+
+int to_dev_model(const shgb_model *m, DevModel &md, DevLQ *lq = nullptr) {
   if (!m) return SHGB_EINVAL;
+  if (m->kind == SHGB_MODEL_LINQUAD) {
+    if (m->d != 1 || !finite_pos(m->eps)) return SHGB_EINVAL;
+    std::memset(&md, 0, sizeof(md));
+    md.kind = SHGB_MODEL_LINQUAD;
+    md.n_comp = m->lq.n_comp;
+    md.mass = 1.0;
+    md.inv_mass = 1.0;
+    md.eps = m->eps;
+    md.d = 1;
+    DevLQ tmp;
+    const int rc = to_dev_lq(m->lq, tmp);
+    if (rc) return rc;
+    if (lq) *lq = tmp;
+    return SHGB_OK;
+  }
   if (m->kind != SHGB_MODEL_QCLE) return SHGB_EUNSUPPORTED;
   if (m->d < 1 || m->d > SHGB_MAX_D) return SHGB_EINVAL;
   if (!finite_pos(m->mass) || !finite_pos(m->eps)) return SHGB_EINVAL;
@@ -43,6 +103,8 @@ int to_dev_model(const shgb_model *m, DevModel &md) {
       !std::isfinite(m->lam) || m->C == 0.0)
     return SHGB_EINVAL;
   std::memset(&md, 0, sizeof(md));
+  md.kind = SHGB_MODEL_QCLE;
+  md.n_comp = SHGB_NCOMP;
   md.mass = m->mass;
   md.inv_mass = 1.0 / m->mass;
   md.eps = m->eps;
@@ -92,19 +154,25 @@ int shgb_init_beams(const shgb_model *model, const shgb_init_spec *spec, const s
   if ((rc = check_state(st, md))) return rc;
   if (!spec) return SHGB_EINVAL;
   if (!std::isfinite(spec->q_mean) || !(spec->q_std >= 0.0) || !std::isfinite(spec->p_a) ||
-      !std::isfinite(spec->p_b) || spec->comp0 < 0 || spec->comp0 >= SHGB_NCOMP)
+      !std::isfinite(spec->p_b) || spec->comp0 < 0 || spec->comp0 >= md.n_comp || !std::isfinite(spec->a0))
     return SHGB_EINVAL;
   if (spec->p_dist != SHGB_DIST_NORMAL && spec->p_dist != SHGB_DIST_UNIFORM) return SHGB_EINVAL;
-  return hip_status(launch_init(md, *spec, *st, seed, (hipStream_t)stream));
+  const double A0 = spec->a0 != 0.0 ? spec->a0 : std::pow(2.0 * M_PI * md.eps, -0.5 * st->m);
+  return hip_status(launch_init(md, *spec, *st, seed, A0, (hipStream_t)stream));
 }
 
 int shgb_step_ensemble(const shgb_model *model, const shgb_state *st, int32_t nsteps, double dt, uint64_t seed,
                        uint64_t *diag, void *stream) {
   DevModel md;
-  int rc = to_dev_model(model, md);
+  DevLQ lq;
+  int rc = to_dev_model(model, md, &lq);
   if (rc) return rc;
   if ((rc = check_state(st, md))) return rc;
   if (nsteps < 0 || !finite_pos(dt)) return SHGB_EINVAL;
+  if (md.kind == SHGB_MODEL_LINQUAD) {
+    if (st->precision != SHGB_FP64) return SHGB_EUNSUPPORTED;
+    return hip_status(launch_step_lq(lq, *st, nsteps, dt, seed, diag, (hipStream_t)stream));
+  }
   if (md.d == 1) return hip_status(launch_step_m2(md, *st, nsteps, dt, seed, diag, (hipStream_t)stream));
   if (!step_wave_supported(md.d)) return SHGB_EUNSUPPORTED;
   return hip_status(launch_step_wave(md, *st, nsteps, dt, seed, diag, (hipStream_t)stream));
@@ -113,10 +181,15 @@ int shgb_step_ensemble(const shgb_model *model, const shgb_state *st, int32_t ns
 int shgb_hop(const shgb_model *model, const shgb_state *st, const int32_t *idx, int64_t n_idx, uint64_t seed,
              uint64_t *diag, void *stream) {
   DevModel md;
-  int rc = to_dev_model(model, md);
+  DevLQ lq;
+  int rc = to_dev_model(model, md, &lq);
   if (rc) return rc;
   if ((rc = check_state(st, md))) return rc;
   if (n_idx < 0 || (n_idx > 0 && !idx)) return SHGB_EINVAL;
+  if (md.kind == SHGB_MODEL_LINQUAD) {
+    if (st->precision != SHGB_FP64) return SHGB_EUNSUPPORTED;
+    return hip_status(launch_hop_lq(lq, *st, idx, n_idx, seed, diag, (hipStream_t)stream));
+  }
   return hip_status(launch_hop(md, *st, idx, n_idx, seed, diag, (hipStream_t)stream));
 }
 

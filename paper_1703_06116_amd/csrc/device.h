@@ -18,6 +18,8 @@ struct DevModel {
   double bath_w[SHGB_MAX_D];  // w_k for bath modes k = 1..d-1 (index 0 unused)
   double bath_k[SHGB_MAX_D];  // mass * w_k^2
   int d;
+  int kind;                   // SHGB_MODEL_QCLE or SHGB_MODEL_LINQUAD
+  int n_comp;
 };
 
 // Row offsets of the structure-of-arrays state for phase-space dimension m.
@@ -322,6 +324,59 @@ __host__ __device__ inline void hop_event(const DevModel &md, double q1, double 
   h.logw += h.Lam;
   h.Lam = 0.0;
   hop_choose(p1 * md.inv_mass * k.d21, h, gid, seed, cnt, tie_rel);
+}
+
+// ---------------------------------------------------------------------------
+// Linear-quadratic model (m = 2) in kernel-argument form.  The constants of
+// the hop are formed once on the host: |gamma_jl| with the C library's
+// hypot, the unit phase factors gamma_jl / |gamma_jl|, the hop rate
+// sum_{j != l} |gamma_jl| summed in ascending j, and the rate integrand
+// d Lam / dt = (sum_j |gamma_jl|) - |gamma_ll|.
+struct DevLQ {
+  int n_comp;
+  double a[SHGB_NCOMP][2], J[SHGB_NCOMP][2][2], b0[SHGB_NCOMP], b[SHGB_NCOMP][2], H[SHGB_NCOMP][2][2];
+  double gll_re[SHGB_NCOMP], gll_im[SHGB_NCOMP];          // gamma_ll
+  double absg[SHGB_NCOMP][SHGB_NCOMP];                     // |gamma_jl|
+  double ure[SHGB_NCOMP][SHGB_NCOMP], uim[SHGB_NCOMP][SHGB_NCOMP];  // gamma_jl / |gamma_jl| (0 if gamma_jl = 0)
+  double hop_rate[SHGB_NCOMP];                             // sum_{j != l} |gamma_jl|, ascending j
+  double lam_rate[SHGB_NCOMP];                             // (sum_j |gamma_jl|) - |gamma_ll|
+};
+
+// Hop (Sec. 2.4 step 5) of a linear-quadratic beam: destination by the
+// inverse CDF of |gamma_jl| over j != l ascending, phase times
+// gamma_jl / |gamma_jl|, then the common updates.
+__host__ __device__ inline void hop_choose_lq(const DevLQ &lq, HopScalars &h, uint64_t gid, uint64_t seed,
+                                              Counters &cnt, double tie_rel = kTieRel) {
+  const U64x4 w = draw(seed, gid, (uint64_t)h.nhop + 1u, kTagHop);
+  const double U = u01(w.v[0]);
+  const double Y = u01(w.v[1]);
+  const int l = h.comp;
+  const double R = lq.hop_rate[l];
+  int dest = l;
+  if (R > 0.0) {
+    const double UR = U * R;
+    double C = 0.0;
+    int last_pos = l;
+    bool chosen = false;
+    for (int j = 0; j < lq.n_comp; ++j) {
+      if (j == l) continue;
+      C = C + lq.absg[j][l];
+      if (lq.absg[j][l] > 0.0) last_pos = j;
+      if (fabs(UR - C) <= tie_rel * R) cnt.dest_ties++;
+      if (!chosen && UR < C) { dest = j; chosen = true; }
+    }
+    if (!chosen) dest = last_pos;
+    const double ur = lq.ure[dest][l], ui = lq.uim[dest][l];
+    const double pr = h.phre, pi = h.phim;
+    h.phre = pr * ur - pi * ui;
+    h.phim = pr * ui + pi * ur;
+  } else {
+    cnt.zero_rate++;
+  }
+  h.comp = dest;
+  h.nhop += 1u;
+  h.E = -log(1.0 - Y);
+  cnt.hops++;
 }
 
 // Hop state of one beam inside a stepping call.  A stepping loop starts a

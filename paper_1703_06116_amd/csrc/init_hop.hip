@@ -63,11 +63,10 @@ init_kernel(DevModel md, shgb_init_spec spec, TS *__restrict__ tr, double *__res
 }
 
 hipError_t launch_init(const DevModel &md, const shgb_init_spec &spec, const shgb_state &st,
-                       uint64_t seed, hipStream_t stream) {
+                       uint64_t seed, double A0, hipStream_t stream) {
   if (st.n_beams == 0) return hipSuccess;
   const int threads = 256;
   const int64_t blocks = (st.n_beams + threads - 1) / threads;
-  const double A0 = pow(2.0 * M_PI * md.eps, -0.5 * st.m);
   double *sc = scalar_block(st);
   if (mixed(st))
     hipLaunchKernelGGL(init_kernel<float>, dim3((unsigned)blocks), dim3(threads), 0, stream, md, spec, st.f32, sc,

@@ -35,11 +35,21 @@ class ShgbError(RuntimeError):
         self.code = code
 
 
+_NC = SHGB_NCOMP
+
+
+class LinQuad(ctypes.Structure):
+    _fields_ = [("n_comp", ctypes.c_int32), ("a", (ctypes.c_double * 2) * _NC),
+                ("J", ((ctypes.c_double * 2) * 2) * _NC), ("b0", ctypes.c_double * _NC),
+                ("b", (ctypes.c_double * 2) * _NC), ("H", ((ctypes.c_double * 2) * 2) * _NC),
+                ("gamma_re", (ctypes.c_double * _NC) * _NC), ("gamma_im", (ctypes.c_double * _NC) * _NC)]
+
+
 class Model(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("d", ctypes.c_int32), ("mass", ctypes.c_double),
                 ("eps", ctypes.c_double), ("A", ctypes.c_double), ("B", ctypes.c_double),
                 ("C", ctypes.c_double), ("D", ctypes.c_double), ("lam", ctypes.c_double),
-                ("bath_omega", ctypes.c_double * (SHGB_MAX_D - 1))]
+                ("bath_omega", ctypes.c_double * (SHGB_MAX_D - 1)), ("lq", LinQuad)]
 
 
 class StateDesc(ctypes.Structure):
@@ -51,7 +61,8 @@ class StateDesc(ctypes.Structure):
 
 class InitSpec(ctypes.Structure):
     _fields_ = [("q_mean", ctypes.c_double), ("q_std", ctypes.c_double), ("p_dist", ctypes.c_int32),
-                ("p_a", ctypes.c_double), ("p_b", ctypes.c_double), ("comp0", ctypes.c_int32)]
+                ("p_a", ctypes.c_double), ("p_b", ctypes.c_double), ("comp0", ctypes.c_int32),
+                ("a0", ctypes.c_double)]
 
 
 def _load():
@@ -123,8 +134,33 @@ def make_model(d, mass, eps, A, B, C, D, lam=0.0, bath_omega=()):
     return mdl
 
 
-def make_init_spec(q_mean, q_std, p_dist, p_a, p_b, comp0):
-    return InitSpec(q_mean, q_std, DIST[p_dist], p_a, p_b, comp0)
+def make_linquad_model(eps, a, J, b0, b, H, gamma):
+    """A linear-quadratic model (m = 2): arrays of shapes (n, 2), (n, 2, 2), (n,), (n, 2),
+    (n, 2, 2) and gamma (n, n) complex with gamma[j, l] the rate from l to j."""
+    import numpy as np
+    a, J, b0, b, H = (np.asarray(v, dtype=np.float64) for v in (a, J, b0, b, H))
+    G = np.asarray(gamma, dtype=np.complex128)
+    n = a.shape[0]
+    mdl = Model()
+    mdl.kind, mdl.d, mdl.mass, mdl.eps = 2, 1, 1.0, float(eps)
+    q = mdl.lq
+    q.n_comp = n
+    for l in range(n):
+        q.b0[l] = b0[l]
+        for i in range(2):
+            q.a[l][i] = a[l, i]
+            q.b[l][i] = b[l, i]
+            for k in range(2):
+                q.J[l][i][k] = J[l, i, k]
+                q.H[l][i][k] = H[l, i, k]
+        for j in range(n):
+            q.gamma_re[j][l] = G[j, l].real
+            q.gamma_im[j][l] = G[j, l].imag
+    return mdl
+
+
+def make_init_spec(q_mean, q_std, p_dist, p_a, p_b, comp0, a0=0.0):
+    return InitSpec(q_mean, q_std, DIST[p_dist], p_a, p_b, comp0, a0)
 
 
 class State:

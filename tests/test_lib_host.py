@@ -91,6 +91,28 @@ def test_validation_rejects_bad_arguments(binding):
                  lambda: lib.shgb_init_beams(by(mdl), by(spec), by(no_f32), 1, nul),
                  lambda: lib.shgb_hop(by(mdl), by(no_f32), ctypes.c_void_p(0x10), 1, 1, nul, nul)):
         assert call() == EINVAL
+    # linear-quadratic models: component count, symmetric H, d == 1; FP64 stepping only
+    import numpy as np
+    good = dict(a=np.zeros((2, 2)), J=np.zeros((2, 2, 2)), b0=np.zeros(2), b=np.zeros((2, 2)),
+                H=np.zeros((2, 2, 2)), gamma=np.array([[-1.0, 0.5], [0.5, -1.0]]))
+    lq = binding.make_linquad_model(0.1, **good)
+    assert lib.shgb_step_ensemble(by(lq), by(_desc(binding, n=0)), 1, 0.5, 1, nul, nul) == 0
+    bad_h = dict(good, H=np.array([[[1.0, 2.0], [0.0, 1.0]], [[0.0, 0.0], [0.0, 0.0]]]))
+    assert lib.shgb_step_ensemble(by(binding.make_linquad_model(0.1, **bad_h)), by(st), 1, 0.5, 1, nul,
+                                  nul) == EINVAL
+    lq0 = binding.make_linquad_model(0.1, **good)
+    lq0.lq.n_comp = 0
+    assert lib.shgb_step_ensemble(by(lq0), by(st), 1, 0.5, 1, nul, nul) == EINVAL
+    lq3 = binding.make_linquad_model(0.1, **good)
+    lq3.d = 2
+    assert lib.shgb_step_ensemble(by(lq3), by(_desc(binding, m=4)), 1, 0.5, 1, nul, nul) == EINVAL
+    mixed_lq = _desc(binding)
+    mixed_lq.precision = binding.PRECISION["mixed"]
+    mixed_lq.f32 = 0x1000
+    assert lib.shgb_step_ensemble(by(lq), by(mixed_lq), 1, 0.5, 1, nul, nul) == EUNS
+    assert lib.shgb_hop(by(lq), by(mixed_lq), ctypes.c_void_p(0x10), 1, 1, nul, nul) == EUNS
+    spec3 = binding.make_init_spec(0, 1, "normal", 0, 1, 2)     # component 2 of a 2-component model
+    assert lib.shgb_init_beams(by(lq), by(spec3), by(st), 1, nul) == EINVAL
     # bad step parameters
     assert lib.shgb_step_ensemble(by(mdl), by(st), -1, 0.5, 1, nul, nul) == EINVAL
     assert lib.shgb_step_ensemble(by(mdl), by(st), 1, 0.0, 1, nul, nul) == EINVAL
