@@ -112,6 +112,107 @@ def cpu_baseline(c, n_beams, pts):
     }
 
 
+def run_batch(a):
+    """A batched workload: every instance initialised, advanced by one persistent launch
+    (launch shape from the autotuner) and reduced to populations, the whole sequence
+    captured once in a HIP graph and replayed; beside it, the same instances through the
+    plain FP64 path one instance at a time."""
+    import numpy as np
+    import torch
+    from paper_1703_06116_amd import autotune, shgb, workloads
+
+    cs = workloads.batch_instances(a.config)
+    torch.cuda.set_device(0)
+    dev = "cuda:0"
+    d, nsteps, dt = cs[0]["d"], cs[0]["nsteps"], cs[0]["dt"]
+    m = 2 * d
+    models = [shgb.make_model(c["d"], c["mass"], c["eps"], c["A"], c["B"], c["C"], c["D"], c["lam"], c["bath_omega"])
+              for c in cs]
+    specs = [shgb.make_init_spec(c["q_mean"], c["q_std"], c["p_dist"], c["p_a"], c["p_b"], c["comp0"]) for c in cs]
+    seeds = [c["seed"] for c in cs]
+    N = sum(c["n_beams"] for c in cs)
+
+    def make(precision):
+        sts = [shgb.State(c["n_beams"], m, device=dev, precision=precision) for c in cs]
+        pops = [torch.empty((4, 5), dtype=torch.float64, device=dev) for _ in cs]
+        works = [torch.empty(max(shgb.populations_workspace(c["n_beams"], m), 8), dtype=torch.uint8, device=dev)
+                 for c in cs]
+        return sts, pops, works
+
+    # mixed precision, batched
+    sts, pops, works = make("mixed")
+    for mdl, sp, st, sd in zip(models, specs, sts, seeds):
+        shgb.init_beams(mdl, sp, st, sd)
+    t_tune = time.perf_counter()
+    cfg, tune_ms = autotune.tune(models, sts, seeds, dt, probe_steps=10, repeats=1)
+    t_tune = time.perf_counter() - t_tune
+    batch = shgb.Batch(models, sts, seeds, config=cfg, device=dev)
+
+    def batched_step():
+        for mdl, sp, st, sd in zip(models, specs, sts, seeds):
+            shgb.init_beams(mdl, sp, st, sd)
+        batch.step(nsteps, dt)
+        for mdl, st, p, w in zip(models, sts, pops, works):
+            shgb.populations(mdl, st, out=p, work=w)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(max(a.warmup, 1)):
+            batched_step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batched_step()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for _ in range(a.steps):
+        graph.replay()
+    ev[1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / a.steps
+    graph_ms = ev[0].elapsed_time(ev[1]) / a.steps
+    mix = [shgb.population_mean_se(p.cpu().numpy(), c["n_beams"]) for p, c in zip(pops, cs)]
+    del graph, batch, sts, pops, works
+    torch.cuda.empty_cache()
+
+    # plain FP64 path, one instance at a time
+    sts64, pops64, works64 = make("fp64")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for mdl, sp, st, sd, p, w, c in zip(models, specs, sts64, seeds, pops64, works64, cs):
+        shgb.init_beams(mdl, sp, st, sd)
+        shgb.step_ensemble(mdl, st, nsteps, dt, sd)
+        shgb.populations(mdl, st, out=p, work=w)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    f64 = [shgb.population_mean_se(p.cpu().numpy(), c["n_beams"]) for p, c in zip(pops64, cs)]
+    worst = 0.0
+    for (mm, sm), (m6, s6) in zip(mix, f64):
+        se = np.sqrt(np.abs(sm) ** 2 + np.abs(s6) ** 2)
+        worst = max(worst, float((np.abs(mm - m6) / np.maximum(se, 1e-300)).max()))
+    value = N * nsteps / (ms_per_step / 1e3)
+    line = {
+        "metric": METRIC, "value": value, "unit": "beam-steps/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 trajectories + f64 phase/weights", "data": "synthetic",
+        "config": {"workload": a.config, "model": f"qcle-two-level-{d}d", "instances": len(cs), "n_beams": N,
+                   "intervals": nsteps, "dt": dt, "phase_space_dim": m, "parallelism": "none (1 GPU)"},
+        "graph_ms_per_step": graph_ms,
+        "launch_shape": {"waves_per_block": cfg[0], "blocks_per_cu": cfg[1], "tiles_per_grab": cfg[2]},
+        "autotune_s": t_tune, "autotune_ms": tune_ms,
+        "fp64_per_instance": {"value": N * nsteps / (t3 - t2), "ms_per_step": (t3 - t2) * 1e3,
+                              "unit": "beam-steps/s"},
+        "speedup_vs_fp64_per_instance": (t3 - t2) * 1e3 / ms_per_step,
+        "population_diff_over_se": worst,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.copy_probe:
@@ -126,6 +227,8 @@ def main():
     import torch
     from paper_1703_06116_amd import shgb, workloads
 
+    if a.config in workloads.BATCH:
+        return run_batch(a)
     c = workloads.config(a.config)
     N, nsteps, dt, seed, m = c["n_beams"], c["nsteps"], c["dt"], c["seed"], 2 * c["d"]
     if m not in (2, 24):

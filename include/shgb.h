@@ -223,12 +223,59 @@ int64_t shgb_reconstruct_workspace(int64_t n_beams, int32_t m, int64_t Q);
 int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double *points,
                      int64_t Q, double *out, void *work, int64_t work_bytes, void *stream);
 
+/* ---- batches: many instances in one persistent launch ------------------
+ * A batch is n_inst independent QCLE instances (model, state, seed) of one
+ * dimension d and one precision; models may differ in every parameter and
+ * states in size.  Each instance's beams are cut into tiles of one
+ * workgroup's worth; a fixed grid of workgroups takes tiles from a device
+ * queue until none is left, so uneven instance sizes and hop histories
+ * balance across the GPU.  Results are bitwise those of shgb_step_ensemble
+ * on each instance alone (the per-beam arithmetic is the same).
+ *
+ * Use: shgb_batch_prepare writes the instance table into host memory and
+ * fills `batch`; the caller copies the table to device memory (it must stay
+ * there while the batch is used), sets batch->table to that copy, and calls
+ * shgb_step_batched as often as wanted.  The launch sequence of
+ * shgb_step_batched (a queue reset kernel and the persistent kernel; no
+ * memset, no allocation, no synchronisation) can be captured in a HIP graph.
+ * Calls that share a work buffer must not overlap. */
+typedef struct shgb_batch_config {
+  int32_t waves_per_block;  /* 2 or 4; a tile is 64*w beams (m = 2), 2w (m = 24), 8w (m = 4, 6, 8) */
+  int32_t blocks_per_cu;    /* persistent workgroups per compute unit, 1..16 */
+  int32_t tiles_per_grab;   /* tiles taken from the queue at once, >= 1 */
+} shgb_batch_config;
+
+typedef struct shgb_batch {
+  int32_t n_inst, d, precision, kind;
+  int64_t total_tiles;
+  shgb_batch_config cfg;
+  const void *table;        /* device copy of the table (set by the caller) */
+} shgb_batch;
+
+#define SHGB_BATCH_WORK_BYTES 256  /* device work buffer of shgb_step_batched */
+
+/* bytes of the host table for n_inst instances (-1 if n_inst < 1) */
+int64_t shgb_batch_table_bytes(int32_t n_inst);
+/* Validate the instances (each as shgb_step_ensemble would) and write the
+ * table.  models, states, seeds: host arrays of n_inst.  Errors: EINVAL
+ * (bad instance, mixed d or precision, bad config, table too small),
+ * EUNSUPPORTED (a kind or d without a batched kernel). */
+int shgb_batch_prepare(const shgb_model *models, const shgb_state *states, const uint64_t *seeds,
+                       int32_t n_inst, const shgb_batch_config *cfg, void *host_table,
+                       int64_t table_bytes, shgb_batch *batch);
+/* Advance every instance of the batch by nsteps intervals of dt (the
+ * algorithm of shgb_step_ensemble).  work: device, >= SHGB_BATCH_WORK_BYTES.
+ * diag: counters summed over the batch.  Errors: EINVAL. */
+int shgb_step_batched(const shgb_batch *batch, int32_t nsteps, double dt, void *work, int64_t work_bytes,
+                      uint64_t *diag, void *stream);
+
 /* Diagnostic: the raw Philox4x64-10 blocks for n counters (device
  * uint64[4n] in and out) under key (seed, 0), as the kernels draw them. */
 int shgb_philox(uint64_t seed, const uint64_t *counters, uint64_t *out, int64_t n, void *stream);
 
-/* sizeof(shgb_model), sizeof(shgb_state), sizeof(shgb_init_spec) into sizes[0..2]
- * (host array), so bindings can check their struct layouts. */
+/* sizeof(shgb_model), sizeof(shgb_state), sizeof(shgb_init_spec),
+ * sizeof(shgb_batch_config), sizeof(shgb_batch) into sizes[0..4] (host
+ * array), so bindings can check their struct layouts. */
 void shgb_abi_sizes(int64_t *sizes);
 
 const char *shgb_strerror(int code);

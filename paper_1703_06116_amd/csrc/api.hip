@@ -4,7 +4,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "device.h"
+#include "batch.h"
 
 namespace shgb {
 hipError_t launch_init(const DevModel &, const shgb_init_spec &, const shgb_state &, uint64_t, double, hipStream_t);
@@ -27,6 +27,18 @@ bool recon_wave_supported(int m);
 hipError_t launch_recon_wave(const DevModel &, const shgb_state &, const double *, int64_t, double *, void *,
                              hipStream_t);
 int64_t recon_mfma_workspace_bytes(int64_t, int64_t);
+int wave_tile_beams(int d, int wpb);
+int m2_tile_beams(int wpb);
+hipError_t launch_step_wave_batched(int d, bool mixed_state, int wpb, const BatchItem *items, int n_items,
+                                    int64_t total_tiles, int grab, int blocks, int nsteps, double dt,
+                                    unsigned long long *queue, uint64_t *diag, hipStream_t stream);
+hipError_t launch_step_m2_batched(bool mixed_state, int wpb, const BatchItem *items, int n_items, int64_t total_tiles,
+                                  int grab, int blocks, int nsteps, double dt, unsigned long long *queue,
+                                  uint64_t *diag, hipStream_t stream);
+
+// Empty the work queue of a batched launch (a kernel, so that graph capture
+// records no memset).
+__global__ void batch_reset_kernel(unsigned long long *queue) { queue[0] = 0ull; }
 hipError_t launch_recon_mfma(const DevModel &, const shgb_state &, const double *, int64_t, double *, void *,
                              hipStream_t);
 }  // namespace shgb
@@ -238,6 +250,93 @@ int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double
   return hip_status(launch_recon_wave(md, *st, points, Q, out, work, (hipStream_t)stream));
 }
 
+int64_t shgb_batch_table_bytes(int32_t n_inst) {
+  if (n_inst < 1) return -1;
+  return (int64_t)n_inst * (int64_t)sizeof(BatchItem);
+}
+
+int shgb_batch_prepare(const shgb_model *models, const shgb_state *states, const uint64_t *seeds, int32_t n_inst,
+                       const shgb_batch_config *cfg, void *host_table, int64_t table_bytes, shgb_batch *batch) {
+  if (!models || !states || !seeds || !cfg || !host_table || !batch || n_inst < 1) return SHGB_EINVAL;
+  if (table_bytes < shgb_batch_table_bytes(n_inst)) return SHGB_EINVAL;
+  if ((cfg->waves_per_block != 2 && cfg->waves_per_block != 4) || cfg->blocks_per_cu < 1 ||
+      cfg->blocks_per_cu > 16 || cfg->tiles_per_grab < 1)
+    return SHGB_EINVAL;
+  BatchItem *items = (BatchItem *)host_table;
+  int64_t tiles = 0;
+  int d = 0, prec = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    DevModel md;
+    int rc = to_dev_model(&models[i], md);
+    if (rc) return rc;
+    if (md.kind != SHGB_MODEL_QCLE) return SHGB_EUNSUPPORTED;
+    if ((rc = check_state(&states[i], md))) return rc;
+    if (i == 0) {
+      d = md.d;
+      prec = states[i].precision;
+      if (d != 1 && !step_wave_supported(d)) return SHGB_EUNSUPPORTED;
+    } else if (md.d != d || states[i].precision != prec) {
+      return SHGB_EINVAL;
+    }
+    const int64_t tb = d == 1 ? m2_tile_beams(cfg->waves_per_block) : wave_tile_beams(d, cfg->waves_per_block);
+    BatchItem &it = items[i];
+    std::memset(&it, 0, sizeof(it));
+    it.md = md;
+    it.tr = prec == SHGB_MIXED ? (void *)states[i].f32 : (void *)states[i].f64;
+    it.sc = scalar_block(states[i]);
+    it.comp = states[i].comp;
+    it.nhop = states[i].nhop;
+    it.n = states[i].n_beams;
+    it.ld = states[i].ld;
+    it.gid0 = states[i].beam_id_offset;
+    it.seed = seeds[i];
+    it.tile0 = tiles;
+    it.tiles = (it.n + tb - 1) / tb;
+    tiles += it.tiles;
+  }
+  batch->n_inst = n_inst;
+  batch->d = d;
+  batch->precision = prec;
+  batch->kind = SHGB_MODEL_QCLE;
+  batch->total_tiles = tiles;
+  batch->cfg = *cfg;
+  batch->table = nullptr;
+  return SHGB_OK;
+}
+
+int shgb_step_batched(const shgb_batch *batch, int32_t nsteps, double dt, void *work, int64_t work_bytes,
+                      uint64_t *diag, void *stream) {
+  if (!batch || batch->n_inst < 1 || nsteps < 0 || !finite_pos(dt)) return SHGB_EINVAL;
+  if (!work || work_bytes < SHGB_BATCH_WORK_BYTES) return SHGB_EINVAL;
+  const shgb_batch_config &cfg = batch->cfg;
+  if ((cfg.waves_per_block != 2 && cfg.waves_per_block != 4) || cfg.blocks_per_cu < 1 || cfg.blocks_per_cu > 16 ||
+      cfg.tiles_per_grab < 1 || batch->total_tiles < 0)
+    return SHGB_EINVAL;
+  if (batch->kind != SHGB_MODEL_QCLE || batch->d < 1 || batch->d > SHGB_MAX_D ||
+      (batch->precision != SHGB_FP64 && batch->precision != SHGB_MIXED))
+    return SHGB_EINVAL;
+  if (batch->total_tiles == 0 || nsteps == 0) return SHGB_OK;
+  if (!batch->table) return SHGB_EINVAL;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return SHGB_EHIP;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long *queue = (unsigned long long *)work;
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, s, queue);
+  const int blocks = cus * cfg.blocks_per_cu;
+  const bool mx = batch->precision == SHGB_MIXED;
+  const BatchItem *items = (const BatchItem *)batch->table;
+  hipError_t e;
+  if (batch->d == 1)
+    e = launch_step_m2_batched(mx, cfg.waves_per_block, items, batch->n_inst, batch->total_tiles, cfg.tiles_per_grab,
+                               blocks, nsteps, dt, queue, diag, s);
+  else
+    e = launch_step_wave_batched(batch->d, mx, cfg.waves_per_block, items, batch->n_inst, batch->total_tiles,
+                                 cfg.tiles_per_grab, blocks, nsteps, dt, queue, diag, s);
+  return hip_status(e);
+}
+
 int shgb_philox(uint64_t seed, const uint64_t *counters, uint64_t *out, int64_t n, void *stream) {
   if (n < 0 || (n > 0 && (!counters || !out))) return SHGB_EINVAL;
   return hip_status(launch_philox(seed, counters, out, n, (hipStream_t)stream));
@@ -261,6 +360,8 @@ void shgb_abi_sizes(int64_t *sizes) {
   sizes[0] = (int64_t)sizeof(shgb_model);
   sizes[1] = (int64_t)sizeof(shgb_state);
   sizes[2] = (int64_t)sizeof(shgb_init_spec);
+  sizes[3] = (int64_t)sizeof(shgb_batch_config);
+  sizes[4] = (int64_t)sizeof(shgb_batch);
 }
 
 }  // extern "C"

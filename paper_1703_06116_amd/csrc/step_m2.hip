@@ -16,7 +16,7 @@
 // the component), so the hop is completed inside that stage.  The weight
 // update (logw += Lam, Lam = 0) is done at once; a hop still pending when
 // the call ends is completed before the state is stored.
-#include "device.h"
+#include "batch.h"
 
 namespace shgb {
 
@@ -127,18 +127,12 @@ __host__ __device__ inline void interval2(const DevModel &md, Ode2 &y, HopCtx &h
   }
 }
 
-// Two waves per SIMD (197 registers, no spills): the state moves through
-// HBM exactly once each way.  A three-wave build spills to scratch, doubling
-// the traffic for a 2 % gain.
-__global__ void __launch_bounds__(256)
-step_m2_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
-               uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps,
-               double dt, uint64_t seed, uint64_t *diag) {
+// All nsteps intervals of beam b (one thread), FP64.
+__device__ inline void m2_beam(const DevModel &md, double *__restrict__ tr, double *__restrict__ sc,
+                               int32_t *__restrict__ comp, uint32_t *__restrict__ nhop, int64_t n, int64_t ld,
+                               uint64_t gid0, int nsteps, double dt, uint64_t seed, int64_t b, Counters &cnt) {
   const Layout L(2, ld);
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = b < n;
-  Counters cnt;
-  if (live) {
+  if (b < n) {
     Ode2 y;
     y.q = tr[L.X(0) * ld + b];
     y.p = tr[L.X(1) * ld + b];
@@ -188,6 +182,18 @@ step_m2_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ sc, in
     comp[b] = h.comp;
     nhop[b] = h.nhop;
   }
+}
+
+// Two waves per SIMD (197 registers, no spills): the state moves through
+// HBM exactly once each way.  A three-wave build spills to scratch, doubling
+// the traffic for a 2 % gain.
+__global__ void __launch_bounds__(256)
+step_m2_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
+               uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps,
+               double dt, uint64_t seed, uint64_t *diag) {
+  Counters cnt;
+  m2_beam(md, tr, sc, comp, nhop, n, ld, gid0, nsteps, dt, seed, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+          cnt);
   flush_counters(cnt, diag);
 }
 
@@ -321,13 +327,11 @@ __host__ __device__ inline void interval2m(const QcleF &mf, Ode2 &y, HopCtx &hc,
 }
 #undef SHGB_TRAJ2_FIELDS
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-step_m2_mixed_kernel(DevModel md, float *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
-                     uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps, double dt,
-                     uint64_t seed, uint64_t *diag) {
+// All nsteps intervals of beam b (one thread), mixed precision.
+__device__ inline void m2m_beam(const DevModel &md, float *__restrict__ tr, double *__restrict__ sc,
+                                int32_t *__restrict__ comp, uint32_t *__restrict__ nhop, int64_t n, int64_t ld,
+                                uint64_t gid0, int nsteps, double dt, uint64_t seed, int64_t b, Counters &cnt) {
   const Layout L(2, ld);
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  Counters cnt;
   if (b < n) {
     const QcleF mf = qcle_f32(md);
     Ode2 y;
@@ -383,7 +387,76 @@ step_m2_mixed_kernel(DevModel md, float *__restrict__ tr, double *__restrict__ s
     comp[b] = h.comp;
     nhop[b] = h.nhop;
   }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+step_m2_mixed_kernel(DevModel md, float *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
+                     uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps, double dt,
+                     uint64_t seed, uint64_t *diag) {
+  Counters cnt;
+  m2m_beam(md, tr, sc, comp, nhop, n, ld, gid0, nsteps, dt, seed, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+           cnt);
   flush_counters(cnt, diag);
+}
+
+// Persistent form for a batch: each workgroup takes tiles of TPB beams from
+// the queue until none is left; the tile decides the instance.
+template <int TPB>
+__global__ void __launch_bounds__(TPB)
+step_m2_batched(const BatchItem *__restrict__ items, int n_items, int64_t total_tiles, int grab, int nsteps,
+                double dt, unsigned long long *queue, uint64_t *diag) {
+  Counters cnt;
+  for (;;) {
+    const int64_t t0 = batch_grab(queue, grab);
+    if (t0 >= total_tiles) break;
+    const int64_t t1 = t0 + grab < total_tiles ? t0 + grab : total_tiles;
+    for (int64_t t = t0; t < t1; ++t) {
+      const BatchItem &it = items[batch_find(items, n_items, t)];
+      m2_beam(it.md, (double *)it.tr, it.sc, it.comp, it.nhop, it.n, it.ld, it.gid0, nsteps, dt, it.seed,
+              (t - it.tile0) * TPB + threadIdx.x, cnt);
+    }
+  }
+  flush_counters(cnt, diag);
+}
+
+template <int TPB>
+__global__ void __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3)))
+step_m2_mixed_batched(const BatchItem *__restrict__ items, int n_items, int64_t total_tiles, int grab, int nsteps,
+                      double dt, unsigned long long *queue, uint64_t *diag) {
+  Counters cnt;
+  for (;;) {
+    const int64_t t0 = batch_grab(queue, grab);
+    if (t0 >= total_tiles) break;
+    const int64_t t1 = t0 + grab < total_tiles ? t0 + grab : total_tiles;
+    for (int64_t t = t0; t < t1; ++t) {
+      const BatchItem &it = items[batch_find(items, n_items, t)];
+      m2m_beam(it.md, (float *)it.tr, it.sc, it.comp, it.nhop, it.n, it.ld, it.gid0, nsteps, dt, it.seed,
+               (t - it.tile0) * TPB + threadIdx.x, cnt);
+    }
+  }
+  flush_counters(cnt, diag);
+}
+
+// beams per tile of the batched m = 2 kernels
+int m2_tile_beams(int wpb) { return 64 * wpb; }
+
+hipError_t launch_step_m2_batched(bool mixed_state, int wpb, const BatchItem *items, int n_items, int64_t total_tiles,
+                                  int grab, int blocks, int nsteps, double dt, unsigned long long *queue,
+                                  uint64_t *diag, hipStream_t stream) {
+#define SHGB_M2B(TPB)                                                                                         \
+  if (mixed_state)                                                                                            \
+    hipLaunchKernelGGL(step_m2_mixed_batched<TPB>, dim3(blocks), dim3(TPB), 0, stream, items, n_items,        \
+                       total_tiles, grab, nsteps, dt, queue, diag);                                          \
+  else                                                                                                        \
+    hipLaunchKernelGGL(step_m2_batched<TPB>, dim3(blocks), dim3(TPB), 0, stream, items, n_items, total_tiles, \
+                       grab, nsteps, dt, queue, diag);
+  if (wpb == 2) {
+    SHGB_M2B(128)
+  } else {
+    SHGB_M2B(256)
+  }
+#undef SHGB_M2B
+  return hipGetLastError();
 }
 
 hipError_t launch_step_m2(const DevModel &md, const shgb_state &st, int nsteps, double dt,

@@ -29,7 +29,7 @@
 // area too), each step's increment is formed in FP32 and added to an FP64
 // copy of the state held in registers for the whole call; S and Lam are
 // FP64 as in the FP64 path.
-#include "device.h"
+#include "batch.h"
 
 namespace shgb {
 
@@ -408,22 +408,22 @@ constexpr int kWavesPerBlock = 4;
 #endif
 constexpr int kLanesPerBeamD12 = SHGB_D12_LANES_PER_BEAM;  // 32: two beams per wavefront
 
-// TS: element type of the stored trajectory rows (double: FP64 path, float:
-// mixed path).  The register copy of the state is FP64 in both.
-template <int D, int LPB, typename TS>
-__global__ void __launch_bounds__(64 * kWavesPerBlock)
-__attribute__((amdgpu_waves_per_eu(sizeof(TS) == sizeof(float) ? 2 : 1)))
-step_wave_kernel(DevModel md, TS *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
-                 uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps, double dt,
-                 uint64_t seed, uint64_t *diag) {
+// All nsteps intervals of the beams of one tile (WPB waves, 64/LPB beams
+// per wave).  TS: element type of the stored trajectory rows (double: FP64
+// path, float: mixed path); the register copy of the state is FP64 in both.
+// The group's replicated counts are added to cnt by its lane 0 only.
+template <int D, int LPB, typename TS, int WPB>
+__device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double *__restrict__ sc,
+                                 int32_t *__restrict__ comp, uint32_t *__restrict__ nhop, int64_t n, int64_t ld,
+                                 uint64_t gid0, int nsteps, double dt, uint64_t seed, int64_t tile,
+                                 PgLds<D, TS> *lds, Counters &cnt_out) {
   using C = PG<D, LPB>;
   constexpr int M = C::M;
   constexpr bool MIXED = sizeof(TS) == sizeof(float);
-  __shared__ PgLds<D, TS> lds[kWavesPerBlock * C::G];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int grp = lane / LPB, r = lane % LPB, base = grp * LPB;
   const int slot = wid * C::G + grp;
-  const int64_t b = (int64_t)blockIdx.x * (kWavesPerBlock * C::G) + slot;
+  const int64_t b = tile * (WPB * C::G) + slot;
   Counters cnt;
   if (b < n) {  // uniform across the beam's lanes
     const Layout L(M, ld);
@@ -531,8 +531,46 @@ step_wave_kernel(DevModel md, TS *__restrict__ tr, double *__restrict__ sc, int3
       comp[b] = h.comp;
       nhop[b] = h.nhop;
       if (bad) cnt.nonfinite++;
-    } else {
-      cnt = Counters();  // the group's replicated counts are reported by its lane 0
+      cnt_out.hops += cnt.hops;
+      cnt_out.thr_ties += cnt.thr_ties;
+      cnt_out.dest_ties += cnt.dest_ties;
+      cnt_out.cap += cnt.cap;
+      cnt_out.zero_rate += cnt.zero_rate;
+      cnt_out.nonfinite += cnt.nonfinite;
+    }
+  }
+}
+
+template <int D, int LPB, typename TS>
+__global__ void __launch_bounds__(64 * kWavesPerBlock)
+__attribute__((amdgpu_waves_per_eu(sizeof(TS) == sizeof(float) ? 2 : 1)))
+step_wave_kernel(DevModel md, TS *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
+                 uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps, double dt,
+                 uint64_t seed, uint64_t *diag) {
+  __shared__ PgLds<D, TS> lds[kWavesPerBlock * PG<D, LPB>::G];
+  Counters cnt;
+  wave_tile<D, LPB, TS, kWavesPerBlock>(md, tr, sc, comp, nhop, n, ld, gid0, nsteps, dt, seed, blockIdx.x, lds, cnt);
+  flush_counters(cnt, diag);
+}
+
+// Persistent form for a batch: each workgroup takes tiles from the queue
+// until none is left; the tile decides the instance (model and state).
+template <int D, int LPB, typename TS, int WPB>
+__global__ void __launch_bounds__(64 * WPB)
+__attribute__((amdgpu_waves_per_eu(sizeof(TS) == sizeof(float) ? 2 : 1)))
+step_wave_batched(const BatchItem *__restrict__ items, int n_items, int64_t total_tiles, int grab, int nsteps,
+                  double dt, unsigned long long *queue, uint64_t *diag) {
+  __shared__ PgLds<D, TS> lds[WPB * PG<D, LPB>::G];
+  Counters cnt;
+  for (;;) {
+    const int64_t t0 = batch_grab(queue, grab);
+    if (t0 >= total_tiles) break;
+    const int64_t t1 = t0 + grab < total_tiles ? t0 + grab : total_tiles;
+    for (int64_t t = t0; t < t1; ++t) {
+      const BatchItem &it = items[batch_find(items, n_items, t)];
+      wave_tile<D, LPB, TS, WPB>(it.md, (TS *)it.tr, it.sc, it.comp, it.nhop, it.n, it.ld, it.gid0, nsteps, dt,
+                                 it.seed, t - it.tile0, lds, cnt);
+      __syncthreads();
     }
   }
   flush_counters(cnt, diag);
@@ -554,6 +592,42 @@ static void launch_pg(const DevModel &md, const shgb_state &st, int nsteps, doub
     hipLaunchKernelGGL((step_wave_kernel<D, LPB, double>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
                        stream, md, st.f64, sc, st.comp, st.nhop, st.n_beams, st.ld, st.beam_id_offset, nsteps, dt,
                        seed, diag);
+}
+
+// beams per tile of the batched wave kernels
+int wave_tile_beams(int d, int wpb) { return wpb * 64 / (d == 12 ? kLanesPerBeamD12 : 8); }
+
+template <int D, int LPB, int WPB>
+static void launch_pg_batched(bool mixed_state, const BatchItem *items, int n_items, int64_t total_tiles, int grab,
+                              int blocks, int nsteps, double dt, unsigned long long *queue, uint64_t *diag,
+                              hipStream_t stream) {
+  if (mixed_state)
+    hipLaunchKernelGGL((step_wave_batched<D, LPB, float, WPB>), dim3(blocks), dim3(64 * WPB), 0, stream, items,
+                       n_items, total_tiles, grab, nsteps, dt, queue, diag);
+  else
+    hipLaunchKernelGGL((step_wave_batched<D, LPB, double, WPB>), dim3(blocks), dim3(64 * WPB), 0, stream, items,
+                       n_items, total_tiles, grab, nsteps, dt, queue, diag);
+}
+
+hipError_t launch_step_wave_batched(int d, bool mixed_state, int wpb, const BatchItem *items, int n_items,
+                                    int64_t total_tiles, int grab, int blocks, int nsteps, double dt,
+                                    unsigned long long *queue, uint64_t *diag, hipStream_t stream) {
+#define SHGB_PGB(DD, LL)                                                                                     \
+  case DD:                                                                                                  \
+    if (wpb == 2) launch_pg_batched<DD, LL, 2>(mixed_state, items, n_items, total_tiles, grab, blocks, nsteps, dt, \
+                                              queue, diag, stream);                                         \
+    else launch_pg_batched<DD, LL, 4>(mixed_state, items, n_items, total_tiles, grab, blocks, nsteps, dt, queue, \
+                                      diag, stream);                                                        \
+    break;
+  switch (d) {
+    SHGB_PGB(2, 8)
+    SHGB_PGB(3, 8)
+    SHGB_PGB(4, 8)
+    SHGB_PGB(12, kLanesPerBeamD12)
+    default: return hipErrorInvalidValue;
+  }
+#undef SHGB_PGB
+  return hipGetLastError();
 }
 
 hipError_t launch_step_wave(const DevModel &md, const shgb_state &st, int nsteps, double dt, uint64_t seed,

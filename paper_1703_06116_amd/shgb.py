@@ -65,6 +65,23 @@ class InitSpec(ctypes.Structure):
                 ("a0", ctypes.c_double)]
 
 
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("tiles_per_grab", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("n_inst", ctypes.c_int32), ("d", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("kind", ctypes.c_int32), ("total_tiles", ctypes.c_int64), ("cfg", BatchConfig),
+                ("table", ctypes.c_void_p)]
+
+
+SHGB_BATCH_WORK_BYTES = 256
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
@@ -84,13 +101,17 @@ def _load():
         "shgb_strerror": (ctypes.c_char_p, [I32]),
         "shgb_version": (I32, []),
         "shgb_abi_sizes": (None, [V]),
+        "shgb_batch_table_bytes": (I64, [I32]),
+        "shgb_batch_prepare": (I32, [P(Model), P(StateDesc), P(U64), I32, P(BatchConfig), V, I64, P(BatchDesc)]),
+        "shgb_step_batched": (I32, [P(BatchDesc), I32, D, V, I64, V, V]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
         fn.restype, fn.argtypes = res, args
-    sizes = (ctypes.c_int64 * 3)()
+    sizes = (ctypes.c_int64 * 5)()
     lib.shgb_abi_sizes(ctypes.cast(sizes, ctypes.c_void_p))
-    want = (ctypes.sizeof(Model), ctypes.sizeof(StateDesc), ctypes.sizeof(InitSpec))
+    want = (ctypes.sizeof(Model), ctypes.sizeof(StateDesc), ctypes.sizeof(InitSpec), ctypes.sizeof(BatchConfig),
+            ctypes.sizeof(BatchDesc))
     if tuple(sizes) != want:
         raise ImportError(f"libshgb ABI mismatch: C sizes {tuple(sizes)} vs binding {want}")
     return lib
@@ -100,7 +121,8 @@ _lib = _load()
 
 EXPORTED = ("shgb_init_beams", "shgb_step_ensemble", "shgb_hop", "shgb_populations_workspace",
             "shgb_populations", "shgb_reconstruct_workspace", "shgb_reconstruct", "shgb_philox",
-            "shgb_strerror", "shgb_version", "shgb_abi_sizes")
+            "shgb_strerror", "shgb_version", "shgb_abi_sizes", "shgb_batch_table_bytes", "shgb_batch_prepare",
+            "shgb_step_batched")
 
 
 def _check(fn, rc):
@@ -267,6 +289,45 @@ def reconstruct(model, state, points, out=None, work=None, stream=None):
     _check("shgb_reconstruct", _lib.shgb_reconstruct(ctypes.byref(model), ctypes.byref(d), _ptr(points), Q,
                                                      _ptr(out), _ptr(work), work.numel(), _stream(stream)))
     return torch.view_as_complex(out)
+
+
+DEFAULT_BATCH_CONFIG = (4, 2, 1)   # waves per block, blocks per CU, tiles per grab
+
+
+class Batch:
+    """Instances (model, state, seed) advanced together by one persistent launch.
+
+    The instance table is written on the host by shgb_batch_prepare and kept
+    in device memory by this object, with the queue's work buffer; ``step``
+    is one call of shgb_step_batched (capturable in a HIP graph).
+    """
+
+    def __init__(self, models, states, seeds, config=DEFAULT_BATCH_CONFIG, device="cuda"):
+        n = len(models)
+        assert n == len(states) == len(seeds) and n >= 1
+        self.models, self.states, self.seeds = list(models), list(states), [int(x) for x in seeds]
+        self.config = config if isinstance(config, BatchConfig) else BatchConfig(*config)
+        nbytes = int(_lib.shgb_batch_table_bytes(n))
+        host = (ctypes.c_uint8 * nbytes)()
+        self._models = (Model * n)(*self.models)
+        self._states = (StateDesc * n)(*[st.desc() for st in self.states])
+        self._seeds = (ctypes.c_uint64 * n)(*self.seeds)
+        self.desc = BatchDesc()
+        _check("shgb_batch_prepare", _lib.shgb_batch_prepare(self._models, self._states, self._seeds, n,
+                                                             ctypes.byref(self.config), host, nbytes,
+                                                             ctypes.byref(self.desc)))
+        self.table = torch.frombuffer(bytearray(bytes(host)), dtype=torch.uint8).to(device)
+        self.desc.table = self.table.data_ptr()
+        self.work = torch.zeros(SHGB_BATCH_WORK_BYTES, dtype=torch.uint8, device=device)
+
+    @property
+    def total_tiles(self):
+        return int(self.desc.total_tiles)
+
+    def step(self, nsteps, dt, diag=None, stream=None):
+        _check("shgb_step_batched", _lib.shgb_step_batched(ctypes.byref(self.desc), int(nsteps), float(dt),
+                                                           _ptr(self.work), self.work.numel(), _ptr(diag),
+                                                           _stream(stream)))
 
 
 def philox(seed, counters, stream=None):

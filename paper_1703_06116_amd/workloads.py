@@ -14,6 +14,10 @@ Workloads (two-level QCLE, Sec. 3.3, with nuclear mass 2000):
                    harmonic with w_k ~ U[0.002, 0.02] coupled to q1 by
                    lam = 1e-3, 2^18 beams, 2000 steps, eps = 0.02; the field at
                    16384 points scattered around beam centres.
+* ``batch64_d12``  64 instances of the d = 12 model with C ~ U[0.002, 0.01],
+                   eps from {0.01, 0.02, 0.05} and beam counts log-uniform in
+                   [2^12, 2^17] (about 2.3e6 beams in all), 500 steps of 0.5,
+                   FP32 trajectories with FP64 phase, one batched launch.
 """
 
 import numpy as np
@@ -31,6 +35,30 @@ CONFIGS = {
                          p_dist="normal", p_a=20.0, p_b=1.0, comp0=1, seed=0x1703061160000003,
                          n_points=16384, lam=1e-3),
 }
+
+
+BATCH = {
+    "batch64_d12": dict(n_inst=64, d=12, C=(0.002, 0.01), eps=(0.01, 0.02, 0.05), beams=(2**12, 2**17),
+                        nsteps=500, dt=0.5, draw_seed=1703061164, seed0=0x1703061160000004),
+}
+
+
+def batch_instances(name, **overrides):
+    """Per-instance configs of a batched workload (model parameters drawn once, seeded)."""
+    b = dict(BATCH[name])
+    b.update(overrides)
+    rng = np.random.default_rng(b["draw_seed"])
+    n = b["n_inst"]
+    C = rng.uniform(*b["C"], n)
+    eps = rng.choice(np.asarray(b["eps"]), n)
+    lo, hi = np.log(b["beams"][0]), np.log(b["beams"][1])
+    beams = np.exp(rng.uniform(lo, hi, n)).astype(np.int64)
+    out = []
+    for i in range(n):
+        c = config("qcle12d_2p18", d=b["d"], bath_omega=bath_omega(b["d"]), C=float(C[i]), eps=float(eps[i]),
+                   n_beams=int(beams[i]), nsteps=b["nsteps"], dt=b["dt"], seed=b["seed0"] + i, n_points=0)
+        out.append(c)
+    return out
 
 
 def bath_omega(d, seed=1703061163):

@@ -48,10 +48,11 @@ def test_every_declared_function_is_exported(binding):
 
 
 def test_abi_sizes_and_version(binding):
-    sizes = (ctypes.c_int64 * 3)()
+    sizes = (ctypes.c_int64 * 5)()
     binding._lib.shgb_abi_sizes(ctypes.cast(sizes, ctypes.c_void_p))
     assert tuple(sizes) == (ctypes.sizeof(binding.Model), ctypes.sizeof(binding.StateDesc),
-                            ctypes.sizeof(binding.InitSpec))
+                            ctypes.sizeof(binding.InitSpec), ctypes.sizeof(binding.BatchConfig),
+                            ctypes.sizeof(binding.BatchDesc))
     assert binding._lib.shgb_version() >= 1
     assert binding._lib.shgb_strerror(-1) == b"invalid argument"
 
@@ -146,6 +147,45 @@ def test_validation_rejects_bad_arguments(binding):
     assert lib.shgb_reconstruct(by(mdl), by(st), nul, 100, ctypes.c_void_p(0x10), ctypes.c_void_p(0x10),
                                 wr, nul) == EINVAL
     assert lib.shgb_philox(1, nul, nul, 5, nul) == EINVAL
+
+
+def test_batch_prepare_validation(binding):
+    """Batch tables: tiles per instance, and the errors, without a device."""
+    lib = binding._lib
+    by = ctypes.byref
+    n = 3
+    models = (binding.Model * n)(*[_model(binding, d=12, lam=1e-3) for _ in range(n)])
+    for mdl in models:
+        for k in range(11):
+            mdl.bath_omega[k] = 0.01
+    sizes = (0, 9, 17)
+    states = (binding.StateDesc * n)(*[_desc(binding, n=k, m=24) for k in sizes])
+    seeds = (ctypes.c_uint64 * n)(1, 2, 3)
+    nbytes = lib.shgb_batch_table_bytes(n)
+    assert nbytes > 0 and lib.shgb_batch_table_bytes(0) == -1
+    host = (ctypes.c_uint8 * nbytes)()
+    desc = binding.BatchDesc()
+    cfg = binding.BatchConfig(4, 2, 1)
+    assert lib.shgb_batch_prepare(models, states, seeds, n, by(cfg), host, nbytes, by(desc)) == 0
+    # m = 24: 8 beams per tile with 4 waves per block (two beams per wave)
+    assert desc.total_tiles == sum((k + 7) // 8 for k in sizes) and desc.d == 12 and desc.n_inst == n
+    assert lib.shgb_batch_prepare(models, states, seeds, n, by(cfg), host, nbytes - 1, by(desc)) == -1
+    for bad in ((3, 2, 1), (4, 0, 1), (4, 17, 1), (4, 2, 0)):
+        assert lib.shgb_batch_prepare(models, states, seeds, n, by(binding.BatchConfig(*bad)), host, nbytes,
+                                      by(desc)) == -1
+    # instances must share d and precision
+    states2 = (binding.StateDesc * n)(*[_desc(binding, n=k, m=24) for k in sizes])
+    states2[1].precision = binding.PRECISION["mixed"]
+    states2[1].f32 = 0x1000
+    assert lib.shgb_batch_prepare(models, states2, seeds, n, by(cfg), host, nbytes, by(desc)) == -1
+    # nothing to do: no launch, no device
+    nul = ctypes.c_void_p(0)
+    work = ctypes.c_void_p(0x1000)
+    desc_ok = binding.BatchDesc()
+    assert lib.shgb_batch_prepare(models, states, seeds, n, by(cfg), host, nbytes, by(desc_ok)) == 0
+    assert lib.shgb_step_batched(by(desc_ok), 0, 0.5, work, 256, nul, nul) == 0        # zero steps
+    assert lib.shgb_step_batched(by(desc_ok), 5, 0.5, work, 255, nul, nul) == -1      # work too small
+    assert lib.shgb_step_batched(by(desc_ok), 5, 0.5, work, 256, nul, nul) == -1      # no device table
 
 
 def test_zero_work_calls_launch_nothing(binding):
