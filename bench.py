@@ -52,10 +52,14 @@ FLOPS_PER_BEAM_STEP_M24 = 4 * 3616 + 13 * 650
 # F = 325 features for Re and Im (4 F = 1300, the matrix-core work)
 FLOPS_PER_EVAL_M24 = 4 * 325
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 64 lanes x 2 flop x 2.4 GHz
-# HBM bytes per launch of step_m2_kernel at 1e6 beams, from rocprofv3 FETCH_SIZE (x2.000) and
-# WRITE_SIZE (x1.000) scaled by a 1 GiB copy (profiles/step_m2_qcle1d_1e6.md); the kernel
-# reads and writes 136 B of state per beam.  None when the kernel or workload differs.
-STEP_M2_TRAFFIC = {}
+# HBM bytes per launch of the FP64 stepping kernel, from rocprofv3 FETCH_SIZE (x2.000) and
+# WRITE_SIZE (x1.000), each scaled by what the counter reads for a 1 GiB device copy
+# (profiles/step_m2_qcle1d_1e6.md, profiles/step_wave_qcle12d_2p18.md).  Remove an entry when
+# its kernel changes.
+STEP_TRAFFIC = {
+    "qcle1d_1e6": (66681.4 * 2.0 + 133300.8 * 1.0) * 1024,          # step_m2_kernel, 1e6 beams
+    "qcle12d_2p18": (1343912.8 * 2.0 + 1484506.4 * 1.0) * 1024,     # step_wave_kernel<12, 32, double>
+}
 
 
 def parse():
@@ -335,8 +339,10 @@ def main():
         "roofline": {"bound": "alu", "kernel": "step_m2_kernel" if m == 2 else "step_wave_kernel<12>",
                      "achieved": step_tflops,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": step_tflops / PEAK_FP64_TFLOPS,
-                     "traffic": STEP_M2_TRAFFIC.get(a.config), "traffic_unit": "bytes/launch",
-                     "algorithmic_bytes": (272 if m == 2 else 2 * 8 * (2 * m + m * (m + 1) + 6)) * N,
+                     "traffic": STEP_TRAFFIC.get(a.config), "traffic_unit": "bytes/launch",
+                     # the state a call reads and writes once: X, P, Z, S, Lam, logw, phase, E
+                     # (A is constant for the QCLE, gamma_ll = 0) and comp, nhop
+                     "algorithmic_bytes": 2 * (8 * (2 * m + m * (m + 1) + 6) + 8) * N,
                      "flops_per_unit": fps, "units_per_launch": N * nsteps},
         "reconstruct_roofline": ({"bound": "alu" if m == 2 else "mfma", "achieved": fpe * evals_per_s / 1e12,
                                   "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
