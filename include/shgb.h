@@ -223,6 +223,33 @@ int64_t shgb_reconstruct_workspace(int64_t n_beams, int32_t m, int64_t Q);
 int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double *points,
                      int64_t Q, double *out, void *work, int64_t work_bytes, void *stream);
 
+/* ---- pathwise derivative of the populations ----------------------------
+ * The derivative of the population sums (Sec. 2.3 eq. (2.26) integrated,
+ * as shgb_populations) after nsteps intervals, with respect to
+ * theta = (A, B, C, D, p_mean): the potential parameters and a common
+ * shift of every beam's initial p1 (the mean initial momentum).  The
+ * discrete algorithm is differentiated with its events frozen: hop tests,
+ * destinations and phase signs are taken at the values exactly as
+ * shgb_step_ensemble takes them, the drawn thresholds carry no derivative,
+ * and the hop time moves with the parameters through
+ * theta = (E - Lam)/(Lam' - Lam) and the shortened step it sets.  This is
+ * the limit of central differences with common random numbers while no
+ * event flips.  Forward (tangent) propagation, one pass per requested
+ * direction; QCLE with d = 1 (m = 2), FP64 state.
+ *
+ * st: the initial ensemble (read, never written).  dir_mask: bit j selects
+ * theta_j.  out: device double[5 * SHGB_NCOMP * 4]; for direction j and
+ * component i, out[(j * SHGB_NCOMP + i) * 4 + {0, 1, 2, 3}] = sum Re c,
+ * sum Im c, d/dtheta_j sum Re c, d/dtheta_j sum Im c over the beams on
+ * component i at the end (entries of unselected directions are left as
+ * they were).  work: device, >= shgb_population_tangent_workspace(n_beams).
+ * Errors: EINVAL, EWORKSPACE, EUNSUPPORTED (m != 2, mixed state, LINQUAD). */
+#define SHGB_NTHETA 5
+int64_t shgb_population_tangent_workspace(int64_t n_beams);
+int shgb_population_tangent(const shgb_model *model, const shgb_state *st, int32_t nsteps, double dt,
+                            uint64_t seed, uint32_t dir_mask, double *out, void *work, int64_t work_bytes,
+                            uint64_t *diag, void *stream);
+
 /* ---- batches: many instances in one persistent launch ------------------
  * A batch is n_inst independent QCLE instances (model, state, seed) of one
  * dimension d and one precision; models may differ in every parameter and

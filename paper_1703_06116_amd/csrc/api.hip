@@ -28,6 +28,9 @@ hipError_t launch_recon_wave(const DevModel &, const shgb_state &, const double 
                              hipStream_t);
 int64_t recon_mfma_workspace_bytes(int64_t, int64_t);
 int wave_tile_beams(int d, int wpb);
+int64_t tangent_workspace_bytes(int64_t n);
+hipError_t launch_tangent_m2(const DevModel &, const shgb_state &, int, double, uint64_t, uint32_t, double *, void *,
+                             uint64_t *, hipStream_t);
 int m2_tile_beams(int wpb);
 hipError_t launch_step_wave_batched(int d, bool mixed_state, int wpb, const BatchItem *items, int n_items,
                                     int64_t total_tiles, int grab, int blocks, int nsteps, double dt,
@@ -248,6 +251,25 @@ int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double
   if (!recon_wave_supported(st->m)) return SHGB_EUNSUPPORTED;
   if (work_bytes < recon_wave_workspace_bytes(st->n_beams, st->m, Q)) return SHGB_EWORKSPACE;
   return hip_status(launch_recon_wave(md, *st, points, Q, out, work, (hipStream_t)stream));
+}
+
+int64_t shgb_population_tangent_workspace(int64_t n_beams) {
+  if (n_beams < 0) return -1;
+  return tangent_workspace_bytes(n_beams);
+}
+
+int shgb_population_tangent(const shgb_model *model, const shgb_state *st, int32_t nsteps, double dt, uint64_t seed,
+                            uint32_t dir_mask, double *out, void *work, int64_t work_bytes, uint64_t *diag,
+                            void *stream) {
+  DevModel md;
+  int rc = to_dev_model(model, md);
+  if (rc) return rc;
+  if ((rc = check_state(st, md))) return rc;
+  if (md.kind != SHGB_MODEL_QCLE || md.d != 1 || st->precision != SHGB_FP64) return SHGB_EUNSUPPORTED;
+  if (nsteps < 0 || !finite_pos(dt) || (dir_mask & ~0x1Fu) || !out) return SHGB_EINVAL;
+  if (!work || work_bytes < tangent_workspace_bytes(st->n_beams)) return SHGB_EWORKSPACE;
+  if (dir_mask == 0) return SHGB_OK;
+  return hip_status(launch_tangent_m2(md, *st, nsteps, dt, seed, dir_mask, out, work, diag, (hipStream_t)stream));
 }
 
 int64_t shgb_batch_table_bytes(int32_t n_inst) {

@@ -101,6 +101,8 @@ def _load():
         "shgb_strerror": (ctypes.c_char_p, [I32]),
         "shgb_version": (I32, []),
         "shgb_abi_sizes": (None, [V]),
+        "shgb_population_tangent_workspace": (I64, [I64]),
+        "shgb_population_tangent": (I32, [P(Model), P(StateDesc), I32, D, U64, ctypes.c_uint32, V, V, I64, V, V]),
         "shgb_batch_table_bytes": (I64, [I32]),
         "shgb_batch_prepare": (I32, [P(Model), P(StateDesc), P(U64), I32, P(BatchConfig), V, I64, P(BatchDesc)]),
         "shgb_step_batched": (I32, [P(BatchDesc), I32, D, V, I64, V, V]),
@@ -122,7 +124,7 @@ _lib = _load()
 EXPORTED = ("shgb_init_beams", "shgb_step_ensemble", "shgb_hop", "shgb_populations_workspace",
             "shgb_populations", "shgb_reconstruct_workspace", "shgb_reconstruct", "shgb_philox",
             "shgb_strerror", "shgb_version", "shgb_abi_sizes", "shgb_batch_table_bytes", "shgb_batch_prepare",
-            "shgb_step_batched")
+            "shgb_step_batched", "shgb_population_tangent_workspace", "shgb_population_tangent")
 
 
 def _check(fn, rc):
@@ -289,6 +291,29 @@ def reconstruct(model, state, points, out=None, work=None, stream=None):
     _check("shgb_reconstruct", _lib.shgb_reconstruct(ctypes.byref(model), ctypes.byref(d), _ptr(points), Q,
                                                      _ptr(out), _ptr(work), work.numel(), _stream(stream)))
     return torch.view_as_complex(out)
+
+
+THETA_NAMES = ("A", "B", "C", "D", "p_mean")
+
+
+def population_tangent(model, state, nsteps, dt, seed, dirs=range(5), out=None, work=None, diag=None,
+                       stream=None):
+    """Population sums and their derivatives along theta_j (see include/shgb.h): a (5, 4, 4)
+    float64 device tensor [direction, component, (Re c, Im c, d Re c, d Im c)] summed over beams."""
+    dev = state.f64.device
+    if out is None:
+        out = torch.zeros((5, SHGB_NCOMP, 4), dtype=torch.float64, device=dev)
+    nb = int(_lib.shgb_population_tangent_workspace(state.n))
+    if work is None:
+        work = torch.empty(max(nb, 8), dtype=torch.uint8, device=dev)
+    mask = 0
+    for j in dirs:
+        mask |= 1 << int(j)
+    d = state.desc()
+    _check("shgb_population_tangent", _lib.shgb_population_tangent(
+        ctypes.byref(model), ctypes.byref(d), int(nsteps), float(dt), seed, mask, _ptr(out), _ptr(work),
+        work.numel(), _ptr(diag), _stream(stream)))
+    return out
 
 
 DEFAULT_BATCH_CONFIG = (4, 2, 1)   # waves per block, blocks per CU, tiles per grab
