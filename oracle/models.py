@@ -29,6 +29,10 @@ Models:
   Sec. 3.1 for which the Gaussian beam ansatz has no modelling error.  With
   alpha = 0 and constant beta it is the x-independent system whose exact
   solution is a matrix exponential (Sec. 2.2, eq. (2.11)).
+* ``Paper32`` the two-component system with nonlinear coefficients of
+  Sec. 3.2, eq. (3.2), in the form d_t u + alpha.grad u = (i/eps) beta u
+  + gamma u: the transport fields are minus the printed drifts,
+  beta_1 = sin|x|^2, beta_2 = cos|x|^2, and gamma = |x|^2 [[-1, 5], [-5, -1/2]].
 """
 
 import numpy as np
@@ -193,3 +197,57 @@ class LinQuad:
 
     def gamma(self, X):
         return np.broadcast_to(self.G, (X.shape[0],) + self.G.shape).copy()
+
+
+class Paper32:
+    """Eq. (3.2): alpha_1 = -(sin(x1 + x2), cos(x1 - x2)), alpha_2 = -(sin(x1 - x2), cos(x1 + x2)),
+    beta_1 = sin(r^2), beta_2 = cos(r^2) with r^2 = x1^2 + x2^2,
+    gamma = r^2 [[-1, 5], [-5, -1/2]] (row receives from column).  Derivatives by hand."""
+
+    n_comp, m = 2, 2
+    G_UNIT = np.array([[-1.0, 5.0], [-5.0, -0.5]])
+
+    @staticmethod
+    def _uv(X):
+        return X[:, 0] + X[:, 1], X[:, 0] - X[:, 1]
+
+    def alpha(self, X, comp):
+        u, v = self._uv(X)
+        a0 = np.stack([-np.sin(u), -np.cos(v)], 1)
+        a1 = np.stack([-np.sin(v), -np.cos(u)], 1)
+        return np.where((comp == 0)[:, None], a0, a1)
+
+    def jac_alpha(self, X, comp):
+        u, v = self._uv(X)
+        cu, su, cv, sv = np.cos(u), np.sin(u), np.cos(v), np.sin(v)
+        J0 = np.stack([np.stack([-cu, -cu], 1), np.stack([sv, -sv], 1)], 1)
+        J1 = np.stack([np.stack([-cv, cv], 1), np.stack([su, su], 1)], 1)
+        return np.where((comp == 0)[:, None, None], J0, J1)
+
+    def beta(self, X, comp):
+        r2 = (X ** 2).sum(1)
+        return np.where(comp == 0, np.sin(r2), np.cos(r2))
+
+    def grad_beta(self, X, comp):
+        r2 = (X ** 2).sum(1)
+        f = np.where(comp == 0, 2.0 * np.cos(r2), -2.0 * np.sin(r2))
+        return f[:, None] * X
+
+    def hess_beta(self, X, comp):
+        r2 = (X ** 2).sum(1)
+        f1 = np.where(comp == 0, 2.0 * np.cos(r2), -2.0 * np.sin(r2))      # coefficient of I
+        f2 = np.where(comp == 0, -4.0 * np.sin(r2), -4.0 * np.cos(r2))     # coefficient of x x^T
+        return f1[:, None, None] * np.eye(2)[None] + f2[:, None, None] * np.einsum("na,nb->nab", X, X)
+
+    def hess_P_alpha(self, X, comp, P):
+        u, v = self._uv(X)
+        ones = np.array([[1.0, 1.0], [1.0, 1.0]])
+        alt = np.array([[1.0, -1.0], [-1.0, 1.0]])
+        # P.alpha_1 = -(P1 sin u + P2 cos v);  P.alpha_2 = -(P1 sin v + P2 cos u)
+        h0 = (P[:, 0] * np.sin(u))[:, None, None] * ones + (P[:, 1] * np.cos(v))[:, None, None] * alt
+        h1 = (P[:, 0] * np.sin(v))[:, None, None] * alt + (P[:, 1] * np.cos(u))[:, None, None] * ones
+        return np.where((comp == 0)[:, None, None], h0, h1)
+
+    def gamma(self, X):
+        r2 = (X ** 2).sum(1)
+        return r2[:, None, None] * self.G_UNIT[None].astype(np.complex128)

@@ -156,3 +156,34 @@ def test_coupling_structure_conserves_trace():
     np.testing.assert_array_equal(G[:, 2, :2], G[:, 3, :2])
     comp2, comp3 = np.array([2, 2]), np.array([3, 3])
     np.testing.assert_array_equal(mdl.beta(X, comp2), -mdl.beta(X, comp3))
+
+
+@pytest.mark.parametrize("comp", [0, 1])
+def test_paper32_derivatives_by_finite_differences(comp):
+    """Eq. (3.2): every Jacobian/Hessian the beam ODEs use equals central differences."""
+    mdl = models.Paper32()
+    rng = np.random.default_rng(40 + comp)
+    for _ in range(6):
+        x = rng.normal(0, 1.2, 2)
+        P = rng.normal(0, 1, 2)
+        c1 = np.array([comp])
+        np.testing.assert_allclose(mdl.jac_alpha(x[None], c1)[0],
+                                   _fd_jac(lambda z: mdl.alpha(z[None], c1)[0], x, 1e-5), atol=1e-9)
+        np.testing.assert_allclose(mdl.grad_beta(x[None], c1)[0],
+                                   _fd_jac(lambda z: mdl.beta(z[None], c1), x, 1e-6)[0], atol=1e-8)
+        np.testing.assert_allclose(mdl.hess_beta(x[None], c1)[0],
+                                   _fd_jac(lambda z: mdl.grad_beta(z[None], c1)[0], x, 1e-5), atol=1e-8)
+        np.testing.assert_allclose(mdl.hess_P_alpha(x[None], c1, P[None])[0],
+                                   _fd_jac(lambda z: P @ mdl.jac_alpha(z[None], c1)[0], x, 1e-5), atol=1e-8)
+
+
+def test_paper32_coefficients_as_printed():
+    """Spot values read off eq. (3.2) at a point, component by component."""
+    mdl = models.Paper32()
+    x = np.array([[0.3, -0.7]])
+    r2 = 0.3 ** 2 + 0.7 ** 2
+    np.testing.assert_allclose(mdl.alpha(x, np.array([0]))[0], [-np.sin(-0.4), -np.cos(1.0)])
+    np.testing.assert_allclose(mdl.alpha(x, np.array([1]))[0], [-np.sin(1.0), -np.cos(-0.4)])
+    assert mdl.beta(x, np.array([0]))[0] == np.sin(r2) and mdl.beta(x, np.array([1]))[0] == np.cos(r2)
+    G = mdl.gamma(x)[0]
+    np.testing.assert_allclose(G, r2 * np.array([[-1, 5], [-5, -0.5]]))
