@@ -52,6 +52,7 @@ extern "C" {
 /* ---- fixed sizes -------------------------------------------------------- */
 #define SHGB_MODEL_QCLE 1
 #define SHGB_MODEL_LINQUAD 2
+#define SHGB_MODEL_PAPER32 3
 #define SHGB_NCOMP 4      /* components (at most, for SHGB_MODEL_LINQUAD)     */
 #define SHGB_MAX_D 12     /* nuclear dimensions: phase space m = 2d <= 24     */
 #define SHGB_HOP_CAP 16   /* hops per beam per interval; later ones deferred  */
@@ -89,7 +90,13 @@ extern "C" {
  * j != l with probability |gamma_jl| / sum_{k != l} |gamma_kl| and
  * multiplies the phase by gamma_jl / |gamma_jl|.  With x-independent
  * coefficients (a = J = b = H = 0) this is the system of Sec. 2.1.
- * Stepping and hops of this kind are FP64 only.                           */
+ * Stepping and hops of this kind are FP64 only.
+ *
+ * SHGB_MODEL_PAPER32: the two-component system with nonlinear coefficients
+ * of Sec. 3.2, eq. (3.2), x in R^2 (d = 1), no parameters besides eps:
+ *   alpha_1 = -(sin(x1 + x2), cos(x1 - x2)), alpha_2 = -(sin(x1 - x2), cos(x1 + x2)),
+ *   beta_1 = sin|x|^2, beta_2 = cos|x|^2, gamma = |x|^2 [[-1, 5], [-5, -1/2]].
+ * FP64 stepping and hops.                                                   */
 typedef struct shgb_linquad {
   int32_t n_comp;                          /* 1..SHGB_NCOMP                  */
   double a[SHGB_NCOMP][2];
@@ -102,7 +109,7 @@ typedef struct shgb_linquad {
 } shgb_linquad;
 
 typedef struct shgb_model {
-  int32_t kind;                       /* SHGB_MODEL_QCLE or SHGB_MODEL_LINQUAD */
+  int32_t kind;                       /* SHGB_MODEL_QCLE, _LINQUAD or _PAPER32 */
   int32_t d;                          /* 1..SHGB_MAX_D (1 for LINQUAD)      */
   double mass, eps;                   /* > 0 (mass unused by LINQUAD)       */
   double A, B, C, D;                  /* QCLE potential parameters (C != 0) */

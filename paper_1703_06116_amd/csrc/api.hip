@@ -9,6 +9,8 @@
 namespace shgb {
 hipError_t launch_init(const DevModel &, const shgb_init_spec &, const shgb_state &, uint64_t, double, hipStream_t);
 hipError_t launch_step_lq(const DevLQ &, const shgb_state &, int, double, uint64_t, uint64_t *, hipStream_t);
+hipError_t launch_step_p32(const shgb_state &, int, double, uint64_t, uint64_t *, hipStream_t);
+hipError_t launch_hop_p32(const shgb_state &, const int32_t *, int64_t, uint64_t, uint64_t *, hipStream_t);
 hipError_t launch_hop_lq(const DevLQ &, const shgb_state &, const int32_t *, int64_t, uint64_t, uint64_t *,
                          hipStream_t);
 hipError_t launch_step_m2(const DevModel &, const shgb_state &, int, double, uint64_t, uint64_t *, hipStream_t);
@@ -96,6 +98,17 @@ int to_dev_lq(const shgb_linquad &q, DevLQ &lq) {
 
 int to_dev_model(const shgb_model *m, DevModel &md, DevLQ *lq = nullptr) {
   if (!m) return SHGB_EINVAL;
+  if (m->kind == SHGB_MODEL_PAPER32) {
+    if (m->d != 1 || !finite_pos(m->eps)) return SHGB_EINVAL;
+    std::memset(&md, 0, sizeof(md));
+    md.kind = SHGB_MODEL_PAPER32;
+    md.n_comp = 2;
+    md.mass = 1.0;
+    md.inv_mass = 1.0;
+    md.eps = m->eps;
+    md.d = 1;
+    return SHGB_OK;
+  }
   if (m->kind == SHGB_MODEL_LINQUAD) {
     if (m->d != 1 || !finite_pos(m->eps)) return SHGB_EINVAL;
     std::memset(&md, 0, sizeof(md));
@@ -188,6 +201,10 @@ int shgb_step_ensemble(const shgb_model *model, const shgb_state *st, int32_t ns
     if (st->precision != SHGB_FP64) return SHGB_EUNSUPPORTED;
     return hip_status(launch_step_lq(lq, *st, nsteps, dt, seed, diag, (hipStream_t)stream));
   }
+  if (md.kind == SHGB_MODEL_PAPER32) {
+    if (st->precision != SHGB_FP64) return SHGB_EUNSUPPORTED;
+    return hip_status(launch_step_p32(*st, nsteps, dt, seed, diag, (hipStream_t)stream));
+  }
   if (md.d == 1) return hip_status(launch_step_m2(md, *st, nsteps, dt, seed, diag, (hipStream_t)stream));
   if (!step_wave_supported(md.d)) return SHGB_EUNSUPPORTED;
   return hip_status(launch_step_wave(md, *st, nsteps, dt, seed, diag, (hipStream_t)stream));
@@ -204,6 +221,10 @@ int shgb_hop(const shgb_model *model, const shgb_state *st, const int32_t *idx, 
   if (md.kind == SHGB_MODEL_LINQUAD) {
     if (st->precision != SHGB_FP64) return SHGB_EUNSUPPORTED;
     return hip_status(launch_hop_lq(lq, *st, idx, n_idx, seed, diag, (hipStream_t)stream));
+  }
+  if (md.kind == SHGB_MODEL_PAPER32) {
+    if (st->precision != SHGB_FP64) return SHGB_EUNSUPPORTED;
+    return hip_status(launch_hop_p32(*st, idx, n_idx, seed, diag, (hipStream_t)stream));
   }
   return hip_status(launch_hop(md, *st, idx, n_idx, seed, diag, (hipStream_t)stream));
 }

@@ -183,6 +183,13 @@ def make_linquad_model(eps, a, J, b0, b, H, gamma):
     return mdl
 
 
+def make_paper32_model(eps):
+    """The nonlinear two-component system of eq. (3.2) (see include/shgb.h)."""
+    mdl = Model()
+    mdl.kind, mdl.d, mdl.mass, mdl.eps = 3, 1, 1.0, float(eps)
+    return mdl
+
+
 def make_init_spec(q_mean, q_std, p_dist, p_a, p_b, comp0, a0=0.0):
     return InitSpec(q_mean, q_std, DIST[p_dist], p_a, p_b, comp0, a0)
 

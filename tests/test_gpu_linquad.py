@@ -170,3 +170,67 @@ def test_hop_entry_point_complex_gamma(gpu):
     assert np.abs(g["phase"] - e.phase).max() < 1e-15
     assert np.abs(g["logw"] - e.logw).max() < 1e-15 and (g["Lam"][idx] == 0).all()
     np.testing.assert_allclose(g["E"], e.E, rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# The nonlinear system of Sec. 3.2, eq. (3.2): x-dependent transport, phases
+# and couplings; beam curvature terms Hess(P.alpha) and Hess(beta) nonzero.
+
+def test_paper_system_32_gpu_matches_oracle(gpu):
+    model = models.Paper32()
+    e0 = random_beams(2, 2 * 256 + 19, seed=21, n_comp=2)
+    e0.X[:] *= 0.8
+    e0.comp[:] = np.arange(e0.n) % 2
+    e0.A[:] = 1.0
+    st = gpu.pack(arrays_from_ensemble(e0))
+    diag = gpu.new_diag()
+    gpu.step_ensemble(gpu.make_paper32_model(0.04), st, 80, 0.01, 21, diag)
+    e = e0.subset(np.arange(e0.n))
+    oshgb.advance(model, e, 80, 0.01, 21)
+    errs, ties = compare_states(gpu.unpack(st), e, label="eq. (3.2)")
+    assert diag.cpu().numpy()[0] == e.nhop.sum() and e.nhop.sum() > e0.n // 4
+    print("eq. (3.2)", errs, "ties", ties, "hops", e.nhop.sum())
+
+
+def test_paper_system_32_from_the_single_initial_beam(gpu):
+    """u1(0, x) = exp(-|x|^2/(2 eps)): every trajectory starts as the same beam (X = 0, Z = I,
+    A = 1); only the hop times differ.  GPU init + stepping + populations against the oracle."""
+    eps, n, nsteps, dt, seed = 0.02, 3 * 256 + 7, 100, 0.005, 0x5EC32
+    mdl = gpu.make_paper32_model(eps)
+    st = gpu.State(n, 2)
+    gpu.init_beams(mdl, gpu.make_init_spec(0.0, 0.0, "normal", 0.0, 0.0, 0, a0=1.0), st, seed)
+    a = gpu_init_reference(n, eps, seed, 0.0)
+    a["A"] = np.ones(n, dtype=np.complex128)
+    e0 = ensemble_from_arrays(a, n_comp=2)
+    g0 = gpu.unpack(st)
+    assert (g0["X"] == 0).all() and (g0["A"] == 1).all()
+    np.testing.assert_allclose(g0["E"], e0.E, rtol=1e-14)
+    gpu.step_ensemble(mdl, st, nsteps, dt, seed)
+    e = e0.subset(np.arange(n))
+    oshgb.advance(models.Paper32(), e, nsteps, dt, seed)
+    compare_states(gpu.unpack(st), e, label="eq. (3.2) single beam")
+    pops = gpu.populations(mdl, st).cpu().numpy()
+    ref = observables.populations(e, eps)
+    ci = observables.beam_integrals(e, eps)
+    assert np.abs(pops[:2, :2] - ref[:2, :2]).max() <= 1e-10 * np.abs(ci).sum()
+    assert e.nhop.sum() > 0
+
+
+def test_hop_entry_point_paper_system_32(gpu):
+    model = models.Paper32()
+    e0 = random_beams(2, 150, seed=23, n_comp=2)
+    e0.comp[:] = np.arange(150) % 2
+    e0.Lam[:] = np.linspace(0.0, 2.0, 150)
+    e0.X[0] = 0.0                      # no coupling at the origin: counted, no hop
+    st = gpu.pack(arrays_from_ensemble(e0))
+    idx = np.arange(0, 150, 3, dtype=np.int32)
+    diag = gpu.new_diag()
+    gpu.hop(gpu.make_paper32_model(0.05), st, torch.from_numpy(idx).cuda(), 8, diag)
+    g = gpu.unpack(st)
+    e = e0.subset(np.arange(150))
+    oshgb.hop_event(model, e, idx, 8)
+    np.testing.assert_array_equal(g["comp"], e.comp)
+    np.testing.assert_array_equal(g["nhop"], e.nhop)
+    np.testing.assert_array_equal(g["phase"], e.phase)
+    assert np.abs(g["logw"] - e.logw).max() < 1e-15
+    assert diag.cpu().numpy()[6] == 1 == e.zero_rate.sum()
