@@ -115,3 +115,27 @@ def test_full_size_d12_field(gpu):
     scale = observables.reconstruct_abs(e, c["eps"], pts[qs], chunk=8192)
     assert (np.abs(out[:, qs] - ref) <= 1e-10 * scale + 1e-300).all()
     assert np.abs(ref).max() > 0
+
+
+@pytest.mark.parametrize("name,k", [("qcle1d_1e6", 32), ("qcle12d_2p18", 16)])
+def test_full_size_mixed_sampled_beams(gpu, name, k):
+    """The bench workloads on a mixed-precision state at full size; sampled beams by the FP64
+    oracle from their global ids, started from the float32-rounded draws (ties within 1e-5
+    excluded, 1e-4 bar)."""
+    c = workloads.config(name)
+    st = gpu.State(c["n_beams"], 2 * c["d"], device="cuda", precision="mixed")
+    diag = gpu.new_diag()
+    mdl = gpu_model(c)
+    gpu.init_beams(mdl, gpu_spec(c), st, c["seed"])
+    gpu.step_ensemble(mdl, st, c["nsteps"], c["dt"], c["seed"], diag)
+    ids = sample_ids(c["n_beams"], k, seed=13)
+    g_all = gpu.unpack(st)
+    g = {key: v[ids] for key, v in g_all.items()}
+    e = oracle_init_ids(c, ids)
+    for f in ("X", "P", "M", "N"):      # the FP64 draws as the mixed state stores them
+        getattr(e, f)[:] = getattr(e, f).astype(np.float32).astype(np.float64)
+    oshgb.advance(oracle_model(c), e, c["nsteps"], c["dt"], c["seed"], tie_rel=oshgb.TIE_REL_MIXED)
+    errs, ties = compare_states(g, e, rtol=1e-4, min_ok=0.8, label=f"{name} mixed")
+    d = diag.cpu().numpy()
+    assert d[3] == 0 and d[4] == 0
+    print(name, "mixed errors", errs, "ties", ties)
