@@ -242,7 +242,8 @@ int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double
  * theta = (E - Lam)/(Lam' - Lam) and the shortened step it sets.  This is
  * the limit of central differences with common random numbers while no
  * event flips.  Forward (tangent) propagation, one pass per requested
- * direction; QCLE with d = 1 (m = 2), FP64 state.
+ * direction; QCLE with d = 1 (m = 2) or with a harmonic bath and
+ * d in {2, 3, 4, 12}, FP64 state.  For d > 1, p_mean shifts p1 only.
  *
  * st: the initial ensemble (read, never written).  dir_mask: bit j selects
  * theta_j.  out: device double[5 * SHGB_NCOMP * 4]; for direction j and
@@ -250,7 +251,8 @@ int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double
  * sum Im c, d/dtheta_j sum Re c, d/dtheta_j sum Im c over the beams on
  * component i at the end (entries of unselected directions are left as
  * they were).  work: device, >= shgb_population_tangent_workspace(n_beams).
- * Errors: EINVAL, EWORKSPACE, EUNSUPPORTED (m != 2, mixed state, LINQUAD). */
+ * Errors: EINVAL, EWORKSPACE, EUNSUPPORTED (other d, mixed state, LINQUAD or
+ * eq. (3.2) model). */
 #define SHGB_NTHETA 5
 int64_t shgb_population_tangent_workspace(int64_t n_beams);
 int shgb_population_tangent(const shgb_model *model, const shgb_state *st, int32_t nsteps, double dt,

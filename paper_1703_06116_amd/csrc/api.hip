@@ -31,6 +31,10 @@ hipError_t launch_recon_wave(const DevModel &, const shgb_state &, const double 
 int64_t recon_mfma_workspace_bytes(int64_t, int64_t);
 int wave_tile_beams(int d, int wpb);
 int64_t tangent_workspace_bytes(int64_t n);
+int64_t tangent_wave_workspace_bytes(int64_t n);
+bool tangent_wave_supported(int d);
+hipError_t launch_tangent_wave(const DevModel &, const shgb_state &, int, double, uint64_t, uint32_t, double *, void *,
+                               uint64_t *, hipStream_t);
 hipError_t launch_tangent_m2(const DevModel &, const shgb_state &, int, double, uint64_t, uint32_t, double *, void *,
                              uint64_t *, hipStream_t);
 int m2_tile_beams(int wpb);
@@ -274,9 +278,15 @@ int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double
   return hip_status(launch_recon_wave(md, *st, points, Q, out, work, (hipStream_t)stream));
 }
 
+// enough for either tangent form (the query does not know m)
+static int64_t tangent_work(int64_t n) {
+  const int64_t a = tangent_workspace_bytes(n), b = tangent_wave_workspace_bytes(n);
+  return a > b ? a : b;
+}
+
 int64_t shgb_population_tangent_workspace(int64_t n_beams) {
   if (n_beams < 0) return -1;
-  return tangent_workspace_bytes(n_beams);
+  return tangent_work(n_beams);
 }
 
 int shgb_population_tangent(const shgb_model *model, const shgb_state *st, int32_t nsteps, double dt, uint64_t seed,
@@ -286,11 +296,14 @@ int shgb_population_tangent(const shgb_model *model, const shgb_state *st, int32
   int rc = to_dev_model(model, md);
   if (rc) return rc;
   if ((rc = check_state(st, md))) return rc;
-  if (md.kind != SHGB_MODEL_QCLE || md.d != 1 || st->precision != SHGB_FP64) return SHGB_EUNSUPPORTED;
+  if (md.kind != SHGB_MODEL_QCLE || st->precision != SHGB_FP64) return SHGB_EUNSUPPORTED;
+  if (md.d != 1 && !tangent_wave_supported(md.d)) return SHGB_EUNSUPPORTED;
   if (nsteps < 0 || !finite_pos(dt) || (dir_mask & ~0x1Fu) || !out) return SHGB_EINVAL;
-  if (!work || work_bytes < tangent_workspace_bytes(st->n_beams)) return SHGB_EWORKSPACE;
+  if (!work || work_bytes < tangent_work(st->n_beams)) return SHGB_EWORKSPACE;
   if (dir_mask == 0) return SHGB_OK;
-  return hip_status(launch_tangent_m2(md, *st, nsteps, dt, seed, dir_mask, out, work, diag, (hipStream_t)stream));
+  if (md.d == 1)
+    return hip_status(launch_tangent_m2(md, *st, nsteps, dt, seed, dir_mask, out, work, diag, (hipStream_t)stream));
+  return hip_status(launch_tangent_wave(md, *st, nsteps, dt, seed, dir_mask, out, work, diag, (hipStream_t)stream));
 }
 
 int64_t shgb_batch_table_bytes(int32_t n_inst) {

@@ -30,60 +30,9 @@
 // copy of the state held in registers for the whole call; S and Lam are
 // FP64 as in the FP64 path.
 #include "batch.h"
+#include "wave.h"
 
 namespace shgb {
-
-__device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-template <int D, int LPB>
-struct PG {
-  static constexpr int M = 2 * D;
-  static constexpr int NGRP = D * (D + 1) / 2;          // pair groups a <= b
-  static constexpr int NG = (NGRP + LPB - 1) / LPB;     // groups per lane
-  static constexpr int G = 64 / LPB;                    // beams per wavefront
-  static_assert(M <= LPB, "X and P need one lane per coordinate");
-};
-
-// One beam's exchange area (T: the stage precision).
-template <int D, typename T>
-struct PgLds {
-  T rp_r[D][D], rp_i[D][D];   // Zrp
-  T pp_r[D][D], pp_i[D][D];   // Zpp (both triangles)
-  T rho_r[D], rho_i[D], chi_r[D], chi_i[D];
-  T x[2 * D], p[2 * D];
-};
-
-// Values of one pair group: Zrr_ab, Zrp_ab, Zrp_ba, Zpp_ab (re, im).
-enum { kRrR, kRrI, kAbR, kAbI, kBaR, kBaI, kPpR, kPpI, kGrpN };
-template <typename T>
-struct Grp {
-  T v[kGrpN];
-};
-
-template <int D, int LPB, typename T>
-struct PgY {
-  Grp<T> g[PG<D, LPB>::NG];
-  T x, p;
-  double S, Lam;
-};
-
-template <int D, int LPB, typename T>
-struct PgCtx {
-  int r;                         // lane within the beam's group
-  int a[PG<D, LPB>::NG], b[PG<D, LPB>::NG];  // pair of each owned group, -1: none
-  T ka[PG<D, LPB>::NG], kb[PG<D, LPB>::NG];  // M w^2 of the pair's bath indices (0 for index 0)
-  T kc;                          // M w^2 of the lane's coordinate (X/P lanes)
-};
-
-// The adiabatic quantities along q1 in the stage precision.
-template <typename T>
-struct Q1T {
-  T s, s1, s2, s3, d21;
-};
 
 __device__ inline Q1T<double> q1_eval(const DevModel &md, const QcleF &, double q) {
   const Q1 k = qcle_q1(md, q);
@@ -94,48 +43,6 @@ __device__ inline Q1T<float> q1_eval(const DevModel &, const QcleF &mf, float q)
   const Q1f k = qcle_q1f(mf, q);
   return Q1T<float>{k.s, k.s1, k.s2, k.s3, k.d21};
 }
-
-template <int D, int LPB, typename T>
-__device__ inline void pg_publish(const PgCtx<D, LPB, T> &cx, const PgY<D, LPB, T> &y, PgLds<D, T> &s) {
-#pragma unroll
-  for (int e = 0; e < PG<D, LPB>::NG; ++e) {
-    const int a = cx.a[e], b = cx.b[e];
-    if (a >= 0) {
-      const T *v = y.g[e].v;
-      s.rp_r[a][b] = v[kAbR];
-      s.rp_i[a][b] = v[kAbI];
-      s.rp_r[b][a] = v[kBaR];   // a == b: the same entry, written twice with one value
-      s.rp_i[b][a] = v[kBaI];
-      s.pp_r[a][b] = v[kPpR];
-      s.pp_i[a][b] = v[kPpI];
-      s.pp_r[b][a] = v[kPpR];
-      s.pp_i[b][a] = v[kPpI];
-    }
-  }
-  if (cx.r < 2 * D) { s.x[cx.r] = y.x; s.p[cx.r] = y.p; }
-  wave_lds_sync();
-  if (cx.r < D) {
-    const int i = cx.r;
-    T sr = 0, si = 0;
-    for (int k = 1; k < D; ++k) { sr += s.rp_r[i][k]; si += s.rp_i[i][k]; }
-    s.rho_r[i] = sr;
-    s.rho_i[i] = si;
-  } else if (cx.r < 2 * D) {
-    const int j = cx.r - D;
-    T sr = 0, si = 0;
-    for (int k = 1; k < D; ++k) { sr += s.pp_r[k][j]; si += s.pp_i[k][j]; }
-    s.chi_r[j] = sr;
-    s.chi_i[j] = si;
-  }
-  wave_lds_sync();
-}
-
-// Per-stage scalars of the beam's right-hand side.
-template <typename T>
-struct StageCoef {
-  Q1T<T> k;
-  T sg, bc, H00, B00, lam, im;
-};
 
 // FP64: stage 0 first completes a pending hop at the stage values (the
 // step's start), from the coupling (p1/M) d21(q1) it evaluates anyway.  The
@@ -157,65 +64,6 @@ __device__ inline StageCoef<T> stage_coef(const DevModel &md, const QcleF &mf, H
   c.lam = (T)md.lam;
   c.B00 = -s.p[D] * c.sg * c.k.s3 - c.bc * c.k.s2;
   return c;
-}
-
-// Derivatives of one pair group (a, b) at the stage values v.
-template <int D, typename T>
-__device__ inline void grp_deriv(int a, int b, T ka, T kb, const StageCoef<T> &c, const T *v, const PgLds<D, T> &s,
-                                 T *d) {
-  const T lam = c.lam, im = c.im;
-  const T Ha = a == 0 ? c.H00 : ka, Hb = b == 0 ? c.H00 : kb;
-  // Zrr_ab' = (Zrp H)_ab + (Zrp H)_ba
-  T xr = v[kAbR] * Hb, xi = v[kAbI] * Hb;
-  if (b > 0) { xr += lam * s.rp_r[a][0]; xi += lam * s.rp_i[a][0]; }
-  else { xr += lam * s.rho_r[a]; xi += lam * s.rho_i[a]; }
-  T tr = v[kBaR] * Ha, ti = v[kBaI] * Ha;
-  if (a > 0) { tr += lam * s.rp_r[b][0]; ti += lam * s.rp_i[b][0]; }
-  else { tr += lam * s.rho_r[b]; ti += lam * s.rho_i[b]; }
-  d[kRrR] = xr + tr;
-  d[kRrI] = (xi + ti) + ((a == 0 && b == 0) ? c.B00 : (T)0);
-  // Zrp_ab' = (H Zpp)_ab - Zrr_ab / M,  Zrp_ba' = (H Zpp)_ba - Zrr_ba / M
-  T ur = Ha * v[kPpR], ui = Ha * v[kPpI];
-  if (a > 0) { ur += lam * s.pp_r[0][b]; ui += lam * s.pp_i[0][b]; }
-  else { ur += lam * s.chi_r[b]; ui += lam * s.chi_i[b]; }
-  T wr = Hb * v[kPpR], wi = Hb * v[kPpI];
-  if (b > 0) { wr += lam * s.pp_r[0][a]; wi += lam * s.pp_i[0][a]; }
-  else { wr += lam * s.chi_r[a]; wi += lam * s.chi_i[a]; }
-  d[kAbR] = ur - v[kRrR] * im;
-  d[kAbI] = ui - v[kRrI] * im;
-  d[kBaR] = wr - v[kRrR] * im;
-  d[kBaI] = wi - v[kRrI] * im;
-  // Zpp_ab' = -(Zrp_ba + Zrp_ab) / M
-  d[kPpR] = -(v[kBaR] + v[kAbR]) * im;
-  d[kPpI] = -(v[kBaI] + v[kAbI]) * im;
-}
-
-// Derivatives of the lane's coordinate X_c, P_c (c = lane index < m).
-template <int D, typename T>
-__device__ inline void xp_deriv(int cc, T kc, const StageCoef<T> &c, const PgLds<D, T> &s, T &dx, T &dp) {
-  const T lam = c.lam, im = c.im;
-  dx = 0;
-  dp = 0;
-  if (cc < D) {
-    dx = s.x[D + cc] * im;
-    if (cc == 0) {
-      T sp = 0;
-      for (int j = 1; j < D; ++j) sp += s.p[D + j];
-      dp = c.bc * c.k.s1 + c.H00 * s.p[D] + lam * sp;
-    } else {
-      dp = kc * s.p[D + cc] + lam * s.p[D];
-    }
-  } else if (cc < 2 * D) {
-    const int kk = cc - D;
-    if (kk == 0) {
-      T sq = 0;
-      for (int j = 1; j < D; ++j) sq += s.x[j];
-      dx = -(lam * sq + c.sg * c.k.s1);
-    } else {
-      dx = -(kc * s.x[kk] + lam * s.x[0]);
-    }
-    dp = -s.p[kk] * im;
-  }
 }
 
 // One Runge-Kutta stage of the FP64 path.  The stage values ys have been

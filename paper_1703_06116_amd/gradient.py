@@ -39,7 +39,7 @@ def population_and_tangent(theta, cfg, device="cuda"):
     """(sums, derivatives) for the run of cfg at theta: sums (4, 2) = (Re, Im) of sum c per
     component; derivatives (5, 4, 2) along each theta_j.  Host float64 tensors."""
     mdl = _model(theta, cfg)
-    st = shgb.State(cfg["n_beams"], 2, device=device)
+    st = shgb.State(cfg["n_beams"], 2 * cfg["d"], device=device)
     shgb.init_beams(mdl, _spec(theta, cfg), st, cfg["seed"])
     out = shgb.population_tangent(mdl, st, cfg["nsteps"], cfg["dt"], cfg["seed"]).cpu()
     return out[0, :, 0:2].clone(), out[:, :, 2:4].clone()

@@ -18,6 +18,8 @@ Workloads (two-level QCLE, Sec. 3.3, with nuclear mass 2000):
                    eps from {0.01, 0.02, 0.05} and beam counts log-uniform in
                    [2^12, 2^17] (about 2.3e6 beams in all), 500 steps of 0.5,
                    FP32 trajectories with FP64 phase, one batched launch.
+* ``qcle12d_grad`` the d = 12 model, 2^16 beams, 1000 steps, FP64: derivative of
+                   the final upper-surface population in (A, B, C, D, p_mean).
 """
 
 import numpy as np
@@ -34,6 +36,10 @@ CONFIGS = {
     "qcle12d_2p18": dict(d=12, eps=0.02, n_beams=2**18, nsteps=2000, dt=0.5, q_mean=-5.0, q_std=0.5,
                          p_dist="normal", p_a=20.0, p_b=1.0, comp0=1, seed=0x1703061160000003,
                          n_points=16384, lam=1e-3),
+    # pathwise derivative of the final upper-surface population in (A, B, C, D, p_mean)
+    "qcle12d_grad": dict(d=12, eps=0.02, n_beams=2**16, nsteps=1000, dt=0.5, q_mean=-5.0, q_std=0.5,
+                         p_dist="normal", p_a=20.0, p_b=1.0, comp0=1, seed=0x1703061160000005,
+                         n_points=0, lam=1e-3),
 }
 
 

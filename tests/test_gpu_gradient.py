@@ -1,5 +1,6 @@
-"""Pathwise derivative of the populations (m = 2 QCLE) with respect to
-theta = (A, B, C, D, p_mean), hop sequences frozen.
+"""Pathwise derivative of the populations (QCLE, m = 2 and the harmonic-bath
+model with m = 2d > 2) with respect to theta = (A, B, C, D, p_mean), hop
+sequences frozen.
 
 The tangent kernel is checked against central differences of the FP64 GPU
 path (Richardson-extrapolated over h and h/2: the phase S/eps makes the
@@ -21,8 +22,11 @@ from _parity import gpu_model, gpu_spec, oracle_model
 pytestmark = pytest.mark.gpu
 
 
-def crossing_cfg(n, nsteps, **kw):
-    return workloads.config("qcle1d_1e4", n_beams=n, nsteps=nsteps, q_mean=-2.5, q_std=0.3, p_a=30.0, **kw)
+def crossing_cfg(n, nsteps, d=1, **kw):
+    if d == 1:
+        return workloads.config("qcle1d_1e4", n_beams=n, nsteps=nsteps, q_mean=-2.5, q_std=0.3, p_a=30.0, **kw)
+    return workloads.config("qcle12d_2p18", d=d, bath_omega=workloads.bath_omega(d), n_beams=n, nsteps=nsteps,
+                            q_mean=-2.5, q_std=0.3, p_a=30.0, **kw)
 
 
 def shifted(cfg, j, h):
@@ -37,16 +41,17 @@ def shifted(cfg, j, h):
 
 
 def gpu_fp64_run(gpu, c):
-    st = gpu.State(c["n_beams"], 2)
+    st = gpu.State(c["n_beams"], 2 * c["d"])
     gpu.init_beams(gpu_model(c), gpu_spec(c), st, c["seed"])
     gpu.step_ensemble(gpu_model(c), st, c["nsteps"], c["dt"], c["seed"])
     sums = gpu.populations(gpu_model(c), st).cpu().numpy()
     return sums[:, 0] + 1j * sums[:, 1], st.nhop.cpu().numpy(), st.comp.cpu().numpy()
 
 
-@pytest.mark.parametrize("p_dist", ["normal", "uniform"])
-def test_tangent_matches_gpu_central_differences(gpu, p_dist):
-    cfg = crossing_cfg(2 * 256 + 37, 600, p_dist=p_dist, p_b=1.0 if p_dist == "normal" else 34.0)
+@pytest.mark.parametrize("d,p_dist,n,nsteps", [(1, "normal", 2 * 256 + 37, 600), (1, "uniform", 2 * 256 + 37, 600),
+                                                (2, "normal", 2 * 128 + 5, 500), (12, "normal", 2 * 64 + 3, 450)])
+def test_tangent_matches_gpu_central_differences(gpu, d, p_dist, n, nsteps):
+    cfg = crossing_cfg(n, nsteps, d=d, p_dist=p_dist, p_b=1.0 if p_dist == "normal" else 34.0)
     theta = gradient.theta_of(cfg)
     sums, deriv = gradient.population_and_tangent(theta, cfg)
     value = sums[:, 0].numpy() + 1j * sums[:, 1].numpy()
@@ -76,8 +81,9 @@ def oracle_populations(c):
     return p[:, 0] + 1j * p[:, 1], e.nhop.copy(), e.comp.copy()
 
 
-def test_tangent_matches_oracle_central_differences(gpu):
-    cfg = crossing_cfg(48, 300)
+@pytest.mark.parametrize("d,n,nsteps", [(1, 48, 300), (12, 24, 400)])
+def test_tangent_matches_oracle_central_differences(gpu, d, n, nsteps):
+    cfg = crossing_cfg(n, nsteps, d=d)
     theta = gradient.theta_of(cfg)
     _, deriv = gradient.population_and_tangent(theta, cfg)
     for j in range(5):
@@ -90,8 +96,9 @@ def test_tangent_matches_oracle_central_differences(gpu):
         assert np.abs(fd - tan).max() <= 1e-5 * np.abs(tan).max(), (j, fd, tan)
 
 
-def test_autograd_function_returns_the_tangent(gpu):
-    cfg = crossing_cfg(300, 400)
+@pytest.mark.parametrize("d", [1, 12])
+def test_autograd_function_returns_the_tangent(gpu, d):
+    cfg = crossing_cfg(300 if d == 1 else 70, 400, d=d)
     theta = torch.tensor(gradient.theta_of(cfg), dtype=torch.float64, requires_grad=True)
     pop = gradient.population(theta, cfg, component=0)
     pop.backward()
@@ -102,10 +109,11 @@ def test_autograd_function_returns_the_tangent(gpu):
     assert abs(pop.item()) < 5.0      # a Monte Carlo estimate with signed weights, not a probability
 
 
-def test_tangent_leaves_the_state_and_respects_the_mask(gpu):
-    c = crossing_cfg(257, 50)
+@pytest.mark.parametrize("d", [1, 12])
+def test_tangent_leaves_the_state_and_respects_the_mask(gpu, d):
+    c = crossing_cfg(257 if d == 1 else 37, 50, d=d)
     mdl = gpu_model(c)
-    st = gpu.State(c["n_beams"], 2)
+    st = gpu.State(c["n_beams"], 2 * d)
     gpu.init_beams(mdl, gpu_spec(c), st, c["seed"])
     before = st.f64.clone()
     out = torch.full((5, 4, 4), 7.0, dtype=torch.float64, device="cuda")
@@ -115,6 +123,6 @@ def test_tangent_leaves_the_state_and_respects_the_mask(gpu):
     o = out.cpu().numpy()
     assert (o[[0, 2, 3]] == 7.0).all() and not (o[[1, 4]] == 7.0).all()
     np.testing.assert_array_equal(o[1, :, :2], o[4, :, :2])                 # same values in every pass
-    empty = gpu.State(0, 2)
+    empty = gpu.State(0, 2 * d)
     z = gpu.population_tangent(mdl, empty, 10, 0.5, 1)
     assert (z.cpu().numpy() == 0).all()

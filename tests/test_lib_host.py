@@ -149,6 +149,36 @@ def test_validation_rejects_bad_arguments(binding):
     assert lib.shgb_philox(1, nul, nul, 5, nul) == EINVAL
 
 
+def test_tangent_validation(binding):
+    lib = binding._lib
+    nul, by = ctypes.c_void_p(0), ctypes.byref
+    EINVAL, EUNS, EWS = -1, -2, -4
+    buf = ctypes.c_void_p(0x10)
+    need = lib.shgb_population_tangent_workspace(100)
+    assert need > 0 and lib.shgb_population_tangent_workspace(-1) == -1
+    assert lib.shgb_population_tangent_workspace(10**6) >= lib.shgb_population_tangent_workspace(100)
+    st = _desc(binding, n=100)
+    mdl = _model(binding)
+
+    def call(model, desc, mask=1, work_bytes=need, out=buf, nsteps=10, dt=0.5):
+        return lib.shgb_population_tangent(by(model), by(desc), nsteps, dt, 1, mask, out, buf, work_bytes, nul, nul)
+
+    assert call(mdl, st, mask=0) == 0                                     # nothing asked: no launch
+    assert call(mdl, st, mask=1 << 5) == EINVAL
+    assert call(mdl, st, out=nul) == EINVAL
+    assert call(mdl, st, nsteps=-1) == EINVAL and call(mdl, st, dt=0.0) == EINVAL
+    assert call(mdl, st, work_bytes=need - 1) == EWS
+    mixed = _desc(binding, n=100)
+    mixed.precision = binding.PRECISION["mixed"]
+    mixed.f32 = 0x1000
+    assert call(mdl, mixed) == EUNS
+    m5 = _model(binding, d=5, lam=1e-3, bath_omega=(0.01, 0.01, 0.01, 0.01))
+    assert call(m5, _desc(binding, n=100, m=10)) == EUNS                  # d = 5 has no tangent kernel
+    m12 = _model(binding, d=12, lam=1e-3, bath_omega=tuple(0.002 + 0.001 * k for k in range(11)))
+    assert call(m12, _desc(binding, n=100, m=24), mask=0) == 0
+    assert call(m12, _desc(binding, n=100, m=24), work_bytes=need - 1) == EWS
+
+
 def test_batch_prepare_validation(binding):
     """Batch tables: tiles per instance, and the errors, without a device."""
     lib = binding._lib
