@@ -217,6 +217,70 @@ def run_batch(a):
     print(json.dumps(line), flush=True)
 
 
+def run_grad(a, c):
+    """The derivative workload: the ensemble sampled, then its populations and their derivatives
+    along all five theta directions (five tangent passes over every interval); beside it the plain
+    FP64 forward run of the same ensemble (init, step, populations)."""
+    import numpy as np
+    import torch
+    from paper_1703_06116_amd import shgb
+
+    N, nsteps, dt, seed, m = c["n_beams"], c["nsteps"], c["dt"], c["seed"], 2 * c["d"]
+    mdl = shgb.make_model(c["d"], c["mass"], c["eps"], c["A"], c["B"], c["C"], c["D"], c["lam"], c["bath_omega"])
+    spec = shgb.make_init_spec(c["q_mean"], c["q_std"], c["p_dist"], c["p_a"], c["p_b"], c["comp0"])
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    st = shgb.State(N, m, device=dev)
+    out = torch.zeros((5, 4, 4), dtype=torch.float64, device=dev)
+    work = torch.empty(max(shgb.population_tangent_workspace(N), 8), dtype=torch.uint8, device=dev)
+    diag = shgb.new_diag(dev)
+    pops = torch.empty((4, 5), dtype=torch.float64, device=dev)
+    pop_work = torch.empty(max(shgb.populations_workspace(N, m), 8), dtype=torch.uint8, device=dev)
+
+    def grad_step():
+        shgb.init_beams(mdl, spec, st, seed)
+        shgb.population_tangent(mdl, st, nsteps, dt, seed, out=out, work=work, diag=diag)
+
+    def forward_step():
+        shgb.init_beams(mdl, spec, st, seed)
+        shgb.step_ensemble(mdl, st, nsteps, dt, seed)
+        shgb.populations(mdl, st, out=pops, work=pop_work)
+
+    def timed(fn):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / a.steps
+
+    ms_grad = timed(grad_step)
+    o = out.cpu().numpy()
+    ms_fwd = timed(forward_step)
+    p = pops.cpu().numpy()
+    value_diff = float(np.abs(o[0, :, 0] - p[:, 0]).max() / max(np.abs(p[:, 0]).sum(), 1e-300))
+    line = {
+        "metric": METRIC, "value": N * nsteps / (ms_grad / 1e3), "unit": "beam-steps/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_grad, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (value, derivative) pairs", "data": "synthetic",
+        "config": {"workload": a.config, "model": f"qcle-two-level-{c['d']}d", "n_beams": N, "intervals": nsteps,
+                   "dt": dt, "eps": c["eps"], "phase_space_dim": m, "directions": 5,
+                   "parallelism": "none (1 GPU)"},
+        "note": "value counts each beam-step once for all five directions (five tangent passes)",
+        "forward_fp64_ms_per_step": ms_fwd,
+        "gradient_over_forward": ms_grad / ms_fwd,
+        "upper_population": float(o[0, 0, 0] / N),
+        "d_upper_population": {n: float(o[j, 0, 2] / N) for j, n in enumerate(("A", "B", "C", "D", "p_mean"))},
+        "tangent_values_vs_forward_rel": value_diff,
+        "diag": {n: int(v) for n, v in zip(shgb.DIAG_NAMES, diag.cpu().numpy() // max(a.steps + a.warmup, 1))},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.copy_probe:
@@ -234,6 +298,8 @@ def main():
     if a.config in workloads.BATCH:
         return run_batch(a)
     c = workloads.config(a.config)
+    if a.config in workloads.GRADIENT:
+        return run_grad(a, c)
     N, nsteps, dt, seed, m = c["n_beams"], c["nsteps"], c["dt"], c["seed"], 2 * c["d"]
     if m not in (2, 24):
         raise SystemExit("bench.py drives the m = 2 and m = 24 workloads")

@@ -303,6 +303,10 @@ def reconstruct(model, state, points, out=None, work=None, stream=None):
 THETA_NAMES = ("A", "B", "C", "D", "p_mean")
 
 
+def population_tangent_workspace(n):
+    return int(_lib.shgb_population_tangent_workspace(int(n)))
+
+
 def population_tangent(model, state, nsteps, dt, seed, dirs=range(5), out=None, work=None, diag=None,
                        stream=None):
     """Population sums and their derivatives along theta_j (see include/shgb.h): a (5, 4, 4)
@@ -310,7 +314,7 @@ def population_tangent(model, state, nsteps, dt, seed, dirs=range(5), out=None, 
     dev = state.f64.device
     if out is None:
         out = torch.zeros((5, SHGB_NCOMP, 4), dtype=torch.float64, device=dev)
-    nb = int(_lib.shgb_population_tangent_workspace(state.n))
+    nb = population_tangent_workspace(state.n)
     if work is None:
         work = torch.empty(max(nb, 8), dtype=torch.uint8, device=dev)
     mask = 0

@@ -43,6 +43,9 @@ CONFIGS = {
 }
 
 
+# workloads whose bench step is the derivative of the populations
+GRADIENT = ("qcle12d_grad",)
+
 BATCH = {
     "batch64_d12": dict(n_inst=64, d=12, C=(0.002, 0.01), eps=(0.01, 0.02, 0.05), beams=(2**12, 2**17),
                         nsteps=500, dt=0.5, draw_seed=1703061164, seed0=0x1703061160000004),
