@@ -12,26 +12,33 @@
 //           -X~^T Z X~/(2 eps) - i P.X~/eps ),
 // so all exponents of a beam tile and a point tile form one dense real
 // GEMM [beams x 328] x [328 x points] for Re and for Im (F = 325 padded to
-// 328).  It runs on v_mfma_f64_16x16x4_f64; the epilogue multiplies
+// 328).  It runs on v_mfma_f64_4x4x4f64 (four 4 x 4 blocks per instruction,
+// which issues at the full FP64 matrix rate on gfx950, where the 16 x 16
+// form reaches about half of it); the epilogue multiplies
 // exp(Re) (cos Im + i sin Im) by the beam weight exp(omega) A exp(iS/eps)
-// and sums per component and point.  Blocks own 128 points and a chunk of
+// and sums per component and point.  Blocks own 64 points and a chunk of
 // beams (64 per tile); partial sums per chunk are added in chunk order.
 #include "device.h"
 
 namespace shgb {
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
 constexpr int RM = 24;
 constexpr int RT = RM * (RM + 1) / 2;  // 300 quadratic features
 constexpr int RF = RT + RM + 1;        // 325
-constexpr int RFP = 328;               // padded to a multiple of the slab
-constexpr int RBK = 64;                // beams per block tile
-constexpr int RBQ = 128;               // points per block tile
-constexpr int RKS = 8;                 // features per LDS slab (two MFMA k-steps)
-constexpr int RNSLAB = RFP / RKS;      // 41
+#ifndef SHGB_RM_SLAB
+#define SHGB_RM_SLAB 8
+#endif
+constexpr int RKS = SHGB_RM_SLAB;      // features per LDS slab (RKS / 4 MFMA k-steps)
+constexpr int RFP = (RF + RKS - 1) / RKS * RKS;  // padded to a multiple of the slab
+constexpr int RNSLAB = RFP / RKS;
+constexpr int RBK = 64;                // beams per block tile (16 per wave)
+constexpr int RBQ = 64;                // points per block tile
 constexpr int RTHREADS = 256;
-constexpr int64_t RMAXCHUNK = 8;
+static_assert(RKS % 8 == 0 && RBK == 64 && RBQ == 64 && RTHREADS == 256,
+              "the slab copy: four waves, rows of 64 doubles, two rows per instruction");
+constexpr int64_t RBLOCKS = 2048;      // aim: 8 workgroups per CU over the launch
+constexpr int64_t RMAXCHUNK = 512;
+constexpr int kBufferFlags = 0x00020000;   // word 3 of a raw (untyped) buffer resource on gfx9
 
 struct RmLayout {
   int64_t NB, QP, n_chunks, tiles_per_chunk, pt_tiles;
@@ -46,9 +53,9 @@ RmLayout rm_layout(int64_t n, int64_t Q) {
   if (L.QP == 0) L.QP = RBQ;
   L.pt_tiles = L.QP / RBQ;
   const int64_t beam_tiles = L.NB / RBK;
-  // enough blocks to fill the chip: at least ~1024 (4 per CU) when the work allows
-  int64_t nc = (1024 + L.pt_tiles - 1) / L.pt_tiles;
-  if (nc > RMAXCHUNK * 64) nc = RMAXCHUNK * 64;
+  // enough blocks to fill the chip several times when the work allows
+  int64_t nc = (RBLOCKS + L.pt_tiles - 1) / L.pt_tiles;
+  if (nc > RMAXCHUNK) nc = RMAXCHUNK;
   if (nc > beam_tiles) nc = beam_tiles;
   if (nc < 1) nc = 1;
   L.tiles_per_chunk = (beam_tiles + nc - 1) / nc;
@@ -169,134 +176,157 @@ rm_beams_kernel(DevModel md, const TS *__restrict__ fs, const double *__restrict
 }
 
 // Dense exponent GEMM on the matrix cores with the field epilogue fused.
-// Waves: w = 2 wy + wx; wave tile 32 beams (wy) x 64 points (wx) = 2 x 4
-// MFMA tiles of 16 x 16, for Re and for Im.  v_mfma_f64_16x16x4_f64 lane
-// layout (checked on gfx950): A[i][k] from lane i + 16k, B[k][j] from lane
-// j + 16k, D[i][j] in lane j + 16 (i % 4), element i / 4.  After each beam tile the epilogue
-// values are summed over the tile's rows (in-lane, then across the four lane
-// groups) and added to per-point accumulators in LDS.
-__global__ void __launch_bounds__(RTHREADS)
+// Wave w owns beams 16 w .. 16 w + 15 of the block tile and all 64 points,
+// for Re and for Im.  v_mfma_f64_4x4x4f64 lane layout (checked on gfx950):
+// block b, A_b[i][k] from lane 16k + 4b + i, B_b[k][j] from lane
+// 16k + 4b + j, D_b[i][j] in lane 16i + 4b + j.  With A the same in all four
+// blocks (four beams) and block b taking points 4b..4b+3 of a 16-point
+// group, one instruction gives 4 beams x 16 points, lane l holding beam
+// l / 16 and point l % 16; a wave tile is 4 beam quads x 4 point groups.
+// Registers (at most 168 per lane) and LDS (two slab buffers, 42 KB in all)
+// let three workgroups share a CU, so one's slab barriers and epilogue
+// (exp, sincos) overlap the others' matrix work.  After each beam
+// tile the epilogue values are summed over the lane's beams, then across
+// the four lane groups, and added to per-point accumulators in LDS.
+__global__ void __launch_bounds__(RTHREADS) __attribute__((amdgpu_waves_per_eu(3)))
 rm_gemm_kernel(const double *__restrict__ wr, const double *__restrict__ wi, const double *__restrict__ wk,
                const double *__restrict__ wc, const double *__restrict__ phi, int64_t NB, int64_t QP, int64_t Q,
                int64_t tiles_per_chunk, double *__restrict__ partial) {
-  __shared__ double Ws[2][2][RKS][RBK];   // [buffer][re/im][feature][beam]
-  __shared__ double Ps[2][RKS][RBQ];      // [buffer][feature][point]
+  // the two slab buffers as separate objects, so that reads of one are not
+  // ordered behind the copies into the other
+  __shared__ double Ws0[2][RKS][RBK], Ws1[2][RKS][RBK];   // [re/im][feature][beam]
+  __shared__ double Ps0[RKS][RBQ], Ps1[RKS][RBQ];         // [feature][point]
   __shared__ double Bw[RBK][3];           // beam weight re, im, component
-  __shared__ double Acc[2][2 * SHGB_NCOMP][RBQ];  // [wave row][comp re/im][point]
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wy = w >> 1, wx = w & 1;
-  const int g = lane >> 4, li = lane & 15;
+  __shared__ double Acc[4][2 * SHGB_NCOMP][RBQ];  // [wave][comp re/im][point]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = lane >> 4, li = lane & 15, i4 = lane & 3;
   const int64_t q0 = (int64_t)blockIdx.x * RBQ;
   const int64_t kt0 = (int64_t)blockIdx.y * tiles_per_chunk;
-  for (int e = tid; e < 2 * 2 * SHGB_NCOMP * RBQ; e += RTHREADS) (&Acc[0][0][0])[e] = 0.0;
-  // this thread's share of each slab: 4 W values and 4 Phi values
-  int64_t woff[4], poff[4];
-  const double *wsrc[4];
+  for (int e = tid; e < 4 * 2 * SHGB_NCOMP * RBQ; e += RTHREADS) (&Acc[0][0][0])[e] = 0.0;
+  // Slabs are copied from global memory straight into LDS (two buffers) by
+  // 16-byte buffer loads with an LDS destination: lane l of a wave writes
+  // bytes [16 l, 16 l + 16) from the wave's LDS base (checked on gfx950), so
+  // one instruction fills two 64-double rows of a slab.  The W slab has
+  // 2 RKS rows (Re, Im), the Phi slab RKS; each wave copies RKS / 4 W row
+  // pairs and RKS / 8 Phi row pairs.  The copy of slab s + 1 runs under the
+  // matrix work of slab s.
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  const uint32_t wvo = (uint32_t)(((int64_t)(lane >> 5) * NB + 2 * (lane & 31)) * 8);
+  const uint32_t pvo = (uint32_t)(((int64_t)(lane >> 5) * QP + 2 * (lane & 31)) * 8);
+  auto rsrc = [](const double *base, int64_t n_after) {
+    const int64_t bytes = n_after * 8;
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, (int)(bytes < 0x7fffffff ? bytes : 0x7fffffff),
+                                             kBufferFlags);
+  };
+  typedef __attribute__((address_space(3))) void *lds_ptr;
+  auto copy_slab = [&](int64_t k0, int s, double (&Wd)[2][RKS][RBK], double (&Pd)[RKS][RBQ]) {
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int e = tid + RTHREADS * u;  // 0..1023
-    wsrc[u] = (e >> 9) ? wi : wr;
-    woff[u] = (int64_t)((e >> 6) & 7) * NB + (e & 63);
-    poff[u] = (int64_t)(e >> 7) * QP + q0 + (e & 127);
-  }
+    for (int h = 0; h < RKS / 4; ++h) {
+      const int j = wu * (RKS / 4) + h, part = j / (RKS / 2), f0 = 2 * (j % (RKS / 2));
+      const int64_t fw = (int64_t)(s * RKS + f0) * NB + k0;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc((part ? wi : wr) + fw, (int64_t)RFP * NB - fw),
+                                               (lds_ptr)&Wd[part][f0][0], 16, wvo, 0, 0, 0);
+    }
+#pragma unroll
+    for (int h = 0; h < RKS / 8; ++h) {
+      const int f0 = 2 * (wu * (RKS / 8) + h);
+      const int64_t fp = (int64_t)(s * RKS + f0) * QP + q0;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc(phi + fp, (int64_t)RFP * QP - fp), (lds_ptr)&Pd[f0][0], 16,
+                                               pvo, 0, 0, 0);
+    }
+  };
   for (int64_t kt = kt0; kt < kt0 + tiles_per_chunk; ++kt) {
     const int64_t k0 = kt * RBK;
     if (k0 >= NB) break;  // uniform across the block
-    dbl4 are[2][4], aim[2][4];
+    double are[4][4], aim[4][4];   // [beam quad][point group]
 #pragma unroll
-    for (int bt = 0; bt < 2; ++bt)
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int pt = 0; pt < 4; ++pt) { are[bt][pt] = dbl4{0, 0, 0, 0}; aim[bt][pt] = dbl4{0, 0, 0, 0}; }
-    double rw[4], rp[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) { rw[u] = wsrc[u][woff[u] + k0]; rp[u] = phi[poff[u]]; }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = tid + RTHREADS * u;
-      Ws[0][e >> 9][(e >> 6) & 7][e & 63] = rw[u];
-      Ps[0][e >> 7][e & 127] = rp[u];
-    }
+      for (int v = 0; v < 4; ++v) { are[u][v] = 0.0; aim[u][v] = 0.0; }
+    copy_slab(k0, 0, Ws0, Ps0);
     if (tid < RBK) {
       Bw[tid][0] = wk[2 * (k0 + tid)];
       Bw[tid][1] = wk[2 * (k0 + tid) + 1];
       Bw[tid][2] = wc[k0 + tid];
     }
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's copies have landed
     __syncthreads();
-    for (int s = 0; s < RNSLAB; ++s) {
-      const int buf = s & 1;
-      const bool more = s + 1 < RNSLAB;
-      if (more) {
-        const int64_t fw = (int64_t)(s + 1) * RKS * NB + k0, fp = (int64_t)(s + 1) * RKS * QP;
+    // slab s from (Wc, Pc) while slab s + 1 is copied into (Wn, Pn)
+    auto slab = [&](int s, const double (&Wc)[2][RKS][RBK], const double (&Pc)[RKS][RBQ],
+                    double (&Wn)[2][RKS][RBK], double (&Pn)[RKS][RBQ]) {
+      if (s + 1 < RNSLAB) copy_slab(k0, s + 1, Wn, Pn);
+      // every operand of the slab from LDS first, then the slab's MFMAs back to back
+      double bq[RKS / 4][4], aqr[RKS / 4][4], aqi[RKS / 4][4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) { rw[u] = wsrc[u][woff[u] + fw]; rp[u] = phi[poff[u] + fp]; }
-      }
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
+      for (int ks = 0; ks < RKS / 4; ++ks) {
         const int f = 4 * ks + g;
-        double bfr[4];
 #pragma unroll
-        for (int pt = 0; pt < 4; ++pt) bfr[pt] = Ps[buf][f][64 * wx + 16 * pt + li];
-#pragma unroll
-        for (int bt = 0; bt < 2; ++bt) {
-          const double ar = Ws[buf][0][f][32 * wy + 16 * bt + li];
-          const double ai = Ws[buf][1][f][32 * wy + 16 * bt + li];
-#pragma unroll
-          for (int pt = 0; pt < 4; ++pt) {
-            are[bt][pt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bfr[pt], are[bt][pt], 0, 0, 0);
-            aim[bt][pt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bfr[pt], aim[bt][pt], 0, 0, 0);
-          }
-        }
-      }
-      if (more) {
+        for (int v = 0; v < 4; ++v) bq[ks][v] = Pc[f][16 * v + li];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int e = tid + RTHREADS * u;
-          Ws[buf ^ 1][e >> 9][(e >> 6) & 7][e & 63] = rw[u];
-          Ps[buf ^ 1][e >> 7][e & 127] = rp[u];
+          aqr[ks][u] = Wc[0][f][16 * w + 4 * u + i4];
+          aqi[ks][u] = Wc[1][f][16 * w + 4 * u + i4];
         }
       }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int ks = 0; ks < RKS / 4; ++ks)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            are[u][v] = __builtin_amdgcn_mfma_f64_4x4x4f64(aqr[ks][u], bq[ks][v], are[u][v], 0, 0, 0);
+            aim[u][v] = __builtin_amdgcn_mfma_f64_4x4x4f64(aqi[ks][u], bq[ks][v], aim[u][v], 0, 0, 0);
+          }
+      // the next slab's copy must have landed (this wave's part) before the
+      // barrier that publishes it; keep both behind the matrix work
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
+    };
+    for (int s = 0; s < RNSLAB; s += 2) {
+      slab(s, Ws0, Ps0, Ws1, Ps1);
+      if (s + 1 < RNSLAB) slab(s + 1, Ws1, Ps1, Ws0, Ps0);
     }
-    // epilogue, one point tile at a time: w_k exp(E) per (beam, point), summed over the
-    // lane's 8 beams per component, then over the four lane groups
+    // epilogue, one point group at a time: w_k exp(E) per (beam, point), summed over the
+    // lane's 4 beams per component, then over the four lane groups
 #pragma unroll
     for (int pt = 0; pt < 4; ++pt) {
       double v[2 * SHGB_NCOMP];
 #pragma unroll
       for (int c = 0; c < 2 * SHGB_NCOMP; ++c) v[c] = 0.0;
 #pragma unroll
-      for (int bt = 0; bt < 2; ++bt)
+      for (int u = 0; u < 4; ++u) {
+        const int kb = 16 * w + 4 * u + g;
+        const double e = exp(are[u][pt]);
+        double sn, cs;
+        sincos(aim[u][pt], &sn, &cs);
+        const double gr = e * cs, gi = e * sn;
+        const double bwr = Bw[kb][0], bwi = Bw[kb][1];
+        const int cc = (int)Bw[kb][2];
+        const double vr = bwr * gr - bwi * gi, vi = bwr * gi + bwi * gr;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int kb = 32 * wy + 16 * bt + g + 4 * r;
-          const double e = exp(are[bt][pt][r]);
-          double sn, cs;
-          sincos(aim[bt][pt][r], &sn, &cs);
-          const double gr = e * cs, gi = e * sn;
-          const double bwr = Bw[kb][0], bwi = Bw[kb][1];
-          const int cc = (int)Bw[kb][2];
-          const double vr = bwr * gr - bwi * gi, vi = bwr * gi + bwi * gr;
-#pragma unroll
-          for (int c = 0; c < SHGB_NCOMP; ++c) {
-            v[2 * c] += (cc == c) ? vr : 0.0;
-            v[2 * c + 1] += (cc == c) ? vi : 0.0;
-          }
+        for (int c = 0; c < SHGB_NCOMP; ++c) {
+          v[2 * c] += (cc == c) ? vr : 0.0;
+          v[2 * c + 1] += (cc == c) ? vi : 0.0;
         }
+      }
 #pragma unroll
       for (int c = 0; c < 2 * SHGB_NCOMP; ++c) {
         double x = v[c];
         x += __shfl_xor(x, 16, 64);
         x += __shfl_xor(x, 32, 64);
-        if (g == 0) Acc[wy][c][64 * wx + 16 * pt + li] += x;
+        if (g == 0) Acc[w][c][16 * pt + li] += x;
       }
     }
     __syncthreads();  // Bw and the slab buffers are rewritten by the next tile
   }
-  // add the two wave rows and write this chunk's partial sums
+  // add the four wave rows and write this chunk's partial sums
   double *dst = partial + (int64_t)blockIdx.y * SHGB_NCOMP * Q * 2;
   for (int e = tid; e < 2 * SHGB_NCOMP * RBQ; e += RTHREADS) {
     const int c = e / RBQ, qq = e % RBQ;
     const int64_t q = q0 + qq;
-    if (q < Q) dst[((c >> 1) * Q + q) * 2 + (c & 1)] = Acc[0][c][qq] + Acc[1][c][qq];
+    if (q < Q) dst[((c >> 1) * Q + q) * 2 + (c & 1)] = (Acc[0][c][qq] + Acc[1][c][qq]) + (Acc[2][c][qq] + Acc[3][c][qq]);
   }
 }
 
