@@ -9,6 +9,11 @@
 // reads).  The component of the current beam is uniform across the block, so
 // the accumulator select is a uniform branch.  Chunks write partial sums;
 // a second kernel adds them in chunk order (bitwise reproducible).
+// A term whose real exponent is below the range of exp (the exponential is
+// exactly +0 in the working precision) adds exactly zero when its phase and
+// the beam weight are finite, so exp, sincos and the accumulation are
+// skipped for it; a wavefront in which every lane is in that case skips the
+// whole evaluation (far beams are the common case on a field grid).
 #include "device.h"
 
 namespace shgb {
@@ -16,6 +21,10 @@ namespace shgb {
 constexpr int kRecThreads = 256;
 constexpr int kRecTile = 256;          // beams per LDS tile
 constexpr int64_t kRecMaxChunks = 128;
+// below these arguments exp (FP64) and the hardware exp2 (FP32) return +0:
+// e^x < 2^-1075 for x < -745.14; 2^x < 2^-150 for x < -150
+constexpr double kExpZero64 = -745.2;
+constexpr float kExp2Zero32 = -151.0f;
 
 struct RecTiling {
   int64_t chunk, n_chunks, pt_tiles;
@@ -95,11 +104,12 @@ recon_m2_kernel(DevModel md, const double *__restrict__ f, const double *__restr
       const double re = -(rec[RC_R11][t] * y11 + rec[RC_R12][t] * y12 + rec[RC_R22][t] * y22);
       const double im = rec[RC_P1][t] * y1 + rec[RC_P2][t] * y2 -
                         (rec[RC_I11][t] * y11 + rec[RC_I12][t] * y12 + rec[RC_I22][t] * y22);
+      const double wr = rec[RC_WRE][t], wi = rec[RC_WIM][t];
+      if (re < kExpZero64 && fabs(im) < INFINITY && fabs(wr) < INFINITY && fabs(wi) < INFINITY) continue;
       const double g = exp(re);
       double sn, cs;
       sincos(im, &sn, &cs);
       const double gr = g * cs, gi = g * sn;
-      const double wr = rec[RC_WRE][t], wi = rec[RC_WIM][t];
       const double vr = wr * gr - wi * gi, vi = wr * gi + wi * gr;
       switch (rcomp[t]) {  // uniform across the block
         case 0: acc[0][0] += vr; acc[0][1] += vi; break;
@@ -171,10 +181,11 @@ recon_m2_mixed_kernel(DevModel md, const float *__restrict__ f, const double *__
       const float re2 = -(rec[RC_R11][t] * y11 + rec[RC_R12][t] * y12 + rec[RC_R22][t] * y22);
       float turns = rec[RC_P1][t] * y1 + rec[RC_P2][t] * y2 -
                     (rec[RC_I11][t] * y11 + rec[RC_I12][t] * y12 + rec[RC_I22][t] * y22);
+      const float wr = rec[RC_WRE][t], wi = rec[RC_WIM][t];
+      if (re2 < kExp2Zero32 && fabsf(turns) < INFINITY && fabsf(wr) < INFINITY && fabsf(wi) < INFINITY) continue;
       turns = turns - rintf(turns);
       const float g = __builtin_amdgcn_exp2f(re2);
       const float gr = g * __builtin_amdgcn_cosf(turns), gi = g * __builtin_amdgcn_sinf(turns);
-      const float wr = rec[RC_WRE][t], wi = rec[RC_WIM][t];
       const double vr = (double)(wr * gr - wi * gi), vi = (double)(wr * gi + wi * gr);
       switch (rcomp[t]) {  // uniform across the block
         case 0: acc[0][0] += vr; acc[0][1] += vi; break;
