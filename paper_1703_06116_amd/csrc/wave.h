@@ -26,13 +26,18 @@ struct PG {
   static_assert(M <= LPB, "X and P need one lane per coordinate");
 };
 
-// One beam's exchange area (T: the stage precision).
+// One beam's exchange area (T: the stage precision).  Matrix rows are
+// padded to D + 1 entries so that a column read by D lanes does not fall
+// into one LDS bank.  sx = sum_{j>0} X_j (bath positions), sp = sum_{j>0}
+// P_{d+j}, the two sums the coordinate derivatives need.
 template <int D, typename T>
 struct PgLds {
-  T rp_r[D][D], rp_i[D][D];   // Zrp
-  T pp_r[D][D], pp_i[D][D];   // Zpp (both triangles)
+  static constexpr int W = D + 1;
+  T rp_r[D][W], rp_i[D][W];   // Zrp
+  T pp_r[D][W], pp_i[D][W];   // Zpp (both triangles)
   T rho_r[D], rho_i[D], chi_r[D], chi_i[D];
   T x[2 * D], p[2 * D];
+  T sx, sp;
 };
 
 // Values of one pair group: Zrr_ab, Zrp_ab, Zrp_ba, Zpp_ab (re, im).
@@ -94,18 +99,25 @@ __device__ inline void pg_publish(const PgCtx<D, LPB, TC> &cx, const PgY<D, LPB,
   }
   if (cx.r < 2 * D) { s.x[cx.r] = y.x; s.p[cx.r] = y.p; }
   wave_lds_sync();
-  if (cx.r < D) {
-    const int i = cx.r;
+  // 2D + 1 sums over k = 1 .. D - 1, one per lane (round robin), all by the
+  // same loop: task i < D: rho_i (row i of Zrp); D <= t < 2D: chi_j (column
+  // j of Zpp); t = 2D: sx and sp
+  for (int t = cx.r; t < 2 * D + 1; t += LPB) {
+    const T *br, *bi;
+    T *orr, *oi;
+    int stride;
+    if (t < D) {
+      br = &s.rp_r[t][0]; bi = &s.rp_i[t][0]; stride = 1; orr = &s.rho_r[t]; oi = &s.rho_i[t];
+    } else if (t < 2 * D) {
+      br = &s.pp_r[0][t - D]; bi = &s.pp_i[0][t - D]; stride = PgLds<D, T>::W; orr = &s.chi_r[t - D];
+      oi = &s.chi_i[t - D];
+    } else {
+      br = &s.x[0]; bi = &s.p[D]; stride = 1; orr = &s.sx; oi = &s.sp;
+    }
     T sr = 0, si = 0;
-    for (int k = 1; k < D; ++k) { sr += s.rp_r[i][k]; si += s.rp_i[i][k]; }
-    s.rho_r[i] = sr;
-    s.rho_i[i] = si;
-  } else if (cx.r < 2 * D) {
-    const int j = cx.r - D;
-    T sr = 0, si = 0;
-    for (int k = 1; k < D; ++k) { sr += s.pp_r[k][j]; si += s.pp_i[k][j]; }
-    s.chi_r[j] = sr;
-    s.chi_i[j] = si;
+    for (int k = 1; k < D; ++k) { sr += br[k * stride]; si += bi[k * stride]; }
+    *orr = sr;
+    *oi = si;
   }
   wave_lds_sync();
 }
@@ -123,22 +135,27 @@ __device__ inline void grp_deriv(int a, int b, T ka, T kb, const StageCoef<T> &c
                                  T *d) {
   const T lam = c.lam, im = c.im;
   const T Ha = a == 0 ? c.H00 : ka, Hb = b == 0 ? c.H00 : kb;
+  // the cross-lane operands, by address select rather than branches
+  const T *xrp = b > 0 ? &s.rp_r[a][0] : &s.rho_r[a], *xip = b > 0 ? &s.rp_i[a][0] : &s.rho_i[a];
+  const T *trp = a > 0 ? &s.rp_r[b][0] : &s.rho_r[b], *tip = a > 0 ? &s.rp_i[b][0] : &s.rho_i[b];
+  const T *urp = a > 0 ? &s.pp_r[0][b] : &s.chi_r[b], *uip = a > 0 ? &s.pp_i[0][b] : &s.chi_i[b];
+  const T *wrp = b > 0 ? &s.pp_r[0][a] : &s.chi_r[a], *wip = b > 0 ? &s.pp_i[0][a] : &s.chi_i[a];
   // Zrr_ab' = (Zrp H)_ab + (Zrp H)_ba
   T xr = v[kAbR] * Hb, xi = v[kAbI] * Hb;
-  if (b > 0) { xr += lam * s.rp_r[a][0]; xi += lam * s.rp_i[a][0]; }
-  else { xr += lam * s.rho_r[a]; xi += lam * s.rho_i[a]; }
+  xr += lam * *xrp;
+  xi += lam * *xip;
   T tr = v[kBaR] * Ha, ti = v[kBaI] * Ha;
-  if (a > 0) { tr += lam * s.rp_r[b][0]; ti += lam * s.rp_i[b][0]; }
-  else { tr += lam * s.rho_r[b]; ti += lam * s.rho_i[b]; }
+  tr += lam * *trp;
+  ti += lam * *tip;
   d[kRrR] = xr + tr;
   d[kRrI] = (xi + ti) + ((a == 0 && b == 0) ? c.B00 : (T)0);
   // Zrp_ab' = (H Zpp)_ab - Zrr_ab / M,  Zrp_ba' = (H Zpp)_ba - Zrr_ba / M
   T ur = Ha * v[kPpR], ui = Ha * v[kPpI];
-  if (a > 0) { ur += lam * s.pp_r[0][b]; ui += lam * s.pp_i[0][b]; }
-  else { ur += lam * s.chi_r[b]; ui += lam * s.chi_i[b]; }
+  ur += lam * *urp;
+  ui += lam * *uip;
   T wr = Hb * v[kPpR], wi = Hb * v[kPpI];
-  if (b > 0) { wr += lam * s.pp_r[0][a]; wi += lam * s.pp_i[0][a]; }
-  else { wr += lam * s.chi_r[a]; wi += lam * s.chi_i[a]; }
+  wr += lam * *wrp;
+  wi += lam * *wip;
   d[kAbR] = ur - v[kRrR] * im;
   d[kAbI] = ui - v[kRrI] * im;
   d[kBaR] = wr - v[kRrR] * im;
@@ -148,31 +165,25 @@ __device__ inline void grp_deriv(int a, int b, T ka, T kb, const StageCoef<T> &c
   d[kPpI] = -(v[kBaI] + v[kAbI]) * im;
 }
 
-// Derivatives of the lane's coordinate X_c, P_c (c = lane index < m).
+// Derivatives of the lane's coordinate X_c, P_c (c = lane index; lanes
+// c >= m get zeros).  Both alternatives are formed and one is selected.
 template <int D, typename T>
 __device__ inline void xp_deriv(int cc, T kc, const StageCoef<T> &c, const PgLds<D, T> &s, T &dx, T &dp) {
   const T lam = c.lam, im = c.im;
-  dx = 0;
-  dp = 0;
+  const int i = cc < D ? cc : (cc < 2 * D ? cc - D : 0);   // the coordinate index
   if (cc < D) {
-    dx = s.x[D + cc] * im;
-    if (cc == 0) {
-      T sp = 0;
-      for (int j = 1; j < D; ++j) sp += s.p[D + j];
-      dp = c.bc * c.k.s1 + c.H00 * s.p[D] + lam * sp;
-    } else {
-      dp = kc * s.p[D + cc] + lam * s.p[D];
-    }
+    dx = s.x[D + i] * im;
+    const T dp0 = c.bc * c.k.s1 + c.H00 * s.p[D] + lam * s.sp;
+    const T dpk = kc * s.p[D + i] + lam * s.p[D];
+    dp = i == 0 ? dp0 : dpk;
   } else if (cc < 2 * D) {
-    const int kk = cc - D;
-    if (kk == 0) {
-      T sq = 0;
-      for (int j = 1; j < D; ++j) sq += s.x[j];
-      dx = -(lam * sq + c.sg * c.k.s1);
-    } else {
-      dx = -(kc * s.x[kk] + lam * s.x[0]);
-    }
-    dp = -s.p[kk] * im;
+    const T dx0 = -(lam * s.sx + c.sg * c.k.s1);
+    const T dxk = -(kc * s.x[i] + lam * s.x[0]);
+    dx = i == 0 ? dx0 : dxk;
+    dp = -s.p[i] * im;
+  } else {
+    dx = 0;
+    dp = 0;
   }
 }
 
