@@ -75,7 +75,7 @@ __host__ __device__ inline void stage2(const DevModel &md, HopCtx &hc, Counters 
 __host__ __device__ inline void rk4_2(const DevModel &md, HopCtx &hc, Counters &cnt, const Ode2 &y, double h,
                                       Ode2 &out) {
   Ode2 ys = y;
-  const double h6 = h / 6.0;
+  const double h6 = h * (1.0 / 6.0);
 #pragma unroll
   for (int st = 0; st < 4; ++st) stage2(md, hc, cnt, y, ys, out, st, st == 2 ? h : 0.5 * h, h6);
 }

@@ -109,7 +109,7 @@ __device__ inline void pg_rk4(const DevModel &md, const QcleF &mf, HopCtx &hc, C
                               const PgCtx<D, LPB, double> &cx, const PgY<D, LPB, double> &y, double h,
                               PgY<D, LPB, double> &out, PgLds<D, double> &s) {
   PgY<D, LPB, double> ys = y;
-  const double h6 = h / 6.0;
+  const double h6 = h * (1.0 / 6.0);
   const double cs[3] = {0.5 * h, 0.5 * h, h};
 #pragma unroll 1
   for (int st = 0; st < 4; ++st) {

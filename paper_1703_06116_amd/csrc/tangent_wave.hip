@@ -88,7 +88,7 @@ template <int D>
 __device__ inline void pg_rk4_du(const QcleDu &p, double lam, HopDu &hc, Counters &cnt, const CtxW<D> &cx,
                                  const YW<D> &y, Du h, YW<D> &out, PgLds<D, Du> &s) {
   YW<D> ys = y;
-  const Du h6 = h / Du(6.0);
+  const Du h6 = h * (1.0 / 6.0);
   const Du hh = 0.5 * h;
 #pragma unroll 1
   for (int st = 0; st < 4; ++st) {
