@@ -57,8 +57,8 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 64 lanes x 2 flop x 2.4
 # (profiles/step_m2_qcle1d_1e6.md, profiles/step_wave_qcle12d_2p18.md).  Remove an entry when
 # its kernel changes.
 STEP_TRAFFIC = {
-    "qcle1d_1e6": (66681.4 * 2.0 + 133300.8 * 1.0) * 1024,          # step_m2_kernel, 1e6 beams
-    "qcle12d_2p18": (1343912.8 * 2.0 + 1484506.4 * 1.0) * 1024,     # step_wave_kernel<12, 32, double>
+    "qcle1d_1e6": (66680.1 * 2.0 + 133300.8 * 1.0) * 1024,          # step_m2_kernel, 1e6 beams
+    "qcle12d_2p18": (1343895.4 * 2.0 + 1606324.0 * 1.0) * 1024,     # step_wave_kernel<12, 32, double>
 }
 
 
