@@ -225,7 +225,8 @@ int shgb_populations(const shgb_model *model, const shgb_state *st, double *out,
  * (divide by N_traj for U_i).  points: device double[Q * m], row-major.
  * Fixed reduction order (bitwise reproducible).  work: device, >=
  * shgb_reconstruct_workspace(n_beams, m, Q) bytes.  Errors: EINVAL, EWORKSPACE,
- * EUNSUPPORTED. */
+ * EUNSUPPORTED (m not in {2, 4, 6, 8, 24}; m = 24 with 2^26 or more beams or
+ * points). */
 int64_t shgb_reconstruct_workspace(int64_t n_beams, int32_t m, int64_t Q);
 int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double *points,
                      int64_t Q, double *out, void *work, int64_t work_bytes, void *stream);

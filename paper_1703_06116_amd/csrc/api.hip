@@ -29,6 +29,7 @@ bool recon_wave_supported(int m);
 hipError_t launch_recon_wave(const DevModel &, const shgb_state &, const double *, int64_t, double *, void *,
                              hipStream_t);
 int64_t recon_mfma_workspace_bytes(int64_t, int64_t);
+bool recon_mfma_supported(int64_t, int64_t);
 int wave_tile_beams(int d, int wpb);
 int64_t tangent_workspace_bytes(int64_t n);
 int64_t tangent_wave_workspace_bytes(int64_t n);
@@ -270,6 +271,7 @@ int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double
     return hip_status(launch_recon_m2(md, *st, points, Q, out, work, (hipStream_t)stream));
   }
   if (st->m == 24) {
+    if (!recon_mfma_supported(st->n_beams, Q)) return SHGB_EUNSUPPORTED;
     if (work_bytes < recon_mfma_workspace_bytes(st->n_beams, Q)) return SHGB_EWORKSPACE;
     return hip_status(launch_recon_mfma(md, *st, points, Q, out, work, (hipStream_t)stream));
   }

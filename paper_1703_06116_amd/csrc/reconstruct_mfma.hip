@@ -341,6 +341,13 @@ __global__ void rm_reduce_kernel(const double *__restrict__ partial, int64_t n_c
 
 int64_t recon_mfma_workspace_bytes(int64_t n, int64_t Q) { return rm_layout(n, Q).total * (int64_t)sizeof(double); }
 
+// The slab copies address a feature row pair from a per-slab base with
+// 32-bit byte offsets (two rows of NB or QP doubles): both counts below 2^26.
+bool recon_mfma_supported(int64_t n, int64_t Q) {
+  const RmLayout L = rm_layout(n, Q);
+  return L.NB < ((int64_t)1 << 26) && L.QP < ((int64_t)1 << 26);
+}
+
 hipError_t launch_recon_mfma(const DevModel &md, const shgb_state &st, const double *pts, int64_t Q, double *out,
                              void *work, hipStream_t stream) {
   if (Q == 0) return hipSuccess;

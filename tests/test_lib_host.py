@@ -147,6 +147,11 @@ def test_validation_rejects_bad_arguments(binding):
     assert lib.shgb_reconstruct(by(mdl), by(st), nul, 100, ctypes.c_void_p(0x10), ctypes.c_void_p(0x10),
                                 wr, nul) == EINVAL
     assert lib.shgb_philox(1, nul, nul, 5, nul) == EINVAL
+    # m = 24 field: the matrix-core path takes fewer than 2^26 beams and points
+    m12 = _model(binding, d=12, lam=1e-3, bath_omega=tuple(0.002 + 0.001 * k for k in range(11)))
+    big = _desc(binding, n=1 << 26, m=24)
+    assert lib.shgb_reconstruct(by(m12), by(big), ctypes.c_void_p(0x10), 100, ctypes.c_void_p(0x10),
+                                ctypes.c_void_p(0x10), 1 << 62, nul) == EUNS
 
 
 def test_tangent_validation(binding):
