@@ -204,7 +204,7 @@ def run_batch(a):
         "metric": METRIC, "value": value, "unit": "beam-steps/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 trajectories + f64 phase/weights", "data": "synthetic",
-        "config": {"workload": a.config, "model": f"qcle-two-level-{d}d", "instances": len(cs), "n_beams": N,
+        "config": {"workload": a.config, "system": f"qcle-two-level-{d}d", "instances": len(cs), "n_beams": N,
                    "intervals": nsteps, "dt": dt, "phase_space_dim": m, "parallelism": "none (1 GPU)"},
         "graph_ms_per_step": graph_ms,
         "launch_shape": {"waves_per_block": cfg[0], "blocks_per_cu": cfg[1], "tiles_per_grab": cfg[2]},
@@ -265,7 +265,7 @@ def run_grad(a, c):
         "metric": METRIC, "value": N * nsteps / (ms_grad / 1e3), "unit": "beam-steps/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_grad, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64 (value, derivative) pairs", "data": "synthetic",
-        "config": {"workload": a.config, "model": f"qcle-two-level-{c['d']}d", "n_beams": N, "intervals": nsteps,
+        "config": {"workload": a.config, "system": f"qcle-two-level-{c['d']}d", "n_beams": N, "intervals": nsteps,
                    "dt": dt, "eps": c["eps"], "phase_space_dim": m, "directions": 5,
                    "parallelism": "none (1 GPU)"},
         "note": "value counts each beam-step once for all five directions (five tangent passes)",
@@ -397,7 +397,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": a.config, "model": f"qcle-two-level-{c['d']}d", "n_beams": N, "intervals": nsteps,
+        "config": {"workload": a.config, "system": f"qcle-two-level-{c['d']}d", "n_beams": N, "intervals": nsteps,
                    "dt": dt, "eps": c["eps"], "eval_points": Q, "phase_space_dim": m,
                    "parallelism": "none (1 GPU)"},
         "beam_point_evals_per_s": evals_per_s,
