@@ -234,3 +234,36 @@ def test_hop_entry_point_paper_system_32(gpu):
     np.testing.assert_array_equal(g["phase"], e.phase)
     assert np.abs(g["logw"] - e.logw).max() < 1e-15
     assert diag.cpu().numpy()[6] == 1 == e.zero_rate.sum()
+
+
+def test_paper_31_field_error_falls_as_inverse_square_root(gpu):
+    """The convergence study of Sec. 3.1 in kind: for eq. (3.1) the expectation of
+    the method is the exact solution (the O(eps^(1/2)) residuals vanish), so the
+    L2 distance between an N-trajectory field and the field of 2^22 trajectories
+    (standing in for the N -> infinity limit, the paper's finite-volume reference
+    being out of scope) is Monte Carlo error: its mean over independent runs falls
+    as N^(-1/2).  eps = 0.1, t = 0.5, both components on a 64 x 64 grid of
+    [-3, 3]^2; 16 runs for each N."""
+    eps, dt, nsteps = 0.1, 0.005, 100
+    mdl = gpu_lq(gpu, paper_system_31(), eps)
+    sd = math.sqrt(1.0 - eps)
+    g = np.linspace(-3.0, 3.0, 64)
+    pts = torch.from_numpy(np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2).copy()).cuda()
+    cell = (g[1] - g[0]) ** 2
+
+    def field(n, seed):
+        st = gpu.State(n, 2)
+        gpu.init_beams(mdl, gpu.make_init_spec(0.0, sd, "normal", 0.0, sd, 0, a0=1.0 / eps), st, seed)
+        gpu.step_ensemble(mdl, st, nsteps, dt, seed)
+        return gpu.reconstruct(mdl, st, pts).cpu().numpy()[:2] / n
+
+    ref = field(1 << 22, 0x31F00D)
+    norm = np.sqrt((np.abs(ref) ** 2).sum() * cell)
+    errs = {}
+    for n in (100, 400, 1600, 6400):
+        e = [np.sqrt((np.abs(field(n, 1000 * n + r) - ref) ** 2).sum() * cell) for r in range(16)]
+        errs[n] = float(np.mean(e))
+    print("eq. (3.1) field: L2 error / L2 norm by N:", {n: round(v / norm, 4) for n, v in errs.items()})
+    for n in (100, 400, 1600):
+        assert 1.6 <= errs[n] / errs[4 * n] <= 2.5, (n, errs)
+    assert errs[6400] < 0.2 * norm
