@@ -8,7 +8,7 @@ Follows Cai & Lu Sec. 2.3-2.4.  Per beam the state is
     E = -log(1 - Y), the threshold of the current waiting time;
     comp = l_t, the current component; nhop = number of hops so far.
 
-Readings taken where the paper leaves a choice (each is listed in the design doc):
+Readings taken where the paper leaves a choice:
 
 * time stepping: fixed intervals [t_n, t_n + dt]; classical RK4 (the
   workloads prescribe RK4; Sec. 2.4 mentions a third-order method).
