@@ -287,7 +287,7 @@ def main():
         copy_probe()
         return
     if a.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {a.gpus}). "
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {a.gpus}). "
               "Beams are independent; a multi-GPU run would shard beams and sum the tallies once.",
               file=sys.stderr)
         sys.exit(2)
