@@ -12,7 +12,10 @@ outputs resident in HBM.
 
 Prints one JSON line.  `value` is beam-steps per second of the whole FP64
 step; the field's beam-point evaluations per second, per-kernel times and
-the dominant kernel's roofline figure are reported beside it.  The same
+the dominant kernel's roofline figure are reported beside it, with the
+stepping kernel's effective HBM rate (`hbm_effective`: the bytes a
+step-synchronous kernel would move, one read and one write of the state per
+interval, over the fused kernel's time).  The same
 workload is then run again on a mixed-precision state (FP32 trajectories,
 FP64 phase, rate integral and weights) and reported under "mixed": its
 throughput, its speedup over the FP64 path and the largest population
@@ -52,6 +55,7 @@ FLOPS_PER_BEAM_STEP_M24 = 4 * 3616 + 13 * 650
 # F = 325 features for Re and Im (4 F = 1300, the matrix-core work)
 FLOPS_PER_EVAL_M24 = 4 * 325
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 64 lanes x 2 flop x 2.4 GHz
+PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
 # HBM bytes per launch of the FP64 stepping kernel, from rocprofv3 FETCH_SIZE (x2.000) and
 # WRITE_SIZE (x1.000), each scaled by what the counter reads for a 1 GiB device copy
 # (profiles/step_m2_qcle1d_1e6.md, profiles/step_wave_qcle12d_2p18.md).  Remove an entry when
@@ -410,6 +414,14 @@ def main():
                      # (A is constant for the QCLE, gamma_ll = 0) and comp, nhop
                      "algorithmic_bytes": 2 * (8 * (2 * m + m * (m + 1) + 6) + 8) * N,
                      "flops_per_unit": fps, "units_per_launch": N * nsteps},
+        # the stepping kernel keeps the state on chip for all intervals; against a step-synchronous
+        # kernel that reads and writes the state once per interval its rate is an effective bandwidth
+        "hbm_effective": {"bytes_per_beam_step_unfused": 2 * (8 * (2 * m + m * (m + 1) + 6) + 8),
+                          "achieved": 2 * (8 * (2 * m + m * (m + 1) + 6) + 8) * N * nsteps
+                          / (phase_ms["step"] / 1e3) / 1e9,
+                          "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                          "frac": 2 * (8 * (2 * m + m * (m + 1) + 6) + 8) * N * nsteps
+                          / (phase_ms["step"] / 1e3) / 1e9 / PEAK_HBM_GBPS},
         "reconstruct_roofline": ({"bound": "alu" if m == 2 else "mfma", "achieved": fpe * evals_per_s / 1e12,
                                   "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                                   "frac": fpe * evals_per_s / 1e12 / PEAK_FP64_TFLOPS,
