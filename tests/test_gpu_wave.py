@@ -125,3 +125,32 @@ def test_hop_entry_point_d12(gpu):
     np.testing.assert_array_equal(g["comp"][ok], e.comp[ok])
     np.testing.assert_array_equal(g["phase"][ok], e.phase[ok])
     np.testing.assert_array_equal(g["nhop"], e.nhop)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_empty_and_single_beam_d12(gpu, precision):
+    """Edge sizes of the m = 24 path: an empty ensemble gives zero sums everywhere;
+    one beam's populations and field (1 and 65 points, ragged against the 64-point
+    tiles of the matrix-core kernel) match the oracle on the stored values."""
+    c = cfg(12)
+    mdl = gpu_model(c)
+    st = gpu.State(0, 24, precision=precision)
+    gpu.init_beams(mdl, gpu_spec(c), st, c["seed"])
+    gpu.step_ensemble(mdl, st, 5, c["dt"], c["seed"])
+    assert (gpu.populations(mdl, st).cpu().numpy() == 0).all()
+    pts = torch.zeros((7, 24), dtype=torch.float64, device="cuda")
+    assert (gpu.reconstruct(mdl, st, pts).cpu().numpy() == 0).all()
+    a = workloads.synthetic_ensemble(1, 24, seed=41, q_range=(0.0, 2.0), p_range=(0.0, 2.0), p_scale=0.3)
+    st = gpu.pack(a, precision=precision)
+    stored = gpu.unpack(st)
+    e = ensemble_from_arrays(stored)
+    for Q in (1, 65):
+        pts = workloads.points_near(a["X"], 0.5 * c["eps"], Q, seed=Q)
+        out = gpu.reconstruct(mdl, st, torch.from_numpy(pts).cuda()).cpu().numpy()
+        ref = observables.reconstruct(e, c["eps"], pts)
+        scale = observables.reconstruct_abs(e, c["eps"], pts)
+        assert (np.abs(out - ref) <= 1e-10 * scale + 1e-300).all(), (Q, out, ref)
+    pops = gpu.populations(mdl, st).cpu().numpy()
+    ref = observables.populations(e, c["eps"])
+    ci = observables.beam_integrals(e, c["eps"])
+    assert np.abs(pops[:, :2] - ref[:, :2]).max() <= 1e-11 * np.abs(ci).sum()
