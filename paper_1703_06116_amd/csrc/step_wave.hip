@@ -20,9 +20,10 @@
 // {Zrr_ab, Zrp_ab, Zrp_ba, Zpp_ab} is owned by one lane, which then has every
 // local operand of its four derivatives; only Zrp_a0, Zpp_0b and the sums
 // rho, chi come from other lanes, through the beam's slice of LDS.  Lane
-// c < m of the group owns X_c and P_c; the scalars (S, Lam, weights, the
-// threshold and the component) are replicated over the group, so the hop
-// logic (Sec. 2.4 steps 3-5) is uniform within a group.
+// r of the group owns X_c and P_c for c = r, r + LPB, ... below m; the
+// scalars (S, Lam, weights, the threshold and the component) are replicated
+// over the group, so the hop logic (Sec. 2.4 steps 3-5) is uniform within a
+// group.
 //
 // Precision: an FP64 state is integrated in FP64 throughout.  For a mixed
 // state the stage values and the right-hand side are FP32 (the exchange
@@ -88,15 +89,18 @@ __device__ inline void pg_stage(const DevModel &md, const QcleF &mf, HopCtx &hc,
   for (int e = 0; e < PG<D, LPB>::NG; ++e) {
     if (cx.a[e] >= 0) {
       double d[kGrpN];
-      grp_deriv<D, double>(cx.a[e], cx.b[e], cx.ka[e], cx.kb[e], sc, ys.g[e].v, s, d);
+      grp_deriv<D, double>(cx.a[e], cx.b[e], sc, ys.g[e].v, s, d);
 #pragma unroll
       for (int j = 0; j < kGrpN; ++j) fold(acc.g[e].v[j], ys.g[e].v[j], y0.g[e].v[j], d[j]);
     }
   }
-  double dx, dp;
-  xp_deriv<D, double>(cx.r, cx.kc, sc, s, dx, dp);
-  fold(acc.x, ys.x, y0.x, dx);
-  fold(acc.p, ys.p, y0.p, dp);
+#pragma unroll
+  for (int j = 0; j < PG<D, LPB>::NXP; ++j) {
+    double dx, dp;
+    xp_deriv<D, double>(cx.r + LPB * j, sc, s, dx, dp);
+    fold(acc.x[j], ys.x[j], y0.x[j], dx);
+    fold(acc.p[j], ys.p[j], y0.p[j], dp);
+  }
   double dS = sc.bc * sc.k.s, dL = 2.0 * fabs(s.x[D] * sc.im * sc.k.d21), unused = 0.0;
   fold(acc.S, unused, y0.S, dS);
   fold(acc.Lam, unused, y0.Lam, dL);
@@ -143,15 +147,18 @@ __device__ inline void pg_stage_m(const DevModel &md, const QcleF &mf, HopCtx &h
   for (int e = 0; e < PG<D, LPB>::NG; ++e) {
     if (cx.a[e] >= 0) {
       float d[kGrpN];
-      grp_deriv<D, float>(cx.a[e], cx.b[e], cx.ka[e], cx.kb[e], sc, ys.g[e].v, s, d);
+      grp_deriv<D, float>(cx.a[e], cx.b[e], sc, ys.g[e].v, s, d);
 #pragma unroll
       for (int j = 0; j < kGrpN; ++j) fold(acc.g[e].v[j], ys.g[e].v[j], y0.g[e].v[j], d[j]);
     }
   }
-  float dx, dp;
-  xp_deriv<D, float>(cx.r, cx.kc, sc, s, dx, dp);
-  fold(acc.x, ys.x, y0.x, dx);
-  fold(acc.p, ys.p, y0.p, dp);
+#pragma unroll
+  for (int j = 0; j < PG<D, LPB>::NXP; ++j) {
+    float dx, dp;
+    xp_deriv<D, float>(cx.r + LPB * j, sc, s, dx, dp);
+    fold(acc.x[j], ys.x[j], y0.x[j], dx);
+    fold(acc.p[j], ys.p[j], y0.p[j], dp);
+  }
   fold64(acc.S, (double)(sc.bc * sc.k.s));
   fold64(acc.Lam, (double)(2.0f * fabsf(s.x[D] * sc.im * sc.k.d21)));
 }
@@ -165,8 +172,11 @@ __device__ inline void pg_rk4_m(const DevModel &md, const QcleF &mf, HopCtx &hc,
   for (int e = 0; e < PG<D, LPB>::NG; ++e)
 #pragma unroll
     for (int j = 0; j < kGrpN; ++j) ys.g[e].v[j] = (float)y.g[e].v[j];
-  ys.x = (float)y.x;
-  ys.p = (float)y.p;
+#pragma unroll
+  for (int j = 0; j < PG<D, LPB>::NXP; ++j) {
+    ys.x[j] = (float)y.x[j];
+    ys.p[j] = (float)y.p[j];
+  }
   const double h6d = h * (1.0 / 6.0);
   const float h6 = (float)h6d;
   const double cs[3] = {0.5 * h, 0.5 * h, h};
@@ -184,8 +194,11 @@ __device__ inline void pg_add_inc(PgY<D, LPB, double> &y, const PgY<D, LPB, floa
   for (int e = 0; e < PG<D, LPB>::NG; ++e)
 #pragma unroll
     for (int j = 0; j < kGrpN; ++j) y.g[e].v[j] = y.g[e].v[j] + (double)inc.g[e].v[j];
-  y.x = y.x + (double)inc.x;
-  y.p = y.p + (double)inc.p;
+#pragma unroll
+  for (int j = 0; j < PG<D, LPB>::NXP; ++j) {
+    y.x[j] = y.x[j] + (double)inc.x[j];
+    y.p[j] = y.p[j] + (double)inc.p[j];
+  }
   y.S = y.S + inc.S;
   y.Lam = y.Lam + inc.Lam;
 }
@@ -238,7 +251,8 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const Pg
     }
     hop_start(hc, y.Lam);
     if constexpr (MIXED) {  // FP32 coupling at once, the draw and choice out of line (fewer spills)
-      const float q1 = (float)__shfl(y.x, base, 64), p1 = (float)__shfl(y.x, base + D, 64);
+      const float q1 = (float)__shfl(y.x[0], base, 64),
+                  p1 = (float)__shfl(y.x[D / LPB], base + D % LPB, 64);
       const Q1f k = qcle_q1f(mf, q1);
       hop_choose_call((double)(p1 * mf.inv_mass * k.d21), hc.h, hc.gid, hc.seed, cnt, kTieRelMixed);
       hc.pending = false;
@@ -251,10 +265,14 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const Pg
 }
 
 constexpr int kWavesPerBlock = 4;
-#ifndef SHGB_D12_LANES_PER_BEAM
-#define SHGB_D12_LANES_PER_BEAM 32
-#endif
-constexpr int kLanesPerBeamD12 = SHGB_D12_LANES_PER_BEAM;  // 32: two beams per wavefront
+// Lanes per d = 12 beam.  FP64 stage values: 16 (four beams per wavefront,
+// five pair groups and two coordinates per lane; the 3 RK4 copies of the
+// state fill the register file of one wave per SIMD either way, and four
+// beams share each wave's latency-bound scalar and exchange work).  FP32
+// stage values (mixed states, and the batched kernels): 32, which keeps two
+// waves per SIMD.
+constexpr int kLanesPerBeamD12 = 32;
+constexpr int kLanesPerBeamD12F64 = 16;
 
 // All nsteps intervals of the beams of one tile (WPB waves, 64/LPB beams
 // per wave).  TS: element type of the stored trajectory rows (double: FP64
@@ -279,14 +297,11 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
     PgCtx<D, LPB, double> cx;
     PgCtx<D, LPB, float> cxf;
     cx.r = cxf.r = r;
-    cx.kc = (r > 0 && r < D) ? md.bath_k[r] : ((r > D && r < M) ? md.bath_k[r - D] : 0.0);
-    cxf.kc = (float)cx.kc;
     PgY<D, LPB, double> y;
 #pragma unroll
     for (int e = 0; e < C::NG; ++e) {
       const int gi = r + LPB * e;
       cx.a[e] = cx.b[e] = -1;
-      cx.ka[e] = cx.kb[e] = 0.0;
 #pragma unroll
       for (int j = 0; j < kGrpN; ++j) y.g[e].v[j] = 0.0;
       if (gi < C::NGRP) {
@@ -295,8 +310,6 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
         const int bb = a + rem;
         cx.a[e] = a;
         cx.b[e] = bb;
-        cx.ka[e] = a > 0 ? md.bath_k[a] : 0.0;
-        cx.kb[e] = bb > 0 ? md.bath_k[bb] : 0.0;
         const int trr = Layout::tri(M, a, bb), tab = Layout::tri(M, a, D + bb), tba = Layout::tri(M, bb, D + a),
                   tpp = Layout::tri(M, D + a, D + bb);
         const int row[kGrpN] = {L.Zre(trr), L.Zim(trr), L.Zre(tab), L.Zim(tab),
@@ -306,11 +319,13 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
       }
       cxf.a[e] = cx.a[e];
       cxf.b[e] = cx.b[e];
-      cxf.ka[e] = (float)cx.ka[e];
-      cxf.kb[e] = (float)cx.kb[e];
     }
-    y.x = r < M ? (double)tr[L.X(r) * ld + b] : 0.0;
-    y.p = r < M ? (double)tr[L.P(r) * ld + b] : 0.0;
+#pragma unroll
+    for (int j = 0; j < C::NXP; ++j) {
+      const int c = r + LPB * j;
+      y.x[j] = c < M ? (double)tr[L.X(c) * ld + b] : 0.0;
+      y.p[j] = c < M ? (double)tr[L.P(c) * ld + b] : 0.0;
+    }
     y.S = sc[kRowS * ld + b];
     y.Lam = sc[kRowLam * ld + b];
     HopCtx hc;
@@ -325,11 +340,12 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
     hc.pending = false;
     hc.gid = gid0 + (uint64_t)b;
     hc.seed = seed;
+    pg_fill_const<D, LPB>(r, md.bath_k, lds[slot]);
     for (int st = 0; st < nsteps; ++st)
       pg_interval<D, LPB, MIXED>(md, mf, cx, cxf, base, y, hc, dt, cnt, (void *)&lds[slot]);
     // a hop still pending at the end of the call: its coupling at the state
     // reached, in the stage precision as inside the loop
-    const double q1 = __shfl(y.x, base, 64), p1 = __shfl(y.x, base + D, 64);
+    const double q1 = __shfl(y.x[0], base, 64), p1 = __shfl(y.x[D / LPB], base + D % LPB, 64);
     if (hc.pending) {
       if constexpr (MIXED) {
         const Q1f k = qcle_q1f(mf, (float)q1);
@@ -343,7 +359,9 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
     // finiteness of the values this lane owns (slots without a pair group
     // or coordinate hold no state)
     double chk = y.S + y.Lam + h.logw;
-    if (r < M) chk += y.x + y.p;
+#pragma unroll
+    for (int j = 0; j < C::NXP; ++j)
+      if (r + LPB * j < M) chk += y.x[j] + y.p[j];
 #pragma unroll
     for (int e = 0; e < C::NG; ++e)
       if (cx.a[e] >= 0)
@@ -365,9 +383,13 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
           if (a != bb || (j != kBaR && j != kBaI)) tr[row[j] * ld + b] = (TS)y.g[e].v[j];
       }
     }
-    if (r < M) {
-      tr[L.X(r) * ld + b] = (TS)y.x;
-      tr[L.P(r) * ld + b] = (TS)y.p;
+#pragma unroll
+    for (int j = 0; j < C::NXP; ++j) {
+      const int c = r + LPB * j;
+      if (c < M) {
+        tr[L.X(c) * ld + b] = (TS)y.x[j];
+        tr[L.P(c) * ld + b] = (TS)y.p[j];
+      }
     }
     if (r == 0) {
       sc[kRowS * ld + b] = y.S;
@@ -426,20 +448,21 @@ step_wave_batched(const BatchItem *__restrict__ items, int n_items, int64_t tota
 
 bool step_wave_supported(int d) { return d == 2 || d == 3 || d == 4 || d == 12; }
 
-template <int D, int LPB>
-static void launch_pg(const DevModel &md, const shgb_state &st, int nsteps, double dt, uint64_t seed, uint64_t *diag,
-                      hipStream_t stream) {
+template <int D, int LPB, typename TS>
+static void launch_pg_t(const DevModel &md, const shgb_state &st, TS *tr, int nsteps, double dt, uint64_t seed,
+                        uint64_t *diag, hipStream_t stream) {
   constexpr int beams_per_block = kWavesPerBlock * PG<D, LPB>::G;
   const int64_t blocks = (st.n_beams + beams_per_block - 1) / beams_per_block;
-  double *sc = scalar_block(st);
-  if (mixed(st))
-    hipLaunchKernelGGL((step_wave_kernel<D, LPB, float>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
-                       stream, md, st.f32, sc, st.comp, st.nhop, st.n_beams, st.ld, st.beam_id_offset, nsteps, dt,
-                       seed, diag);
-  else
-    hipLaunchKernelGGL((step_wave_kernel<D, LPB, double>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0,
-                       stream, md, st.f64, sc, st.comp, st.nhop, st.n_beams, st.ld, st.beam_id_offset, nsteps, dt,
-                       seed, diag);
+  hipLaunchKernelGGL((step_wave_kernel<D, LPB, TS>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, stream,
+                     md, tr, scalar_block(st), st.comp, st.nhop, st.n_beams, st.ld, st.beam_id_offset, nsteps, dt,
+                     seed, diag);
+}
+
+template <int D, int LPB32, int LPB64>
+static void launch_pg(const DevModel &md, const shgb_state &st, int nsteps, double dt, uint64_t seed, uint64_t *diag,
+                      hipStream_t stream) {
+  if (mixed(st)) launch_pg_t<D, LPB32, float>(md, st, st.f32, nsteps, dt, seed, diag, stream);
+  else launch_pg_t<D, LPB64, double>(md, st, st.f64, nsteps, dt, seed, diag, stream);
 }
 
 // beams per tile of the batched wave kernels
@@ -482,10 +505,10 @@ hipError_t launch_step_wave(const DevModel &md, const shgb_state &st, int nsteps
                             uint64_t *diag, hipStream_t stream) {
   if (st.n_beams == 0 || nsteps == 0) return hipSuccess;
   switch (md.d) {
-    case 2: launch_pg<2, 8>(md, st, nsteps, dt, seed, diag, stream); break;
-    case 3: launch_pg<3, 8>(md, st, nsteps, dt, seed, diag, stream); break;
-    case 4: launch_pg<4, 8>(md, st, nsteps, dt, seed, diag, stream); break;
-    case 12: launch_pg<12, kLanesPerBeamD12>(md, st, nsteps, dt, seed, diag, stream); break;
+    case 2: launch_pg<2, 8, 8>(md, st, nsteps, dt, seed, diag, stream); break;
+    case 3: launch_pg<3, 8, 8>(md, st, nsteps, dt, seed, diag, stream); break;
+    case 4: launch_pg<4, 8, 8>(md, st, nsteps, dt, seed, diag, stream); break;
+    case 12: launch_pg<12, kLanesPerBeamD12, kLanesPerBeamD12F64>(md, st, nsteps, dt, seed, diag, stream); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -27,6 +27,7 @@ constexpr int64_t kTwMaxBlocks = 2048;
 
 template <int D>
 using PGW = PG<D, kTwLanes>;
+static_assert(PG<12, kTwLanes>::NXP == 1, "one coordinate per lane");
 template <int D>
 using YW = PgY<D, kTwLanes, Du>;
 template <int D>
@@ -70,15 +71,15 @@ __device__ inline void pg_stage_du(const QcleDu &p, double lam, HopDu &hc, Count
   for (int e = 0; e < PGW<D>::NG; ++e) {
     if (cx.a[e] >= 0) {
       Du d[kGrpN];
-      grp_deriv<D, Du>(cx.a[e], cx.b[e], Du(cx.ka[e]), Du(cx.kb[e]), sc, ys.g[e].v, s, d);
+      grp_deriv<D, Du>(cx.a[e], cx.b[e], sc, ys.g[e].v, s, d);
 #pragma unroll
       for (int j = 0; j < kGrpN; ++j) fold(acc.g[e].v[j], ys.g[e].v[j], y0.g[e].v[j], d[j]);
     }
   }
   Du dx, dp;
-  xp_deriv<D, Du>(cx.r, Du(cx.kc), sc, s, dx, dp);
-  fold(acc.x, ys.x, y0.x, dx);
-  fold(acc.p, ys.p, y0.p, dp);
+  xp_deriv<D, Du>(cx.r, sc, s, dx, dp);
+  fold(acc.x[0], ys.x[0], y0.x[0], dx);
+  fold(acc.p[0], ys.p[0], y0.p[0], dp);
   Du unused(0.0);
   fold(acc.S, unused, y0.S, sc.bc * sc.k.s);
   fold(acc.Lam, unused, y0.Lam, 2.0 * dfabs(s.x[D] * sc.im * sc.k.d21));
@@ -197,21 +198,17 @@ tangent_wave_kernel(DevModel md, int dir, const double *__restrict__ tr, const d
   // the lane's pair groups and coordinate (the same for every beam)
   CtxW<D> cx;
   cx.r = lane;
-  cx.kc = (lane > 0 && lane < D) ? md.bath_k[lane] : ((lane > D && lane < M) ? md.bath_k[lane - D] : 0.0);
   int rows[NG][kGrpN];
 #pragma unroll
   for (int e = 0; e < NG; ++e) {
     const int gi = lane + kTwLanes * e;
     cx.a[e] = cx.b[e] = -1;
-    cx.ka[e] = cx.kb[e] = 0.0;
     if (gi < PGW<D>::NGRP) {
       int a = 0, rem = gi;
       while (rem >= D - a) { rem -= D - a; ++a; }
       const int bb = a + rem;
       cx.a[e] = a;
       cx.b[e] = bb;
-      cx.ka[e] = a > 0 ? md.bath_k[a] : 0.0;
-      cx.kb[e] = bb > 0 ? md.bath_k[bb] : 0.0;
       const int trr = Layout::tri(M, a, bb), tab = Layout::tri(M, a, D + bb), tba = Layout::tri(M, bb, D + a),
                 tpp = Layout::tri(M, D + a, D + bb);
       const int row[kGrpN] = {L.Zre(trr), L.Zim(trr), L.Zre(tab), L.Zim(tab),
@@ -230,8 +227,8 @@ tangent_wave_kernel(DevModel md, int dir, const double *__restrict__ tr, const d
     for (int e = 0; e < NG; ++e)
 #pragma unroll
       for (int j = 0; j < kGrpN; ++j) y.g[e].v[j] = Du(cx.a[e] >= 0 ? tr[rows[e][j] * ld + b] : 0.0);
-    y.x = Du(lane < M ? tr[L.X(lane) * ld + b] : 0.0, (dir == 4 && lane == D) ? 1.0 : 0.0);
-    y.p = Du(lane < M ? tr[L.P(lane) * ld + b] : 0.0);
+    y.x[0] = Du(lane < M ? tr[L.X(lane) * ld + b] : 0.0, (dir == 4 && lane == D) ? 1.0 : 0.0);
+    y.p[0] = Du(lane < M ? tr[L.P(lane) * ld + b] : 0.0);
     y.S = Du(sc[kRowS * ld + b]);
     y.Lam = Du(sc[kRowLam * ld + b]);
     HopDu hc;
@@ -246,16 +243,17 @@ tangent_wave_kernel(DevModel md, int dir, const double *__restrict__ tr, const d
     hc.pending = false;
     hc.gid = gid0 + (uint64_t)b;
     hc.seed = seed;
+    pg_fill_const<D, kTwLanes>(lane, md.bath_k, lds[wid].ex);
     for (int st = 0; st < nsteps; ++st) pg_interval_du<D>(p, md.lam, cx, y, hc, dt, cnt, lds[wid].ex);
     if (hc.pending) {   // a hop started in the last interval: its coupling at the state reached
-      const Du q1(__shfl(y.x.v, 0, 64), __shfl(y.x.d, 0, 64));
-      const double p1 = __shfl(y.x.v, D, 64);
+      const Du q1(__shfl(y.x[0].v, 0, 64), __shfl(y.x[0].d, 0, 64));
+      const double p1 = __shfl(y.x[0].v, D, 64);
       const Q1Du k = qcle_q1_du(p, q1);
       hop_choose(p1 * p.inv_mass * k.d21.v, hc.h, hc.gid, hc.seed, cnt, kTieRel);
       hc.pending = false;
     }
     double chk = y.S.v + y.S.d + y.Lam.v + y.Lam.d + hc.logw.v + hc.logw.d;
-    if (lane < M) chk += y.x.v + y.x.d + y.p.v + y.p.d;
+    if (lane < M) chk += y.x[0].v + y.x[0].d + y.p[0].v + y.p[0].d;
     // the beam integral: dual Z and P into LDS, then Z = L D L^T
     wave_lds_sync();
     TwFull<D> &f = lds[wid].f;
@@ -280,7 +278,7 @@ tangent_wave_kernel(DevModel md, int dir, const double *__restrict__ tr, const d
         }
       }
     }
-    if (lane < M) f.w[lane] = cd_real(y.p);
+    if (lane < M) f.w[lane] = cd_real(y.p[0]);
     wave_lds_sync();
     Cdu sq = {{1.0, 0.0}, {0.0, 0.0}}, quad = {{0.0, 0.0}, {0.0, 0.0}};
     for (int k = 0; k < M; ++k) {

@@ -23,7 +23,15 @@ struct PG {
   static constexpr int NGRP = D * (D + 1) / 2;          // pair groups a <= b
   static constexpr int NG = (NGRP + LPB - 1) / LPB;     // groups per lane
   static constexpr int G = 64 / LPB;                    // beams per wavefront
-  static_assert(M <= LPB, "X and P need one lane per coordinate");
+  static constexpr int NXP = (M + LPB - 1) / LPB;       // coordinates per lane
+  static_assert(64 % LPB == 0, "whole beams per wavefront");
+};
+
+// A complex entry of the exchange area: real and imaginary part side by
+// side, so that one LDS access moves both.
+template <typename T>
+struct alignas(2 * sizeof(T)) Cx2 {
+  T re, im;
 };
 
 // One beam's exchange area (T: the stage precision).  Matrix rows are
@@ -33,12 +41,20 @@ struct PG {
 template <int D, typename T>
 struct PgLds {
   static constexpr int W = D + 1;
-  T rp_r[D][W], rp_i[D][W];   // Zrp
-  T pp_r[D][W], pp_i[D][W];   // Zpp (both triangles)
-  T rho_r[D], rho_i[D], chi_r[D], chi_i[D];
+  Cx2<T> rp[D][W];   // Zrp
+  Cx2<T> pp[D][W];   // Zpp (both triangles)
+  Cx2<T> rho[D], chi[D];
   T x[2 * D], p[2 * D];
   T sx, sp;
+  T hk[D];           // H_kk = M w_k^2 for k > 0 (hk[0] is not used)
 };
+
+// Fill the constant part of the exchange area (before the first publish,
+// whose barrier orders it before every read).
+template <int D, int LPB, typename T>
+__device__ inline void pg_fill_const(int r, const double *bath_k, PgLds<D, T> &s) {
+  for (int k = r; k < D; k += LPB) s.hk[k] = T(k > 0 ? bath_k[k] : 0.0);
+}
 
 // Values of one pair group: Zrr_ab, Zrp_ab, Zrp_ba, Zpp_ab (re, im).
 enum { kRrR, kRrI, kAbR, kAbI, kBaR, kBaI, kPpR, kPpI, kGrpN };
@@ -57,10 +73,12 @@ struct ScalarOf<float> {
   using type = double;
 };
 
+// Lane r of the group owns the pair groups r + LPB e and the coordinates
+// X_c, P_c, c = r + LPB j.
 template <int D, int LPB, typename T>
 struct PgY {
   Grp<T> g[PG<D, LPB>::NG];
-  T x, p;
+  T x[PG<D, LPB>::NXP], p[PG<D, LPB>::NXP];
   typename ScalarOf<T>::type S, Lam;
 };
 
@@ -68,8 +86,6 @@ template <int D, int LPB, typename T>
 struct PgCtx {
   int r;                         // lane within the beam's group
   int a[PG<D, LPB>::NG], b[PG<D, LPB>::NG];  // pair of each owned group, -1: none
-  T ka[PG<D, LPB>::NG], kb[PG<D, LPB>::NG];  // M w^2 of the pair's bath indices (0 for index 0)
-  T kc;                          // M w^2 of the lane's coordinate (X/P lanes)
 };
 
 // The adiabatic quantities along q1 in the stage precision.
@@ -87,17 +103,17 @@ __device__ inline void pg_publish(const PgCtx<D, LPB, TC> &cx, const PgY<D, LPB,
     const int a = cx.a[e], b = cx.b[e];
     if (a >= 0) {
       const T *v = y.g[e].v;
-      s.rp_r[a][b] = v[kAbR];
-      s.rp_i[a][b] = v[kAbI];
-      s.rp_r[b][a] = v[kBaR];   // a == b: the same entry, written twice with one value
-      s.rp_i[b][a] = v[kBaI];
-      s.pp_r[a][b] = v[kPpR];
-      s.pp_i[a][b] = v[kPpI];
-      s.pp_r[b][a] = v[kPpR];
-      s.pp_i[b][a] = v[kPpI];
+      s.rp[a][b] = Cx2<T>{v[kAbR], v[kAbI]};
+      s.rp[b][a] = Cx2<T>{v[kBaR], v[kBaI]};   // a == b: the same entry, written twice with one value
+      s.pp[a][b] = Cx2<T>{v[kPpR], v[kPpI]};
+      s.pp[b][a] = Cx2<T>{v[kPpR], v[kPpI]};
     }
   }
-  if (cx.r < 2 * D) { s.x[cx.r] = y.x; s.p[cx.r] = y.p; }
+#pragma unroll
+  for (int j = 0; j < PG<D, LPB>::NXP; ++j) {
+    const int c = cx.r + LPB * j;
+    if (c < 2 * D) { s.x[c] = y.x[j]; s.p[c] = y.p[j]; }
+  }
   wave_lds_sync();
   // 2D + 1 sums over k = 1 .. D - 1, one per lane (round robin), all by the
   // same loop: task i < D: rho_i (row i of Zrp); D <= t < 2D: chi_j (column
@@ -107,10 +123,10 @@ __device__ inline void pg_publish(const PgCtx<D, LPB, TC> &cx, const PgY<D, LPB,
     T *orr, *oi;
     int stride;
     if (t < D) {
-      br = &s.rp_r[t][0]; bi = &s.rp_i[t][0]; stride = 1; orr = &s.rho_r[t]; oi = &s.rho_i[t];
+      br = &s.rp[t][0].re; bi = &s.rp[t][0].im; stride = 2; orr = &s.rho[t].re; oi = &s.rho[t].im;
     } else if (t < 2 * D) {
-      br = &s.pp_r[0][t - D]; bi = &s.pp_i[0][t - D]; stride = PgLds<D, T>::W; orr = &s.chi_r[t - D];
-      oi = &s.chi_i[t - D];
+      br = &s.pp[0][t - D].re; bi = &s.pp[0][t - D].im; stride = 2 * PgLds<D, T>::W; orr = &s.chi[t - D].re;
+      oi = &s.chi[t - D].im;
     } else {
       br = &s.x[0]; bi = &s.p[D]; stride = 1; orr = &s.sx; oi = &s.sp;
     }
@@ -131,31 +147,28 @@ struct StageCoef {
 
 // Derivatives of one pair group (a, b) at the stage values v.
 template <int D, typename T>
-__device__ inline void grp_deriv(int a, int b, T ka, T kb, const StageCoef<T> &c, const T *v, const PgLds<D, T> &s,
-                                 T *d) {
+__device__ inline void grp_deriv(int a, int b, const StageCoef<T> &c, const T *v, const PgLds<D, T> &s, T *d) {
   const T lam = c.lam, im = c.im;
-  const T Ha = a == 0 ? c.H00 : ka, Hb = b == 0 ? c.H00 : kb;
+  const T Ha = a == 0 ? c.H00 : s.hk[a], Hb = b == 0 ? c.H00 : s.hk[b];
   // the cross-lane operands, by address select rather than branches
-  const T *xrp = b > 0 ? &s.rp_r[a][0] : &s.rho_r[a], *xip = b > 0 ? &s.rp_i[a][0] : &s.rho_i[a];
-  const T *trp = a > 0 ? &s.rp_r[b][0] : &s.rho_r[b], *tip = a > 0 ? &s.rp_i[b][0] : &s.rho_i[b];
-  const T *urp = a > 0 ? &s.pp_r[0][b] : &s.chi_r[b], *uip = a > 0 ? &s.pp_i[0][b] : &s.chi_i[b];
-  const T *wrp = b > 0 ? &s.pp_r[0][a] : &s.chi_r[a], *wip = b > 0 ? &s.pp_i[0][a] : &s.chi_i[a];
+  const Cx2<T> xo = *(b > 0 ? &s.rp[a][0] : &s.rho[a]), to = *(a > 0 ? &s.rp[b][0] : &s.rho[b]);
+  const Cx2<T> uo = *(a > 0 ? &s.pp[0][b] : &s.chi[b]), wo = *(b > 0 ? &s.pp[0][a] : &s.chi[a]);
   // Zrr_ab' = (Zrp H)_ab + (Zrp H)_ba
   T xr = v[kAbR] * Hb, xi = v[kAbI] * Hb;
-  xr += lam * *xrp;
-  xi += lam * *xip;
+  xr += lam * xo.re;
+  xi += lam * xo.im;
   T tr = v[kBaR] * Ha, ti = v[kBaI] * Ha;
-  tr += lam * *trp;
-  ti += lam * *tip;
+  tr += lam * to.re;
+  ti += lam * to.im;
   d[kRrR] = xr + tr;
   d[kRrI] = (xi + ti) + ((a == 0 && b == 0) ? c.B00 : (T)0);
   // Zrp_ab' = (H Zpp)_ab - Zrr_ab / M,  Zrp_ba' = (H Zpp)_ba - Zrr_ba / M
   T ur = Ha * v[kPpR], ui = Ha * v[kPpI];
-  ur += lam * *urp;
-  ui += lam * *uip;
+  ur += lam * uo.re;
+  ui += lam * uo.im;
   T wr = Hb * v[kPpR], wi = Hb * v[kPpI];
-  wr += lam * *wrp;
-  wi += lam * *wip;
+  wr += lam * wo.re;
+  wi += lam * wo.im;
   d[kAbR] = ur - v[kRrR] * im;
   d[kAbI] = ui - v[kRrI] * im;
   d[kBaR] = wr - v[kRrR] * im;
@@ -165,12 +178,12 @@ __device__ inline void grp_deriv(int a, int b, T ka, T kb, const StageCoef<T> &c
   d[kPpI] = -(v[kBaI] + v[kAbI]) * im;
 }
 
-// Derivatives of the lane's coordinate X_c, P_c (c = lane index; lanes
-// c >= m get zeros).  Both alternatives are formed and one is selected.
+// Derivatives of the coordinate X_c, P_c (indices c >= m get zeros).  Both alternatives are formed and one is selected.
 template <int D, typename T>
-__device__ inline void xp_deriv(int cc, T kc, const StageCoef<T> &c, const PgLds<D, T> &s, T &dx, T &dp) {
+__device__ inline void xp_deriv(int cc, const StageCoef<T> &c, const PgLds<D, T> &s, T &dx, T &dp) {
   const T lam = c.lam, im = c.im;
   const int i = cc < D ? cc : (cc < 2 * D ? cc - D : 0);   // the coordinate index
+  const T kc = s.hk[i];
   if (cc < D) {
     dx = s.x[D + i] * im;
     const T dp0 = c.bc * c.k.s1 + c.H00 * s.p[D] + lam * s.sp;
