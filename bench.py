@@ -425,7 +425,11 @@ def main():
         "reconstruct_roofline": ({"bound": "alu" if m == 2 else "mfma", "achieved": fpe * evals_per_s / 1e12,
                                   "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                                   "frac": fpe * evals_per_s / 1e12 / PEAK_FP64_TFLOPS,
-                                  "flops_per_unit": fpe}
+                                  "flops_per_unit": fpe,
+                                  # m = 2: the kernel culls the beam-point pairs whose term is exactly zero
+                                  # (same sums); the rate counts every pair of the direct sum
+                                  "note": ("per beam-point pair of the direct sum, exactly-zero terms culled"
+                                           if m == 2 else "per beam-point pair")}
                                  if Q else None),
         "populations": {"mean_re": mean.real.tolist(), "mean_im": mean.imag.tolist(),
                         "se_re": se.real.tolist()},
