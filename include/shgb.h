@@ -223,7 +223,8 @@ int shgb_populations(const shgb_model *model, const shgb_state *st, double *out,
  * out[(i*Q + q)*2 + {0,1}] = Re, Im of sum_{k: l_k = i} exp(omega_k) G_k(x_q),
  * G(x) = A exp(-(x-X)^T Z (x-X)/(2 eps) + i P.(x-X)/eps + i S/eps), unnormalised
  * (divide by N_traj for U_i).  points: device double[Q * m], row-major.
- * Fixed reduction order (bitwise reproducible).  work: device, >=
+ * Fixed reduction order (bitwise reproducible for the same beam count and
+ * point count: the beam chunks of the sum depend on both).  work: device, >=
  * shgb_reconstruct_workspace(n_beams, m, Q) bytes.  Errors: EINVAL, EWORKSPACE,
  * EUNSUPPORTED (m not in {2, 4, 6, 8, 24}; m = 24 with 2^26 or more beams or
  * points). */

@@ -160,6 +160,57 @@ def test_reconstruct_matches_oracle(gpu, n, Q):
     assert np.abs(ref).max() > 0
 
 
+@pytest.mark.parametrize("extra", [0, 904])
+def test_reconstruct_on_a_wide_grid_matches_oracle(gpu, extra):
+    # beams spread over the grid as in the bench workload, so that most beam-point terms are
+    # exactly zero and whole beams are culled per wavefront; 4096 + 904 points span two sorted
+    # point chunks with a ragged tail
+    c = workloads.config("qcle1d_1e6")
+    n = 3 * 256 + 41
+    a = workloads.synthetic_ensemble(n, 2, seed=11, q_range=(10.0, 15.0), p_range=(15.0, 20.0), z_scale=0.3,
+                                     p_scale=0.2)
+    rng = np.random.default_rng(3)
+    pts = np.concatenate([workloads.grid_points_2d(),
+                          np.column_stack([rng.uniform(0, 30, extra), rng.uniform(0, 35, extra)])])
+    st = gpu.pack(a)
+    out = gpu.reconstruct(gpu_model(c), st, torch.from_numpy(pts).cuda()).cpu().numpy()
+    e = ensemble_from_arrays(a)
+    ref = observables.reconstruct(e, c["eps"], pts)
+    scale = observables.reconstruct_abs(e, c["eps"], pts)
+    assert (np.abs(out - ref) <= 1e-10 * scale + 1e-300).all()
+    assert (ref == 0).mean() > 0.5 and np.abs(ref).max() > 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_reconstruct_per_point_sums_do_not_depend_on_the_other_points(gpu, precision):
+    # each point's sum runs over the beams in one fixed order whatever the other points are:
+    # permuting the points, evaluating a subset, or putting non-finite and huge points into
+    # the same wavefront (which switches culling off there) leaves every sum bitwise the same
+    # (5000 beams give the same beam chunks for every point count used here)
+    c = workloads.config("qcle1d_1e6")
+    mdl = gpu_model(c)
+    st = gpu.State(5000, 2, device="cuda", precision=precision)
+    gpu.init_beams(mdl, gpu_spec(c), st, c["seed"])
+    gpu.step_ensemble(mdl, st, 400, c["dt"], c["seed"])
+    grid = workloads.grid_points_2d()
+    ref = gpu.reconstruct(mdl, st, torch.from_numpy(grid).cuda()).cpu().numpy()
+    assert np.isfinite(ref).all() and np.abs(ref).max() > 0
+    perm = np.random.default_rng(1).permutation(grid.shape[0])
+    out = gpu.reconstruct(mdl, st, torch.from_numpy(np.ascontiguousarray(grid[perm])).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(out, ref[:, perm])
+    sub = np.arange(100, 4096, 7)
+    out = gpu.reconstruct(mdl, st, torch.from_numpy(np.ascontiguousarray(grid[sub])).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(out, ref[:, sub])
+    odd = np.array([[1e120, 3.0], [np.nan, 20.0], [np.inf, 1.0], [-1e300, 1e300]])
+    mix = np.concatenate([grid[sub[:30]], odd, grid[sub[30:60]]])
+    out = gpu.reconstruct(mdl, st, torch.from_numpy(mix).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(out[:, :30], ref[:, sub[:30]])
+    np.testing.assert_array_equal(out[:, 34:], ref[:, sub[30:60]])
+    assert np.isnan(out[1, 31])   # component 1 (the lower surface) holds beams: NaN propagates
+    one = gpu.reconstruct(mdl, st, torch.from_numpy(grid[2080:2081].copy()).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(one, ref[:, 2080:2081])
+
+
 def test_empty_and_degenerate(gpu):
     c = workloads.config("qcle1d_1e4")
     mdl = gpu_model(c)
