@@ -45,20 +45,13 @@ __device__ inline Q1T<float> q1_eval(const DevModel &, const QcleF &mf, float q)
   return Q1T<float>{k.s, k.s1, k.s2, k.s3, k.d21};
 }
 
-// FP64: stage 0 first completes a pending hop at the stage values (the
-// step's start), from the coupling (p1/M) d21(q1) it evaluates anyway.  The
-// mixed kernel completes its hops where they start (see pg_interval).
+// Per-stage scalars on component l (a hop is completed where it starts, see
+// pg_interval, so l is fixed over an RK4 step).
 template <int D, typename T>
-__device__ inline StageCoef<T> stage_coef(const DevModel &md, const QcleF &mf, HopCtx &hc, Counters &cnt, int stage,
-                                          const PgLds<D, T> &s) {
+__device__ inline StageCoef<T> stage_coef(const DevModel &md, const QcleF &mf, int l, const PgLds<D, T> &s) {
   StageCoef<T> c;
   c.k = q1_eval(md, mf, s.x[0]);
   c.im = (T)md.inv_mass;
-  if (sizeof(T) == sizeof(double) && stage == 0 && hc.pending) {
-    hop_choose((double)(s.x[D] * c.im * c.k.d21), hc.h, hc.gid, hc.seed, cnt, kTieRel);
-    hc.pending = false;
-  }
-  const int l = hc.h.comp;
   c.sg = (T)comp_sigma(l);
   c.bc = (T)comp_bcoef(l);
   c.H00 = c.sg * c.k.s2;
@@ -67,35 +60,38 @@ __device__ inline StageCoef<T> stage_coef(const DevModel &md, const QcleF &mf, H
   return c;
 }
 
-// One Runge-Kutta stage of the FP64 path.  The stage values ys have been
+// One Runge-Kutta stage ST of the FP64 path.  The stage values ys have been
 // published to s; the derivative of each owned value is formed and folded
 // at once into the accumulator and the next stage:
 //   stage 0: acc = k;            ys = y0 + c k
 //   stage 1, 2: acc += 2 k;      ys = y0 + c k
 //   stage 3: acc = y0 + h6 (acc + k)   (the step's result)
-template <int D, int LPB>
-__device__ inline void pg_stage(const DevModel &md, const QcleF &mf, HopCtx &hc, Counters &cnt,
-                                const PgCtx<D, LPB, double> &cx, const PgY<D, LPB, double> &y0,
-                                PgY<D, LPB, double> &ys, PgY<D, LPB, double> &acc, int stage, double c, double h6,
-                                const PgLds<D, double> &s) {
-  const StageCoef<double> sc = stage_coef<D, double>(md, mf, hc, cnt, stage, s);
+// The stage has no branches: every slot is evaluated (a slot without a pair
+// group reads group (0, 0) and gets a zero derivative), so that the pair
+// groups, which do not depend on the two-level quantities unless a or b is
+// 0, can be scheduled together with their evaluation.
+template <int D, int LPB, int ST>
+__device__ inline void pg_stage(const DevModel &md, const QcleF &mf, int l, const PgCtx<D, LPB, double> &cx,
+                                const PgY<D, LPB, double> &y0, PgY<D, LPB, double> &ys, PgY<D, LPB, double> &acc,
+                                double c, double h6, const PgLds<D, double> &s) {
+  using C = PG<D, LPB>;
+  const StageCoef<double> sc = stage_coef<D, double>(md, mf, l, s);
   auto fold = [&](double &a, double &yv, double y0v, double d) {
-    if (stage == 0) a = d;
-    else if (stage < 3) a = a + 2.0 * d;
+    if constexpr (ST == 0) a = d;
+    else if constexpr (ST < 3) a = a + 2.0 * d;
     else a = y0v + h6 * (a + d);
-    if (stage < 3) yv = y0v + c * d;
+    if constexpr (ST < 3) yv = y0v + c * d;
   };
 #pragma unroll
-  for (int e = 0; e < PG<D, LPB>::NG; ++e) {
-    if (cx.a[e] >= 0) {
-      double d[kGrpN];
-      grp_deriv<D, double>(cx.a[e], cx.b[e], sc, ys.g[e].v, s, d);
+  for (int e = 0; e < C::NG; ++e) {
+    const bool live = (e + 1) * LPB <= C::NGRP || cx.a[e] >= 0;
+    double d[kGrpN];
+    grp_deriv<D, double>(live ? cx.a[e] : 0, live ? cx.b[e] : 0, sc, ys.g[e].v, s, d);
 #pragma unroll
-      for (int j = 0; j < kGrpN; ++j) fold(acc.g[e].v[j], ys.g[e].v[j], y0.g[e].v[j], d[j]);
-    }
+    for (int j = 0; j < kGrpN; ++j) fold(acc.g[e].v[j], ys.g[e].v[j], y0.g[e].v[j], live ? d[j] : 0.0);
   }
 #pragma unroll
-  for (int j = 0; j < PG<D, LPB>::NXP; ++j) {
+  for (int j = 0; j < C::NXP; ++j) {
     double dx, dp;
     xp_deriv<D, double>(cx.r + LPB * j, sc, s, dx, dp);
     fold(acc.x[j], ys.x[j], y0.x[j], dx);
@@ -106,21 +102,27 @@ __device__ inline void pg_stage(const DevModel &md, const QcleF &mf, HopCtx &hc,
   fold(acc.Lam, unused, y0.Lam, dL);
 }
 
-// One classical RK4 step of the group's beam on component l, into `out`;
+// One classical RK4 step of the group's beam on its component, into `out`;
 // `s` is clobbered.
 template <int D, int LPB>
-__device__ inline void pg_rk4(const DevModel &md, const QcleF &mf, HopCtx &hc, Counters &cnt,
-                              const PgCtx<D, LPB, double> &cx, const PgY<D, LPB, double> &y, double h,
-                              PgY<D, LPB, double> &out, PgLds<D, double> &s) {
+__device__ inline void pg_rk4(const DevModel &md, const QcleF &mf, const HopCtx &hc, const PgCtx<D, LPB, double> &cx,
+                              const PgY<D, LPB, double> &y, double h, PgY<D, LPB, double> &out,
+                              PgLds<D, double> &s) {
   PgY<D, LPB, double> ys = y;
   const double h6 = h * (1.0 / 6.0);
-  const double cs[3] = {0.5 * h, 0.5 * h, h};
-#pragma unroll 1
-  for (int st = 0; st < 4; ++st) {
-    pg_publish(cx, ys, s);
-    pg_stage(md, mf, hc, cnt, cx, y, ys, out, st, st < 3 ? cs[st] : 0.0, h6, s);
-    wave_lds_sync();
-  }
+  const int l = hc.h.comp;
+  pg_publish(cx, ys, s);
+  pg_stage<D, LPB, 0>(md, mf, l, cx, y, ys, out, 0.5 * h, h6, s);
+  wave_lds_sync();
+  pg_publish(cx, ys, s);
+  pg_stage<D, LPB, 1>(md, mf, l, cx, y, ys, out, 0.5 * h, h6, s);
+  wave_lds_sync();
+  pg_publish(cx, ys, s);
+  pg_stage<D, LPB, 2>(md, mf, l, cx, y, ys, out, h, h6, s);
+  wave_lds_sync();
+  pg_publish(cx, ys, s);
+  pg_stage<D, LPB, 3>(md, mf, l, cx, y, ys, out, 0.0, h6, s);
+  wave_lds_sync();
 }
 
 // Mixed precision: one stage with FP32 stage values and accumulator; stage 3
@@ -131,7 +133,7 @@ __device__ inline void pg_stage_m(const DevModel &md, const QcleF &mf, HopCtx &h
                                   const PgCtx<D, LPB, float> &cx, const PgY<D, LPB, double> &y0,
                                   PgY<D, LPB, float> &ys, PgY<D, LPB, float> &acc, int stage, double c, float h6,
                                   double h6d, const PgLds<D, float> &s) {
-  const StageCoef<float> sc = stage_coef<D, float>(md, mf, hc, cnt, stage, s);
+  const StageCoef<float> sc = stage_coef<D, float>(md, mf, hc.h.comp, s);
   auto fold = [&](float &a, float &yv, double y0v, float d) {
     if (stage == 0) a = d;
     else if (stage < 3) a = a + 2.0f * d;
@@ -205,8 +207,8 @@ __device__ inline void pg_add_inc(PgY<D, LPB, double> &y, const PgY<D, LPB, floa
 
 // One interval [t_n, t_n + dt] (Sec. 2.4 steps 3-5) for the group's beam: a
 // trial RK4 step; if Lam reaches the threshold, the step to the
-// interpolated hop time, the hop (started here, completed in the next
-// stage 0), and the rest of the interval.  MIXED selects the
+// interpolated hop time, the hop (at the state reached), and the rest of
+// the interval.  MIXED selects the
 // mixed-precision step.
 template <int D, int LPB, bool MIXED>
 __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const PgCtx<D, LPB, double> &cx,
@@ -220,7 +222,7 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const Pg
   YN yn;  // FP64: the trial result; mixed: the trial increment
   auto trial = [&](double hh) {
     if constexpr (MIXED) pg_rk4_m(md, mf, hc, cnt, cxf, y, hh, yn, *(PgLds<D, float> *)lds);
-    else pg_rk4(md, mf, hc, cnt, cx, y, hh, yn, *(PgLds<D, double> *)lds);
+    else pg_rk4(md, mf, hc, cx, y, hh, yn, *(PgLds<D, double> *)lds);
   };
   auto accept = [&]() {
     if constexpr (MIXED) pg_add_inc(y, yn);
@@ -249,14 +251,20 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const Pg
       accept();
       partial = false;
     }
+    // the hop at once, from the coupling (p1/M) d21(q1) at the state reached (in
+    // the stage precision); the draw and the choice out of line (fewer spills)
     hop_start(hc, y.Lam);
-    if constexpr (MIXED) {  // FP32 coupling at once, the draw and choice out of line (fewer spills)
+    if constexpr (MIXED) {
       const float q1 = (float)__shfl(y.x[0], base, 64),
                   p1 = (float)__shfl(y.x[D / LPB], base + D % LPB, 64);
       const Q1f k = qcle_q1f(mf, q1);
       hop_choose_call((double)(p1 * mf.inv_mass * k.d21), hc.h, hc.gid, hc.seed, cnt, kTieRelMixed);
-      hc.pending = false;
+    } else {
+      const double q1 = __shfl(y.x[0], base, 64), p1 = __shfl(y.x[D / LPB], base + D % LPB, 64);
+      const Q1 k = qcle_q1(md, q1);
+      hop_choose(p1 * md.inv_mass * k.d21, hc.h, hc.gid, hc.seed, cnt, kTieRel);
     }
+    hc.pending = false;
     ++hops;
     rem = rem * (1.0 - theta);
     if (!(rem > 0.0)) break;
@@ -265,14 +273,13 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const Pg
 }
 
 constexpr int kWavesPerBlock = 4;
-// Lanes per d = 12 beam.  FP64 stage values: 16 (four beams per wavefront,
-// five pair groups and two coordinates per lane; the 3 RK4 copies of the
-// state fill the register file of one wave per SIMD either way, and four
-// beams share each wave's latency-bound scalar and exchange work).  FP32
-// stage values (mixed states, and the batched kernels): 32, which keeps two
-// waves per SIMD.
+// Lanes per d = 12 beam: 32, two beams per wavefront.  FP64 stage values
+// fill the register file of one wave per SIMD; their stage has no branches,
+// so the scheduler overlaps the pair groups with the two-level quantities
+// (with 16 lanes per beam that schedule spills).  FP32 stage values keep two
+// waves per SIMD; there the branch-free stage spills, so the mixed stage
+// keeps its branches.
 constexpr int kLanesPerBeamD12 = 32;
-constexpr int kLanesPerBeamD12F64 = 16;
 
 // All nsteps intervals of the beams of one tile (WPB waves, 64/LPB beams
 // per wave).  TS: element type of the stored trajectory rows (double: FP64
@@ -508,7 +515,7 @@ hipError_t launch_step_wave(const DevModel &md, const shgb_state &st, int nsteps
     case 2: launch_pg<2, 8, 8>(md, st, nsteps, dt, seed, diag, stream); break;
     case 3: launch_pg<3, 8, 8>(md, st, nsteps, dt, seed, diag, stream); break;
     case 4: launch_pg<4, 8, 8>(md, st, nsteps, dt, seed, diag, stream); break;
-    case 12: launch_pg<12, kLanesPerBeamD12, kLanesPerBeamD12F64>(md, st, nsteps, dt, seed, diag, stream); break;
+    case 12: launch_pg<12, kLanesPerBeamD12, kLanesPerBeamD12>(md, st, nsteps, dt, seed, diag, stream); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

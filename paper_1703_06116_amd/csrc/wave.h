@@ -178,26 +178,25 @@ __device__ inline void grp_deriv(int a, int b, const StageCoef<T> &c, const T *v
   d[kPpI] = -(v[kBaI] + v[kAbI]) * im;
 }
 
-// Derivatives of the coordinate X_c, P_c (indices c >= m get zeros).  Both alternatives are formed and one is selected.
+// Derivatives of the coordinate X_c, P_c (indices c >= m get zeros).  All
+// alternatives are formed and one is selected (no branches).
 template <int D, typename T>
 __device__ inline void xp_deriv(int cc, const StageCoef<T> &c, const PgLds<D, T> &s, T &dx, T &dp) {
   const T lam = c.lam, im = c.im;
-  const int i = cc < D ? cc : (cc < 2 * D ? cc - D : 0);   // the coordinate index
+  const bool q = cc < D, pm = !q && cc < 2 * D;   // a position, a momentum coordinate
+  const int i = q ? cc : (pm ? cc - D : 0);        // the coordinate index
   const T kc = s.hk[i];
-  if (cc < D) {
-    dx = s.x[D + i] * im;
-    const T dp0 = c.bc * c.k.s1 + c.H00 * s.p[D] + lam * s.sp;
-    const T dpk = kc * s.p[D + i] + lam * s.p[D];
-    dp = i == 0 ? dp0 : dpk;
-  } else if (cc < 2 * D) {
-    const T dx0 = -(lam * s.sx + c.sg * c.k.s1);
-    const T dxk = -(kc * s.x[i] + lam * s.x[0]);
-    dx = i == 0 ? dx0 : dxk;
-    dp = -s.p[i] * im;
-  } else {
-    dx = 0;
-    dp = 0;
-  }
+  // position: X_i' = p_i / M;  P_i' = d beta / d r_i + (H P_p)_i
+  const T dxq = s.x[D + i] * im;
+  const T dp0 = c.bc * c.k.s1 + c.H00 * s.p[D] + lam * s.sp;
+  const T dpk = kc * s.p[D + i] + lam * s.p[D];
+  // momentum: X_{d+i}' = -(grad E)_i;  P_{d+i}' = -P_{r,i} / M
+  const T dx0 = -(lam * s.sx + c.sg * c.k.s1);
+  const T dxk = -(kc * s.x[i] + lam * s.x[0]);
+  const T dpm = -s.p[i] * im;
+  const T zero = T(0.0);
+  dx = q ? dxq : (pm ? (i == 0 ? dx0 : dxk) : zero);
+  dp = q ? (i == 0 ? dp0 : dpk) : (pm ? dpm : zero);
 }
 
 }  // namespace shgb
