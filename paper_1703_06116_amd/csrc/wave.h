@@ -94,10 +94,10 @@ struct Q1T {
   T s, s1, s2, s3, d21;
 };
 
-// Publish the stage values of the beam's lanes to its exchange area and form
-// the sums rho, chi (the context may hold another element type than T).
+// Write the stage values of the beam's lanes to its exchange area (the
+// context may hold another element type than T).
 template <int D, int LPB, typename TC, typename T>
-__device__ inline void pg_publish(const PgCtx<D, LPB, TC> &cx, const PgY<D, LPB, T> &y, PgLds<D, T> &s) {
+__device__ inline void pg_write(const PgCtx<D, LPB, TC> &cx, const PgY<D, LPB, T> &y, PgLds<D, T> &s) {
 #pragma unroll
   for (int e = 0; e < PG<D, LPB>::NG; ++e) {
     const int a = cx.a[e], b = cx.b[e];
@@ -114,27 +114,44 @@ __device__ inline void pg_publish(const PgCtx<D, LPB, TC> &cx, const PgY<D, LPB,
     const int c = cx.r + LPB * j;
     if (c < 2 * D) { s.x[c] = y.x[j]; s.p[c] = y.p[j]; }
   }
-  wave_lds_sync();
-  // 2D + 1 sums over k = 1 .. D - 1, one per lane (round robin), all by the
-  // same loop: task i < D: rho_i (row i of Zrp); D <= t < 2D: chi_j (column
-  // j of Zpp); t = 2D: sx and sp
-  for (int t = cx.r; t < 2 * D + 1; t += LPB) {
-    const T *br, *bi;
-    T *orr, *oi;
-    int stride;
-    if (t < D) {
-      br = &s.rp[t][0].re; bi = &s.rp[t][0].im; stride = 2; orr = &s.rho[t].re; oi = &s.rho[t].im;
-    } else if (t < 2 * D) {
-      br = &s.pp[0][t - D].re; bi = &s.pp[0][t - D].im; stride = 2 * PgLds<D, T>::W; orr = &s.chi[t - D].re;
-      oi = &s.chi[t - D].im;
-    } else {
-      br = &s.x[0]; bi = &s.p[D]; stride = 1; orr = &s.sx; oi = &s.sp;
-    }
-    T sr = 0, si = 0;
-    for (int k = 1; k < D; ++k) { sr += br[k * stride]; si += bi[k * stride]; }
-    *orr = sr;
-    *oi = si;
+}
+
+// Sum task t < 2D + 1 over k = 1 .. D - 1: t < D: rho_t (row t of Zrp);
+// D <= t < 2D: chi_{t-D} (column t - D of Zpp); t = 2D: sx and sp.  The
+// operands are picked by address (no branches).
+template <int D, typename T>
+__device__ inline void pg_sum_task(int t, PgLds<D, T> &s) {
+  const bool row = t < D, col = !row && t < 2 * D;
+  const int u = row ? t : (col ? t - D : 0);
+  const T *br = row ? &s.rp[u][0].re : (col ? &s.pp[0][u].re : &s.x[0]);
+  const T *bi = row ? &s.rp[u][0].im : (col ? &s.pp[0][u].im : &s.p[D]);
+  const int stride = row ? 2 : (col ? 2 * PgLds<D, T>::W : 1);
+  T *orr = row ? &s.rho[u].re : (col ? &s.chi[u].re : &s.sx);
+  T *oi = row ? &s.rho[u].im : (col ? &s.chi[u].im : &s.sp);
+  T sr = 0, si = 0;
+  for (int k = 1; k < D; ++k) { sr += br[k * stride]; si += bi[k * stride]; }
+  *orr = sr;
+  *oi = si;
+}
+
+// The 2D + 1 sums, once the written stage values are visible: one task per
+// lane (lanes past the last task repeat it: the same values to the same
+// place), round robin when the group has fewer lanes than tasks.
+template <int D, int LPB, typename TC, typename T>
+__device__ inline void pg_sums(const PgCtx<D, LPB, TC> &cx, PgLds<D, T> &s) {
+  if constexpr (2 * D + 1 <= LPB) {
+    pg_sum_task<D, T>(cx.r < 2 * D + 1 ? cx.r : 2 * D, s);
+  } else {
+    for (int t = cx.r; t < 2 * D + 1; t += LPB) pg_sum_task<D, T>(t, s);
   }
+}
+
+// Publish the stage values and form the sums rho, chi, sx, sp.
+template <int D, int LPB, typename TC, typename T>
+__device__ inline void pg_publish(const PgCtx<D, LPB, TC> &cx, const PgY<D, LPB, T> &y, PgLds<D, T> &s) {
+  pg_write(cx, y, s);
+  wave_lds_sync();
+  pg_sums(cx, s);
   wave_lds_sync();
 }
 
