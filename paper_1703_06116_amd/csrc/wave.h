@@ -11,10 +11,14 @@
 
 namespace shgb {
 
+// Orders the LDS accesses of a beam's lanes, which all sit in one wavefront
+// (LPB divides 64): a wavefront executes its LDS accesses in order, so
+// wavefront-scope fences (no waits on other memory) and a barrier for the
+// compiler suffice.
 __device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int D, int LPB>
