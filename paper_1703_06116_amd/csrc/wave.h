@@ -105,7 +105,7 @@ __device__ inline void pg_write(const PgCtx<D, LPB, TC> &cx, const PgY<D, LPB, T
 #pragma unroll
   for (int e = 0; e < PG<D, LPB>::NG; ++e) {
     const int a = cx.a[e], b = cx.b[e];
-    if (a >= 0) {
+    if ((e + 1) * LPB <= PG<D, LPB>::NGRP || a >= 0) {   // slots every lane fills need no test
       const T *v = y.g[e].v;
       s.rp[a][b] = Cx2<T>{v[kAbR], v[kAbI]};
       s.rp[b][a] = Cx2<T>{v[kBaR], v[kBaI]};   // a == b: the same entry, written twice with one value
