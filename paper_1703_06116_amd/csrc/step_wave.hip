@@ -147,7 +147,7 @@ __device__ inline void pg_stage_m(const DevModel &md, const QcleF &mf, HopCtx &h
   };
 #pragma unroll
   for (int e = 0; e < PG<D, LPB>::NG; ++e) {
-    if (cx.a[e] >= 0) {
+    if ((e + 1) * LPB <= PG<D, LPB>::NGRP || cx.a[e] >= 0) {   // slots every lane fills need no test
       float d[kGrpN];
       grp_deriv<D, float>(cx.a[e], cx.b[e], sc, ys.g[e].v, s, d);
 #pragma unroll
