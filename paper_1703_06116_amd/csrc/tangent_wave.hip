@@ -69,7 +69,7 @@ __device__ inline void pg_stage_du(const QcleDu &p, double lam, HopDu &hc, Count
   };
 #pragma unroll
   for (int e = 0; e < PGW<D>::NG; ++e) {
-    if (cx.a[e] >= 0) {
+    if ((e + 1) * kTwLanes <= PGW<D>::NGRP || cx.a[e] >= 0) {   // slots every lane fills need no test
       Du d[kGrpN];
       grp_deriv<D, Du>(cx.a[e], cx.b[e], sc, ys.g[e].v, s, d);
 #pragma unroll
