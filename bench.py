@@ -62,7 +62,7 @@ PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
 # its kernel changes.
 STEP_TRAFFIC = {
     "qcle1d_1e6": (66680.1 * 2.0 + 133300.8 * 1.0) * 1024,          # step_m2_kernel, 1e6 beams
-    "qcle12d_2p18": (2785012.1 * 2.0 + 4882423.2 * 1.0) * 1024,     # step_wave_kernel<12, 32, double>
+    "qcle12d_2p18": (2773065.8 * 2.0 + 4688936.7 * 1.0) * 1024,     # step_wave_kernel<12, 32, double>
 }
 
 
