@@ -350,19 +350,7 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
     pg_fill_const<D, LPB>(r, md.bath_k, lds[slot]);
     for (int st = 0; st < nsteps; ++st)
       pg_interval<D, LPB, MIXED>(md, mf, cx, cxf, base, y, hc, dt, cnt, (void *)&lds[slot]);
-    // a hop still pending at the end of the call: its coupling at the state
-    // reached, in the stage precision as inside the loop
-    const double q1 = __shfl(y.x[0], base, 64), p1 = __shfl(y.x[D / LPB], base + D % LPB, 64);
-    if (hc.pending) {
-      if constexpr (MIXED) {
-        const Q1f k = qcle_q1f(mf, (float)q1);
-        hop_choose((double)((float)p1 * mf.inv_mass * k.d21), h, hc.gid, hc.seed, cnt, kTieRelMixed);
-      } else {
-        const Q1 k = qcle_q1(md, q1);
-        hop_choose(p1 * md.inv_mass * k.d21, h, hc.gid, hc.seed, cnt, kTieRel);
-      }
-      hc.pending = false;
-    }
+    // (every hop is completed where it starts, so none is pending here)
     // finiteness of the values this lane owns (slots without a pair group
     // or coordinate hold no state)
     double chk = y.S + y.Lam + h.logw;
