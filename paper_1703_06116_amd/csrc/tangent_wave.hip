@@ -33,20 +33,14 @@ using YW = PgY<D, kTwLanes, Du>;
 template <int D>
 using CtxW = PgCtx<D, kTwLanes, double>;
 
-// Stage coefficients on dual numbers; stage 0 completes a pending hop from
-// the coupling value (p1/M) d21(q1) at the stage values, as the FP64 kernel.
+// Stage coefficients on dual numbers (a hop is completed where it starts,
+// see pg_interval_du, as in the FP64 kernel).
 template <int D>
-__device__ inline StageCoef<Du> stage_coef_du(const QcleDu &p, HopDu &hc, Counters &cnt, int stage,
-                                              const PgLds<D, Du> &s, double lam) {
+__device__ inline StageCoef<Du> stage_coef_du(const QcleDu &p, int l, const PgLds<D, Du> &s, double lam) {
   StageCoef<Du> c;
   const Q1Du k = qcle_q1_du(p, s.x[0]);
   c.k = Q1T<Du>{k.s, k.s1, k.s2, k.s3, k.d21};
   c.im = Du(p.inv_mass);
-  if (stage == 0 && hc.pending) {
-    hop_choose_call(s.x[D].v * p.inv_mass * k.d21.v, hc.h, hc.gid, hc.seed, cnt, kTieRel);
-    hc.pending = false;
-  }
-  const int l = hc.h.comp;
   c.sg = Du(comp_sigma(l));
   c.bc = Du(comp_bcoef(l));
   c.H00 = c.sg * c.k.s2;
@@ -60,7 +54,7 @@ template <int D>
 __device__ inline void pg_stage_du(const QcleDu &p, double lam, HopDu &hc, Counters &cnt, const CtxW<D> &cx,
                                    const YW<D> &y0, YW<D> &ys, YW<D> &acc, int stage, Du c, Du h6,
                                    const PgLds<D, Du> &s) {
-  const StageCoef<Du> sc = stage_coef_du<D>(p, hc, cnt, stage, s, lam);
+  const StageCoef<Du> sc = stage_coef_du<D>(p, hc.h.comp, s, lam);
   auto fold = [&](Du &a, Du &yv, Du y0v, Du d) {
     if (stage == 0) a = d;
     else if (stage < 3) a = a + 2.0 * d;
@@ -130,9 +124,12 @@ __device__ inline void pg_interval_du(const QcleDu &p, double lam, const CtxW<D>
       y = yn;
       partial = false;
     }
-    hc.logw = hc.logw + y.Lam;   // the hop starts: weight update; completed in the next stage 0
+    hc.logw = hc.logw + y.Lam;   // the hop: weight update, then the coupling at the state reached
     y.Lam = Du(0.0);
-    hc.pending = true;
+    {
+      const Q1Du k = qcle_q1_du(p, Du(__shfl(y.x[0].v, 0, 64), __shfl(y.x[0].d, 0, 64)));
+      hop_choose(__shfl(y.x[0].v, D, 64) * p.inv_mass * k.d21.v, hc.h, hc.gid, hc.seed, cnt, kTieRel);
+    }
     ++hops;
     rem = rem * (Du(1.0) - theta);
     if (!(rem.v > 0.0)) break;
@@ -245,13 +242,6 @@ tangent_wave_kernel(DevModel md, int dir, const double *__restrict__ tr, const d
     hc.seed = seed;
     pg_fill_const<D, kTwLanes>(lane, md.bath_k, lds[wid].ex);
     for (int st = 0; st < nsteps; ++st) pg_interval_du<D>(p, md.lam, cx, y, hc, dt, cnt, lds[wid].ex);
-    if (hc.pending) {   // a hop started in the last interval: its coupling at the state reached
-      const Du q1(__shfl(y.x[0].v, 0, 64), __shfl(y.x[0].d, 0, 64));
-      const double p1 = __shfl(y.x[0].v, D, 64);
-      const Q1Du k = qcle_q1_du(p, q1);
-      hop_choose(p1 * p.inv_mass * k.d21.v, hc.h, hc.gid, hc.seed, cnt, kTieRel);
-      hc.pending = false;
-    }
     double chk = y.S.v + y.S.d + y.Lam.v + y.Lam.d + hc.logw.v + hc.logw.d;
     if (lane < M) chk += y.x[0].v + y.x[0].d + y.p[0].v + y.p[0].d;
     // the beam integral: dual Z and P into LDS, then Z = L D L^T
