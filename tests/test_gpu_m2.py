@@ -211,6 +211,23 @@ def test_reconstruct_per_point_sums_do_not_depend_on_the_other_points(gpu, preci
     np.testing.assert_array_equal(one, ref[:, 2080:2081])
 
 
+def test_reconstruct_many_sorted_point_chunks(gpu):
+    # 20000 scattered points: five Morton-sorted chunks of 4096 and 79 point tiles; each point's
+    # sum equals the one from a call on a subset (5000 beams: the same beam chunks for both)
+    c = workloads.config("qcle1d_1e6")
+    mdl = gpu_model(c)
+    st = gpu.State(5000, 2, device="cuda")
+    gpu.init_beams(mdl, gpu_spec(c), st, c["seed"])
+    gpu.step_ensemble(mdl, st, 400, c["dt"], c["seed"])
+    rng = np.random.default_rng(8)
+    pts = np.column_stack([rng.uniform(-5, 35, 20000), rng.uniform(0, 40, 20000)])
+    out = gpu.reconstruct(mdl, st, torch.from_numpy(pts).cuda()).cpu().numpy()
+    sub = np.sort(rng.choice(20000, 3000, replace=False))
+    part = gpu.reconstruct(mdl, st, torch.from_numpy(np.ascontiguousarray(pts[sub])).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(out[:, sub], part)
+    assert np.isfinite(out).all() and (out != 0).any() and (out == 0).any()
+
+
 def test_empty_and_degenerate(gpu):
     c = workloads.config("qcle1d_1e4")
     mdl = gpu_model(c)
