@@ -65,6 +65,28 @@ def test_P3_waiting_times_and_destinations():
     assert abs(k / len(dest) - p1) < 4 * math.sqrt(p1 * (1 - p1) / len(dest))
 
 
+# coupling column of component 0 with rates |gamma_10| : |gamma_20| = 9 : 1 (complex entries)
+GAM_UNEQUAL = np.array([[0.0, 0.1, 0.2], [0.9 * np.exp(0.3j), 0.0, 0.1], [0.1j, 0.3, 0.0]])
+
+
+def forced_hop_destinations(shgb_mod, n=5000, seed=21):
+    """Destinations of n hops forced at once from component 0 (hop_event of ``shgb_mod``)."""
+    model = models.LinQuad.xindep(B0, GAM_UNEQUAL)
+    ens = xindep_ensemble(n, comp0=0, seed=seed)
+    ens.E[:] = 0.0
+    shgb_mod.hop_event(model, ens, np.arange(n), seed)
+    return ens.comp.copy()
+
+
+def test_destinations_follow_unequal_rates():
+    """Sec. 2.4 step 5: the destination j is drawn with probability |gamma_j0| / sum_k |gamma_k0|
+    (here 0.9 and 0.1; binomial band of 4 SE)."""
+    dest = forced_hop_destinations(shgb)
+    assert np.isin(dest, [1, 2]).all()
+    p1, n = 0.9, dest.size
+    assert abs((dest == 1).mean() - p1) < 4 * math.sqrt(p1 * (1 - p1) / n)
+
+
 def test_forced_hop_and_weight_bookkeeping():
     """A threshold at or below Lam hops at once; phase and weight follow gamma."""
     model = models.LinQuad.xindep(B0, GAM)

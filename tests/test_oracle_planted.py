@@ -1,0 +1,151 @@
+"""Planted mistakes: each plausible error in the oracle's beam ODEs, RK4 and
+hopping code makes one of its pins fail.
+
+The source of oracle/shgb.py is loaded with one textual change into a fresh
+module (in memory, on the CPU) and the checks of two pins run against it:
+P1 (closed-form propagation of a linear-quadratic beam, tests/test_oracle_gb.py)
+for the right-hand side of eq. (2.24) and the RK4 step, and P3 (x-independent
+system: populations against the matrix exponential, first hop times against
+the exponential law, destinations of forced hops against unequal rates,
+tests/test_oracle_hopping.py) and the QCLE weight invariant
+Re omega = 2 |theta(q_T) - theta(q_0)| (tests/test_oracle_qcle.py) for the hop
+bookkeeping of Sec. 2.4.  The unchanged source, loaded the same way, passes
+every check.
+"""
+
+import math
+import types
+
+import numpy as np
+import pytest
+from scipy import linalg, stats
+
+import oracle.shgb as base
+from oracle import models, observables, sampling
+
+import test_oracle_gb as gb
+import test_oracle_hopping as hop
+import test_oracle_qcle as qcle
+
+
+def load(old=None, new=None):
+    src = open(base.__file__).read()
+    if old is not None:
+        assert src.count(old) == 1, old
+        src = src.replace(old, new)
+    mod = types.ModuleType("oracle.shgb_planted")
+    mod.__file__, mod.__package__ = base.__file__, "oracle"
+    exec(compile(src, base.__file__, "exec"), mod.__dict__)
+    return mod
+
+
+def p1_error(mod, m=2, n=80, T=1.5):
+    """Max error of a beam after n RK4 steps against its closed form (the P1 bar at n = 80: 1e-6)."""
+    model, ens = gb.random_linquad(m, seed=m), gb.one_beam(m, seed=m)
+    XT, PT, ZT, ST, AT = gb.exact_beam(model, ens, T)
+    e = ens.subset([0])
+    for _ in range(n):
+        mod.advance_interval(model, e, T / n, seed=1)
+    return max(np.abs(e.X[0] - XT).max(), np.abs(e.P[0] - PT).max(), np.abs(e.M[0] + 1j * e.N[0] - ZT).max(),
+               abs(e.S[0] - ST), abs(e.A[0] - AT))
+
+
+def p3_run(mod, n=4000, T=1.0, steps=10, seed=3):
+    model = models.LinQuad.xindep(hop.B0, hop.GAM)
+    ens = hop.xindep_ensemble(n, seed=seed)
+    mod.advance(model, ens, steps, T / steps, seed)
+    return model, ens
+
+
+def p3_population_excess(mod, n=4000, T=1.0):
+    """Largest |mean - exact| over the P3 band 4 SE + 1e-3 (the pin passes below 1)."""
+    _, ens = p3_run(mod, n, T)
+    mean, se = observables.population_mean_se(observables.populations(ens, hop.EPS), n)
+    exact = linalg.expm(T * (1j * np.diag(hop.B0) / hop.EPS + hop.GAM))[:, 0]
+    return max(max(abs(mean[i].real - exact[i].real) / (4 * se[i].real + 1e-3),
+                   abs(mean[i].imag - exact[i].imag) / (4 * se[i].imag + 1e-3)) for i in range(3))
+
+
+def p3_first_hop_pvalue(mod, n=4000, T=1.0):
+    """KS p-value of the first hop times against the censored exponential law (the pin: > 1e-3)."""
+    _, ens = p3_run(mod, n, T, steps=7, seed=11)
+    R0 = abs(hop.GAM[1, 0]) + abs(hop.GAM[2, 0])
+    t1 = np.array([log[0][2] for log in ens.hop_log if log])
+    return stats.kstest(t1, lambda t: (1 - np.exp(-R0 * t)) / (1 - math.exp(-R0 * T))).pvalue
+
+
+def qcle_weight_error(mod, n=100, nsteps=700):
+    """Largest |logw + Lam - 2 |theta(q_T) - theta(q_0)|| relative to the largest angle term, on
+    the QCLE ensemble of tests/test_oracle_qcle.py (the pin: 1e-7 relative)."""
+    mdl = models.QCLE(**qcle.PAR)
+    ens = sampling.init_beams(mdl, n, qcle.EPS, 99, -2.5, 0.3, "normal", 30.0, 1.0, 1)
+    th0 = mdl.mixing_angle(ens.X[:, 0])
+    mod.advance(mdl, ens, nsteps, 0.5, 99)
+    ref = 2 * np.abs(mdl.mixing_angle(ens.X[:, 0]) - th0)
+    return np.abs(ens.logw + ens.Lam - ref).max() / ref.max()
+
+
+def test_unchanged_source_passes_every_check():
+    mod = load()
+    assert p1_error(mod) < 1e-6
+    assert p3_population_excess(mod) < 1.0
+    assert p3_first_hop_pvalue(mod) > 1e-3
+    assert qcle_weight_error(mod) < 1e-7
+
+
+ODE_MISTAKES = {
+    "dP: sign of the J^T P term": ('- np.einsum("nab,nb->na", Jt, P)', '+ np.einsum("nab,nb->na", Jt, P)'),
+    "dM: J and J^T exchanged": ("dM = -M @ J - Jt @ M", "dM = -M @ Jt - J @ M"),
+    "dN: sign of Hess beta": ("- model.hess_beta(X, comp) - N @ J", "+ model.hess_beta(X, comp) - N @ J"),
+    "dS: sign of beta": ("dS = model.beta(X, comp)", "dS = -model.beta(X, comp)"),
+    "dA: gamma_ll dropped": ("dA = G[idx, comp, comp] * A", "dA = 0.0 * A"),
+    "RK4: weights of k3 and k4 exchanged": ("(b1 + 2.0 * b2 + 2.0 * b3 + b4)", "(b1 + 2.0 * b2 + b3 + 2.0 * b4)"),
+    "RK4: k3 from k1": ("k3 = rhs(model, comp, _axpy(y, 0.5 * h, k2))", "k3 = rhs(model, comp, _axpy(y, 0.5 * h, k1))"),
+}
+
+
+@pytest.mark.parametrize("name", list(ODE_MISTAKES))
+def test_P1_catches_planted_ode_mistake(name):
+    err = p1_error(load(*ODE_MISTAKES[name]))
+    assert err > 1e-4, (name, err)      # 100x the pin's bar
+
+
+HOP_MISTAKES = {
+    "phase jump conjugated": ("ens.phase[b] * (col[dest] / abs(col[dest]))",
+                              "ens.phase[b] * (col[dest].conjugate() / abs(col[dest]))"),
+    "weight update dropped": ("ens.logw[b] += ens.Lam[b]", "ens.logw[b] += 0.0"),
+    "coupling row instead of column": ("col = [complex(g) for g in G[t, :, l]]",
+                                       "col = [complex(g) for g in G[t, l, :]]"),
+}
+
+
+@pytest.mark.parametrize("name", list(HOP_MISTAKES))
+def test_P3_catches_planted_hop_mistake(name):
+    excess = p3_population_excess(load(*HOP_MISTAKES[name]))
+    assert excess > 2.0, (name, excess)   # twice the pin's band
+
+
+def test_P3_waiting_times_catch_out_rate_with_gamma_ll():
+    mod = load("out_rate = np.abs(G[idx, :, comp]).sum(1) - np.abs(G[idx, comp, comp])",
+               "out_rate = np.abs(G[idx, :, comp]).sum(1)")
+    assert p3_first_hop_pvalue(mod) < 1e-4
+
+
+def test_destination_pin_catches_uniform_destinations():
+    mod = load("            for j in order:\n                C = C + abs(col[j])\n                if U * R < C:",
+               "            for j in order:\n                C = C + R / len(order)\n                if U * R < C:")
+    dest = hop.forced_hop_destinations(mod)
+    assert abs((dest == 1).mean() - 0.9) > 0.2
+
+
+def test_QCLE_weight_invariant_catches_Lam_not_reset_at_a_hop():
+    # the x-independent populations do not see this one: the estimator's own standard error
+    # grows with the overcounted weights and widens the band
+    err = qcle_weight_error(load("ens.Lam[b] = 0.0", "ens.Lam[b] = ens.Lam[b]"))
+    assert err > 1e-3, err
+
+
+def test_P3_catches_hop_at_the_end_of_the_trial_step():
+    mod = load("theta = np.where(Ec <= L0c, 0.0, (Ec - L0c) / (L1c - L0c))",
+               "theta = np.where(Ec <= L0c, 0.0, np.ones_like(Ec))")
+    assert p3_first_hop_pvalue(mod) < 1e-6
