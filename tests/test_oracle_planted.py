@@ -10,7 +10,10 @@ the exponential law, destinations of forced hops against unequal rates,
 tests/test_oracle_hopping.py) and the QCLE weight invariant
 Re omega = 2 |theta(q_T) - theta(q_0)| (tests/test_oracle_qcle.py) for the hop
 bookkeeping of Sec. 2.4.  The unchanged source, loaded the same way, passes
-every check.
+every check.  The same is done for oracle/observables.py against its pins:
+the beam integral against two-dimensional quadrature, the field summed on a
+fine grid against the populations, and the field's momentum expectation
+against P.
 """
 
 import math
@@ -20,22 +23,24 @@ import numpy as np
 import pytest
 from scipy import linalg, stats
 
+import oracle.observables as obs_base
 import oracle.shgb as base
 from oracle import models, observables, sampling
 
 import test_oracle_gb as gb
 import test_oracle_hopping as hop
+import test_oracle_observables as obs_pins
 import test_oracle_qcle as qcle
 
 
-def load(old=None, new=None):
-    src = open(base.__file__).read()
+def load(old=None, new=None, original=base):
+    src = open(original.__file__).read()
     if old is not None:
         assert src.count(old) == 1, old
         src = src.replace(old, new)
-    mod = types.ModuleType("oracle.shgb_planted")
-    mod.__file__, mod.__package__ = base.__file__, "oracle"
-    exec(compile(src, base.__file__, "exec"), mod.__dict__)
+    mod = types.ModuleType(original.__name__ + "_planted")
+    mod.__file__, mod.__package__ = original.__file__, "oracle"
+    exec(compile(src, original.__file__, "exec"), mod.__dict__)
     return mod
 
 
@@ -149,3 +154,54 @@ def test_P3_catches_hop_at_the_end_of_the_trial_step():
     mod = load("theta = np.where(Ec <= L0c, 0.0, (Ec - L0c) / (L1c - L0c))",
                "theta = np.where(Ec <= L0c, 0.0, np.ones_like(Ec))")
     assert p3_first_hop_pvalue(mod) < 1e-6
+
+
+def dblquad_error(obs, seed=0, eps=0.4):
+    """Relative error of the closed-form beam integral against quadrature (the pin: 1e-8)."""
+    e = obs_pins.random_beam(2, np.random.default_rng(seed), eps)
+    got = obs.beam_integrals(e, eps)[0]
+    return abs(got - obs_pins.dblquad_integral(e, eps)) / max(1.0, abs(got))
+
+
+def grid_error(obs):
+    """Largest |grid integral of the field - population| relative to the largest population
+    (the pin: 1e-9)."""
+    integral, pops = obs_pins.grid_integral_and_populations(obs)
+    ref = pops[:, 0] + 1j * pops[:, 1]
+    return np.abs(integral - ref).max() / np.abs(ref).max()
+
+
+def test_unchanged_observables_pass_their_checks():
+    obs = load(original=obs_base)
+    assert dblquad_error(obs) < 1e-8 and grid_error(obs) < 1e-9 and momentum_error(obs) < 1e-9
+
+
+OBSERVABLE_MISTAKES = {
+    "det(Z)^(+1/2)": ("/ sqrt_det * np.exp(-quad / (2.0 * eps))", "* sqrt_det * np.exp(-quad / (2.0 * eps))"),
+    "sign of P^T Z^-1 P": ("sqrt_det * np.exp(-quad / (2.0 * eps))", "sqrt_det * np.exp(quad / (2.0 * eps))"),
+    "conjugate Z in the integral": ("    Z = ens.M + 1j * ens.N\n    lam = np.linalg.eigvals(Z)",
+                                    "    Z = ens.M - 1j * ens.N\n    lam = np.linalg.eigvals(Z)"),
+    "phase exp(i S / eps) dropped from the integral": (
+        "return beam_weights(ens) * np.exp(1j * ens.S / eps) * gauss", "return beam_weights(ens) * gauss"),
+    "field: sign of the linear term": ("np.exp(-quad / (2.0 * eps) + 1j * lin / eps)",
+                                       "np.exp(-quad / (2.0 * eps) - 1j * lin / eps)"),
+    "field: M instead of Z": ('quad = np.einsum("kqa,kab,kqb->kq", y, Z[sl], y)',
+                              'quad = np.einsum("kqa,kab,kqb->kq", y, ens.M[sl], y)'),
+}
+
+
+def momentum_error(obs):
+    """Largest |<-i eps grad> - P| of one beam's field (the pin: 1e-9)."""
+    e, _, p_mean = obs_pins.field_moments(obs)
+    return np.abs(p_mean - e.P[0]).max()
+
+
+@pytest.mark.parametrize("name", list(OBSERVABLE_MISTAKES))
+def test_observable_pins_catch_planted_mistake(name):
+    obs = load(*OBSERVABLE_MISTAKES[name], original=obs_base)
+    if name == "field: sign of the linear term":
+        # the grid integral is even in P and does not see this one; the momentum pin does
+        err = momentum_error(obs)
+    else:
+        err = grid_error(obs) if name.startswith("field") else dblquad_error(obs)
+    assert err > 1e-4, (name, err)
