@@ -19,11 +19,11 @@ from oracle import models
 PAR = dict(A=0.01, B=1.6, C=0.005, D=1.0, mass=2000.0)
 
 
-def qcle(d=1):
+def qcle(d=1, mod=models):
     if d == 1:
-        return models.QCLE(**PAR)
+        return mod.QCLE(**PAR)
     rng = np.random.default_rng(5)
-    return models.QCLE(**PAR, d=d, lam=1e-3, bath_omega=rng.uniform(0.002, 0.02, d - 1))
+    return mod.QCLE(**PAR, d=d, lam=1e-3, bath_omega=rng.uniform(0.002, 0.02, d - 1))
 
 
 def vmat(mdl, r):
@@ -37,21 +37,30 @@ def vmat(mdl, r):
     return np.array([[a + vb, c], [c, -a + vb]])
 
 
-@pytest.mark.parametrize("d", [1, 3])
-def test_energies_match_eigvalsh(d):
-    mdl = qcle(d)
+def energy_errors(d, mod=models):
+    """Energies of both surfaces against numpy.linalg.eigvalsh of the diabatic matrix."""
+    mdl = qcle(d, mod)
     rng = np.random.default_rng(1)
     r = rng.normal(0, 1.5, size=(50, d))
+    out = []
     for comp, pick in ((0, 1), (1, 0)):
         E = mdl.energy(r, np.full(50, comp))
         ref = np.array([np.linalg.eigvalsh(vmat(mdl, ri))[pick] for ri in r])
+        out.append((E, ref))
+    return out
+
+
+@pytest.mark.parametrize("d", [1, 3])
+def test_energies_match_eigvalsh(d):
+    for E, ref in energy_errors(d):
         np.testing.assert_allclose(E, ref, rtol=1e-13, atol=1e-16)
 
 
-def test_d21_is_derivative_of_eigenvector_angle():
+def d21_and_angle_errors(mod=models):
+    """Largest |d21 - d(angle)/dq| (relative to max(1, |fd|)) and |mixing angle - angle| on a grid."""
     # upper eigenvector (cos t, sin t) with t in (0, pi/2) because V12 > 0;
     # d21 = <phi2 | d phi1/dq> = dt/dq for phi2 = (-sin t, cos t)
-    mdl = qcle(1)
+    mdl = qcle(1, mod)
     h = 1e-5
 
     def angle(q):
@@ -59,10 +68,17 @@ def test_d21_is_derivative_of_eigenvector_angle():
         up = v[:, 1] * np.sign(v[0, 1] + v[1, 1])
         return math.atan2(up[1], up[0])
 
+    e_d21 = e_ang = 0.0
     for q in np.linspace(-3, 3, 25):
         fd = (angle(q + h) - angle(q - h)) / (2 * h)
-        assert abs(mdl.d21(np.array([q]))[0] - fd) <= 1e-6 * max(1.0, abs(fd)), q
-        assert abs(mdl.mixing_angle(np.array([q]))[0] - angle(q)) < 1e-12
+        e_d21 = max(e_d21, abs(mdl.d21(np.array([q]))[0] - fd) / max(1.0, abs(fd)))
+        e_ang = max(e_ang, abs(mdl.mixing_angle(np.array([q]))[0] - angle(q)))
+    return e_d21, e_ang
+
+
+def test_d21_is_derivative_of_eigenvector_angle():
+    e_d21, e_ang = d21_and_angle_errors()
+    assert e_d21 <= 1e-6 and e_ang < 1e-12
 
 
 def test_s_derivatives_high_precision():

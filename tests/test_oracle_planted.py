@@ -13,7 +13,8 @@ bookkeeping of Sec. 2.4.  The unchanged source, loaded the same way, passes
 every check.  The same is done for oracle/observables.py against its pins:
 the beam integral against two-dimensional quadrature, the field summed on a
 fine grid against the populations, and the field's momentum expectation
-against P.
+against P; and for the QCLE coefficients of oracle/models.py against the
+energies of numpy.linalg.eigvalsh and the derivative of the eigenvector angle.
 """
 
 import math
@@ -23,12 +24,14 @@ import numpy as np
 import pytest
 from scipy import linalg, stats
 
+import oracle.models as models_base
 import oracle.observables as obs_base
 import oracle.shgb as base
 from oracle import models, observables, sampling
 
 import test_oracle_gb as gb
 import test_oracle_hopping as hop
+import test_oracle_model as model_pins
 import test_oracle_observables as obs_pins
 import test_oracle_qcle as qcle
 
@@ -204,4 +207,34 @@ def test_observable_pins_catch_planted_mistake(name):
         err = momentum_error(obs)
     else:
         err = grid_error(obs) if name.startswith("field") else dblquad_error(obs)
+    assert err > 1e-4, (name, err)
+
+
+def energy_error(mod):
+    """Largest relative error of the surface energies against eigvalsh (the pin: 1e-13)."""
+    return max(np.abs(E - ref).max() / np.abs(ref).max() for E, ref in model_pins.energy_errors(1, mod))
+
+
+def test_unchanged_model_passes_its_checks():
+    mod = load(original=models_base)
+    e_d21, e_ang = model_pins.d21_and_angle_errors(mod)
+    assert energy_error(mod) < 1e-13 and e_d21 <= 1e-6 and e_ang < 1e-12
+
+
+MODEL_MISTAKES = {
+    "s without the factor 4 on V12^2": ("s = sp.sqrt((V11 - V22) ** 2 + 4 * V12**2) / 2",
+                                        "s = sp.sqrt((V11 - V22) ** 2 + V12**2) / 2"),
+    "V22 = +a": ("V11, V22, V12 = a, -a, self.C", "V11, V22, V12 = a, a, self.C"),
+    "d21 with the opposite sign": (
+        "d21 = ((V11 - V22) * sp.diff(V12, q) - V12 * sp.diff(V11 - V22, q)) / (",
+        "d21 = (V12 * sp.diff(V11 - V22, q) - (V11 - V22) * sp.diff(V12, q)) / ("),
+    "d21 denominator without the factor 4": ("/ (\n            (V11 - V22) ** 2 + 4 * V12**2)",
+                                             "/ (\n            (V11 - V22) ** 2 + V12**2)"),
+}
+
+
+@pytest.mark.parametrize("name", list(MODEL_MISTAKES))
+def test_model_pins_catch_planted_mistake(name):
+    mod = load(*MODEL_MISTAKES[name], original=models_base)
+    err = model_pins.d21_and_angle_errors(mod)[0] if name.startswith("d21") else energy_error(mod)
     assert err > 1e-4, (name, err)
