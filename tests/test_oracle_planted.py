@@ -14,7 +14,9 @@ every check.  The same is done for oracle/observables.py against its pins:
 the beam integral against two-dimensional quadrature, the field summed on a
 fine grid against the populations, and the field's momentum expectation
 against P; and for the QCLE coefficients of oracle/models.py against the
-energies of numpy.linalg.eigvalsh and the derivative of the eigenvector angle.
+energies of numpy.linalg.eigvalsh and the derivative of the eigenvector angle;
+and for the initial sampling of oracle/sampling.py against the law of the
+centres and the unit beam integral.
 """
 
 import math
@@ -26,6 +28,7 @@ from scipy import linalg, stats
 
 import oracle.models as models_base
 import oracle.observables as obs_base
+import oracle.sampling as sampling_base
 import oracle.shgb as base
 from oracle import models, observables, sampling
 
@@ -238,3 +241,23 @@ def test_model_pins_catch_planted_mistake(name):
     mod = load(*MODEL_MISTAKES[name], original=models_base)
     err = model_pins.d21_and_angle_errors(mod)[0] if name.startswith("d21") else energy_error(mod)
     assert err > 1e-4, (name, err)
+
+
+def test_unchanged_sampling_passes_its_checks():
+    err_c, z_q, err_std, p_ks = qcle.initial_law(load(original=sampling_base))
+    assert err_c < 1e-13 and z_q < 4.0 and err_std < 0.0134 and p_ks > 1e-3
+
+
+SAMPLING_MISTAKES = {
+    "A0 = (2 pi eps)^(+m/2)": ("ens.A[:] = (2.0 * math.pi * eps) ** (-m / 2.0)",
+                               "ens.A[:] = (2.0 * math.pi * eps) ** (m / 2.0)"),
+    "q_std not applied": ("x[0] = q_mean + q_std * normal(seed, gid, 0)", "x[0] = q_mean + normal(seed, gid, 0)"),
+    "uniform law on [p_a, p_a + p_b)": ("x[d] = p_a + (p_b - p_a) * uniform(seed, gid, d)",
+                                        "x[d] = p_a + p_b * uniform(seed, gid, d)"),
+}
+
+
+@pytest.mark.parametrize("name", list(SAMPLING_MISTAKES))
+def test_sampling_pin_catches_planted_mistake(name):
+    err_c, z_q, err_std, p_ks = qcle.initial_law(load(*SAMPLING_MISTAKES[name], original=sampling_base))
+    assert err_c > 1e-3 or z_q > 8.0 or err_std > 0.05 or p_ks < 1e-6, name

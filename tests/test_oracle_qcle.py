@@ -14,6 +14,7 @@ import math
 
 import numpy as np
 import pytest
+from scipy import stats
 
 from oracle import models, observables, sampling, shgb
 
@@ -75,3 +76,19 @@ def test_trajectories_do_not_depend_on_eps(run):
     shgb.advance(mdl, e, 700, 0.5, 99)
     np.testing.assert_array_equal(e.X, ens.X[:20])
     np.testing.assert_array_equal(e.nhop, ens.nhop[:20])
+
+
+def initial_law(sampling_mod, n=2000):
+    """Sec. 2.5 sampling with q1 ~ N(-2.5, 0.3^2) and p1 ~ U[10, 30): (largest |beam integral - 1|,
+    |mean q1 + 2.5| in standard errors, |std q1 - 0.3|, KS p-value of p1 against U[10, 30))."""
+    mdl = models.QCLE(**PAR)
+    ens = sampling_mod.init_beams(mdl, n, EPS, 7, -2.5, 0.3, "uniform", 10.0, 30.0, 1)
+    c = observables.beam_integrals(ens, EPS)
+    q, p = ens.X[:, 0], ens.X[:, 1]
+    return (np.abs(c - 1.0).max(), abs(q.mean() + 2.5) / (0.3 / math.sqrt(n)), abs(q.std() - 0.3),
+            stats.kstest((p - 10.0) / 20.0, "uniform").pvalue)
+
+
+def test_initial_law_of_centres_and_amplitude():
+    err_c, z_q, err_std, p_ks = initial_law(sampling)
+    assert err_c < 1e-13 and z_q < 4.0 and err_std < 4 * 0.3 / math.sqrt(2 * 2000) and p_ks > 1e-3
