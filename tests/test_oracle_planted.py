@@ -16,7 +16,9 @@ fine grid against the populations, and the field's momentum expectation
 against P; and for the QCLE coefficients of oracle/models.py against the
 energies of numpy.linalg.eigvalsh and the derivative of the eigenvector angle;
 and for the initial sampling of oracle/sampling.py against the law of the
-centres and the unit beam integral.
+centres and the unit beam integral, and its bath modes against the ground
+state of each harmonic mode (energy, its kinetic and potential parts,
+q-p correlation, normality).
 """
 
 import math
@@ -261,3 +263,36 @@ SAMPLING_MISTAKES = {
 def test_sampling_pin_catches_planted_mistake(name):
     err_c, z_q, err_std, p_ks = qcle.initial_law(load(*SAMPLING_MISTAKES[name], original=sampling_base))
     assert err_c > 1e-3 or z_q > 8.0 or err_std > 0.05 or p_ks < 1e-6, name
+
+
+def test_unchanged_sampling_passes_the_bath_law():
+    z_energy, z_parts, corr, p_ks = qcle.bath_law(load(original=sampling_base))
+    assert z_energy < 4.0 and z_parts < 4.0 and corr < 4.0 and p_ks > 1e-3
+
+
+BATH_MISTAKES = {
+    "mass swapped between the two widths": (
+        "x[k] = math.sqrt(eps / (2.0 * model.mass * w)) * normal(seed, gid, k)\n"
+        "            x[d + k] = math.sqrt(eps * model.mass * w / 2.0) * normal(seed, gid, d + k)",
+        "x[k] = math.sqrt(eps * model.mass / (2.0 * w)) * normal(seed, gid, k)\n"
+        "            x[d + k] = math.sqrt(eps * w / (2.0 * model.mass)) * normal(seed, gid, d + k)"),
+    "frequency swapped between the two widths": (
+        "x[k] = math.sqrt(eps / (2.0 * model.mass * w)) * normal(seed, gid, k)\n"
+        "            x[d + k] = math.sqrt(eps * model.mass * w / 2.0) * normal(seed, gid, d + k)",
+        "x[k] = math.sqrt(eps * w / (2.0 * model.mass)) * normal(seed, gid, k)\n"
+        "            x[d + k] = math.sqrt(eps * model.mass / (2.0 * w)) * normal(seed, gid, d + k)"),
+    "factor 2 dropped from the position width": (
+        "x[k] = math.sqrt(eps / (2.0 * model.mass * w))", "x[k] = math.sqrt(eps / (model.mass * w))"),
+    "variance used as the momentum width": (
+        "x[d + k] = math.sqrt(eps * model.mass * w / 2.0) * normal", "x[d + k] = (eps * model.mass * w / 2.0) * normal"),
+    "position and momentum from the same normal": (
+        "x[d + k] = math.sqrt(eps * model.mass * w / 2.0) * normal(seed, gid, d + k)",
+        "x[d + k] = math.sqrt(eps * model.mass * w / 2.0) * normal(seed, gid, k)"),
+    "bath frequencies out by one mode": ("w = model.bath_omega[k - 1]", "w = model.bath_omega[k % (d - 1)]"),
+}
+
+
+@pytest.mark.parametrize("name", list(BATH_MISTAKES))
+def test_bath_law_catches_planted_mistake(name):
+    z_energy, z_parts, corr, p_ks = qcle.bath_law(load(*BATH_MISTAKES[name], original=sampling_base))
+    assert z_energy > 8.0 or z_parts > 8.0 or corr > 8.0 or p_ks < 1e-6, (name, z_energy, z_parts, corr, p_ks)
