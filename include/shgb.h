@@ -6,16 +6,16 @@
  * high-dimensional transport systems", arXiv:1703.06116.  A Monte Carlo
  * ensemble of complex Gaussian beams solves the n-component transport system
  *
- *   d_t u_i + alpha_i(x)^T grad u_i = (i/eps) beta_i(x) u_i + sum_j gamma_ij(x) u_j   (Sec. 1, eq. (1.1))
+ *   d_t u_i + alpha_i(x)^T grad u_i = (i/eps) beta_i(x) u_i + sum_j gamma_ij(x) u_j   (Sec. 1, eq:equations)
  *
  * Each beam follows the characteristic of its current component, carries a
- * phase, a complex Hessian and an amplitude (Sec. 2.3, eq. (2.24)), hops
+ * phase, a complex Hessian and an amplitude (Sec. 2.3, eq:shgb_odes), hops
  * between components at rates |gamma_jl| (Sec. 2.4) and updates its weight
  * exp(omega).  The solution estimate is U_i(x) = E[exp(omega) G(x) delta_{i,l}]
- * (Sec. 2.3, eq. (2.26)).
+ * (Sec. 2.3, eq:shgb).
  *
  * The model is the two-level quantum-classical Liouville equation of Sec. 3.3
- * (eqs. (3.5)-(3.6)) with nuclear mass, as the linear four-component system
+ * (eq:QCLE and the adiabatic quantities below it) with nuclear mass, as the linear four-component system
  * for (u11, u22, u21, u12 = conj u21); component order 0 = u11 (upper
  * adiabatic surface), 1 = u22 (lower), 2 = u21, 3 = u12.
  *
@@ -76,12 +76,12 @@ extern "C" {
  * p = (p1..pd), phase space x = (r, p), m = 2d.  Diabatic potential
  *   V11 =  A tanh(B q1) + Vb(r),  V22 = -A tanh(B q1) + Vb(r),  V12 = C exp(-D q1^2),
  *   Vb(r) = sum_{k=2..d} ( mass w_k^2 q_k^2 / 2 + lam q1 q_k ),
- * adiabatic energies and coupling d21 by eq. (3.6); transport fields
+ * adiabatic energies and coupling d21 by the adiabatic energies and d21 below eq:QCLE; transport fields
  * alpha_l = (p/mass, -grad E_l), phases beta = (0, 0, E1-E2, E2-E1), couplings
- * gamma from (p/mass).d21 as in eq. (3.5).  eps is the semiclassical
+ * gamma from (p/mass).d21 as in eq:QCLE.  eps is the semiclassical
  * parameter: it enters only the beam shape G, never the beam ODEs.
  *
- * Linear-quadratic systems (the class of Sec. 3.1, eq. (3.1) among them):
+ * Linear-quadratic systems (the class of Sec. 3.1, eq:ex1 among them):
  * x in R^2 (m = 2, d = 1), n_comp <= SHGB_NCOMP components with
  *   alpha_l(x) = a_l + J_l x,   beta_l(x) = b0_l + b_l.x + x^T H_l x / 2,
  *   gamma_jl constant complex,
@@ -93,7 +93,7 @@ extern "C" {
  * Stepping and hops of this kind are FP64 only.
  *
  * SHGB_MODEL_PAPER32: the two-component system with nonlinear coefficients
- * of Sec. 3.2, eq. (3.2), x in R^2 (d = 1), no parameters besides eps:
+ * of Sec. 3.2, eq:ex2, x in R^2 (d = 1), no parameters besides eps:
  *   alpha_1 = -(sin(x1 + x2), cos(x1 - x2)), alpha_2 = -(sin(x1 - x2), cos(x1 + x2)),
  *   beta_1 = sin|x|^2, beta_2 = cos|x|^2, gamma = |x|^2 [[-1, 5], [-5, -1/2]].
  * FP64 stepping and hops.                                                   */
@@ -123,7 +123,7 @@ typedef struct shgb_model {
  * [f * ld + b].  With T = m(m+1)/2 the fields are
  *   trajectory rows:  X[m], P[m], Zre[T], Zim[T]          (shgb_traj_fields(m))
  *   scalar rows:      S, Are, Aim, logw, phre, phim, Lam, E (SHGB_SCALAR_FIELDS)
- * Z = M + iN is the complex symmetric beam Hessian (Sec. 2, eq. (2.2)) packed
+ * Z = M + iN is the complex symmetric beam Hessian (Sec. 2, the beam G^eps) packed
  * by rows of its upper triangle ((i, j), i <= j, at i*m - i(i-1)/2 + j - i);
  * A the complex amplitude; Re omega = logw + Lam where Lam is the rate
  * integral since the last hop; exp(i Im omega) = phre + i phim; E the current
@@ -184,7 +184,7 @@ int shgb_init_beams(const shgb_model *model, const shgb_init_spec *spec,
 
 /* Advance every beam by `nsteps` intervals of length dt (Sec. 2.4 steps 3-5):
  * per interval a classical RK4 trial step of the beam ODEs (Sec. 2.3,
- * eq. (2.24)) on the current component; if the rate integral reaches the
+ * eq:shgb_odes) on the current component; if the rate integral reaches the
  * threshold, the hop time is found by linear interpolation of Lam, the system
  * is re-integrated to it, the hop is applied (shgb_hop) and the beam finishes
  * the interval on its new component, up to SHGB_HOP_CAP hops per interval.
@@ -206,7 +206,7 @@ int shgb_step_ensemble(const shgb_model *model, const shgb_state *st, int32_t ns
 int shgb_hop(const shgb_model *model, const shgb_state *st, const int32_t *idx,
              int64_t n_idx, uint64_t seed, uint64_t *diag, void *stream);
 
-/* Component populations (Sec. 2.3 eq. (2.26) integrated over x, Sec. 2.4
+/* Component populations (Sec. 2.3 eq:shgb integrated over x, Sec. 2.4
  * steps 6-7).  Per beam c = exp(logw+Lam) phase A exp(iS/eps)
  * (2 pi eps)^(m/2) det(Z)^(-1/2) exp(-P^T Z^-1 P / (2 eps)) with the branch of
  * det(Z)^(1/2) = prod of principal square roots of the LDL^T pivots.  out:
@@ -219,7 +219,17 @@ int64_t shgb_populations_workspace(int64_t n_beams, int32_t m);
 int shgb_populations(const shgb_model *model, const shgb_state *st, double *out,
                      void *work, int64_t work_bytes, uint64_t *diag, void *stream);
 
-/* Superposition at Q evaluation points (Sec. 2.3 eq. (2.26), Sec. 2.4 step 6):
+/* Sec. 2.4 step 7: the population estimates from the sums of shgb_populations
+ * (or of several shards' sums added together) over n_traj >= 1 trajectories.
+ * stats: device double[SHGB_NCOMP * 4]; for component i,
+ * stats[i*4 + {0, 1}] = Re, Im of the mean sum c / n_traj and
+ * stats[i*4 + {2, 3}] = the standard errors of the real and imaginary parts,
+ * sqrt((sum x^2 / n_traj - mean^2) / (n_traj - 1)) (variance clipped at zero;
+ * n_traj - 1 read as 1 when n_traj == 1).  sums: device double[SHGB_NCOMP * 5].
+ * Errors: EINVAL. */
+int shgb_population_stats(const double *sums, int64_t n_traj, double *stats, void *stream);
+
+/* Superposition at Q evaluation points (Sec. 2.3 eq:shgb, Sec. 2.4 step 6):
  * out[(i*Q + q)*2 + {0,1}] = Re, Im of sum_{k: l_k = i} exp(omega_k) G_k(x_q),
  * G(x) = A exp(-(x-X)^T Z (x-X)/(2 eps) + i P.(x-X)/eps + i S/eps), unnormalised
  * (divide by N_traj for U_i).  points: device double[Q * m], row-major.
@@ -233,7 +243,7 @@ int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double
                      int64_t Q, double *out, void *work, int64_t work_bytes, void *stream);
 
 /* ---- pathwise derivative of the populations ----------------------------
- * The derivative of the population sums (Sec. 2.3 eq. (2.26) integrated,
+ * The derivative of the population sums (Sec. 2.3 eq:shgb integrated,
  * as shgb_populations) after nsteps intervals, with respect to
  * theta = (A, B, C, D, p_mean): the potential parameters and a common
  * shift of every beam's initial p1 (the mean initial momentum).  The
@@ -254,7 +264,7 @@ int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double
  * component i at the end (entries of unselected directions are left as
  * they were).  work: device, >= shgb_population_tangent_workspace(n_beams).
  * Errors: EINVAL, EWORKSPACE, EUNSUPPORTED (other d, mixed state, LINQUAD or
- * eq. (3.2) model). */
+ * eq:ex2 model). */
 #define SHGB_NTHETA 5
 int64_t shgb_population_tangent_workspace(int64_t n_beams);
 int shgb_population_tangent(const shgb_model *model, const shgb_state *st, int32_t nsteps, double dt,

@@ -12,14 +12,14 @@ high-dimensional transport systems" (arXiv:1703.06116):
 * ``philox``      Philox4x64-10 counter-based generator (Salmon et al., SC'11),
                   the source of every random number the method draws.
 * ``models``      coefficient functions alpha_i, beta_i, gamma_ij of the
-                  transport system (Sec. 1, eq. (1.1)): the two-level QCLE of
+                  transport system (Sec. 1, eq:equations): the two-level QCLE of
                   Sec. 3.3 written as a four-component instance, plus two
                   test families with closed-form solutions.
 * ``sampling``    initial beam parameters (Sec. 2.5, step 2 of Sec. 2.4).
-* ``shgb``        the beam ODEs (Sec. 2.3, eq. (2.24)), classical RK4, the
+* ``shgb``        the beam ODEs (Sec. 2.3, eq:shgb_odes), classical RK4, the
                   hop-time / hop / weight algorithm (Sec. 2.4 steps 3-5).
 * ``observables`` the estimator U_i = E[exp(omega) G delta_{i,l_t}]
-                  (Sec. 2.3, eq. (2.26)): populations and the superposition
+                  (Sec. 2.3, eq:shgb): populations and the superposition
                   at evaluation points.
 
 Every floating point quantity is float64 (complex128 for complex values).

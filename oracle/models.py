@@ -1,4 +1,4 @@
-"""Coefficients of the transport system (Sec. 1, eq. (1.1)) for the oracle.
+"""Coefficients of the transport system (Sec. 1, eq:equations) for the oracle.
 
     d_t u_i + alpha_i(x)^T grad u_i = (i/eps) beta_i(x) u_i + sum_j gamma_ij(x) u_j
 
@@ -15,22 +15,22 @@ Each model exposes, vectorised over beams (``X`` is (N, m), ``comp`` is (N,)):
 Models:
 
 * ``QCLE``    the two-level quantum-classical Liouville equation of Sec. 3.3
-  (eq. (3.5), adiabatic quantities eq. (3.6)) with a nuclear mass, written as
+  (eq:QCLE, adiabatic quantities the adiabatic energies and d21 below eq:QCLE) with a nuclear mass, written as
   a linear four-component system for (u11, u22, u21, u12 := conj u21).
   Component order: 0 = u11 (upper surface E1, the '+' root), 1 = u22 (lower
   surface E2), 2 = u21, 3 = u12.  Diabatic potential
       V11 = A tanh(B q1) + Vb(r),  V22 = -A tanh(B q1) + Vb(r),
       V12 = C exp(-D q1^2),
       Vb(r) = sum_{k>=2} ( M w_k^2 q_k^2 / 2 + lam q1 q_k )  (d > 1 only).
-  The adiabatic energies and d21 are taken from eq. (3.6) symbolically
+  The adiabatic energies and d21 are taken from the adiabatic energies and d21 below eq:QCLE symbolically
   (SymPy) and differentiated symbolically in q1; the quadratic bath part is
   differentiated by hand.
 * ``LinQuad`` alpha linear, beta quadratic, gamma constant: the class of
   Sec. 3.1 for which the Gaussian beam ansatz has no modelling error.  With
   alpha = 0 and constant beta it is the x-independent system whose exact
-  solution is a matrix exponential (Sec. 2.2, eq. (2.11)).
+  solution is a matrix exponential (Sec. 2.2, eq:tilde_gamma).
 * ``Paper32`` the two-component system with nonlinear coefficients of
-  Sec. 3.2, eq. (3.2), in the form d_t u + alpha.grad u = (i/eps) beta u
+  Sec. 3.2, eq:ex2, in the form d_t u + alpha.grad u = (i/eps) beta u
   + gamma u: the transport fields are minus the printed drifts,
   beta_1 = sin|x|^2, beta_2 = cos|x|^2, and gamma = |x|^2 [[-1, 5], [-5, -1/2]].
 """
@@ -57,7 +57,7 @@ class QCLE:
         q = sp.Symbol("q", real=True)
         a = self.A * sp.tanh(self.B * q)          # q1-dependent part of V11 (V22 = -a)
         V11, V22, V12 = a, -a, self.C * sp.exp(-self.D * q**2)
-        # eq. (3.6): E_{1,2} = (V11+V22)/2 +- sqrt((V11-V22)^2 + 4 V12^2)/2
+        # the adiabatic energies and d21 below eq:QCLE: E_{1,2} = (V11+V22)/2 +- sqrt((V11-V22)^2 + 4 V12^2)/2
         s = sp.sqrt((V11 - V22) ** 2 + 4 * V12**2) / 2
         d21 = ((V11 - V22) * sp.diff(V12, q) - V12 * sp.diff(V11 - V22, q)) / (
             (V11 - V22) ** 2 + 4 * V12**2)
@@ -102,7 +102,7 @@ class QCLE:
         H[:, 0, 0] += self.sigma[comp] * self.s(r[:, 0], 2)
         return H
 
-    # --- coefficients of eq. (1.1) --------------------------------------------
+    # --- coefficients of eq:equations --------------------------------------------
     def _split(self, X):
         return X[:, : self.d], X[:, self.d:]
 
@@ -140,7 +140,7 @@ class QCLE:
         return H
 
     def kappa(self, X):
-        """(p/M) . d21(r): the real coupling coefficient of eq. (3.5)."""
+        """(p/M) . d21(r): the real coupling coefficient of eq:QCLE."""
         return X[:, self.d] / self.mass * self.d21(X[:, 0])
 
     def gamma(self, X):
@@ -200,7 +200,7 @@ class LinQuad:
 
 
 class Paper32:
-    """Eq. (3.2): alpha_1 = -(sin(x1 + x2), cos(x1 - x2)), alpha_2 = -(sin(x1 - x2), cos(x1 + x2)),
+    """Eq:ex2: alpha_1 = -(sin(x1 + x2), cos(x1 - x2)), alpha_2 = -(sin(x1 - x2), cos(x1 + x2)),
     beta_1 = sin(r^2), beta_2 = cos(r^2) with r^2 = x1^2 + x2^2,
     gamma = r^2 [[-1, 5], [-5, -1/2]] (row receives from column).  Derivatives by hand."""
 

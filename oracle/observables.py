@@ -1,7 +1,7 @@
-"""Observables of the SHGB estimator (oracle), Sec. 2.3 eq. (2.26) and Sec. 2.4 steps 6-7.
+"""Observables of the SHGB estimator (oracle), Sec. 2.3 eq:shgb and Sec. 2.4 steps 6-7.
 
     U_i(T, x) = E[ exp(omega(T)) G(T; x) delta_{i, l_T} ]
-    G(x) = A exp( -(x-X)^T (M + iN) (x-X) / (2 eps) + i P.(x-X)/eps + i S/eps )   (Sec. 2, eq. (2.2))
+    G(x) = A exp( -(x-X)^T (M + iN) (x-X) / (2 eps) + i P.(x-X)/eps + i S/eps )   (Sec. 2, the beam G^eps)
 
 with exp(omega) = exp(logw + Lam) * phase.
 

@@ -86,7 +86,7 @@ class Ensemble:
 
 
 def rhs(model, comp, y):
-    """Right-hand side of the beam ODEs, Sec. 2.3 eq. (2.24), on component l = comp.
+    """Right-hand side of the beam ODEs, Sec. 2.3 eq:shgb_odes, on component l = comp.
 
     dX/dt = alpha_l, dS/dt = beta_l, dP/dt = grad beta_l - J^T P,
     dA/dt = gamma_ll A, dM/dt = -M J - J^T M,

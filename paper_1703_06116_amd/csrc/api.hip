@@ -21,6 +21,7 @@ hipError_t launch_hop(const DevModel &, const shgb_state &, const int32_t *, int
 hipError_t launch_philox(uint64_t, const uint64_t *, uint64_t *, int64_t, hipStream_t);
 int64_t pop_workspace_bytes(int64_t, int);
 hipError_t launch_populations(const DevModel &, const shgb_state &, double *, void *, uint64_t *, hipStream_t);
+hipError_t launch_population_stats(const double *, int64_t, double *, hipStream_t);
 int64_t recon_m2_workspace_bytes(int64_t, int64_t);
 hipError_t launch_recon_m2(const DevModel &, const shgb_state &, const double *, int64_t, double *, void *,
                            hipStream_t);
@@ -249,6 +250,11 @@ int shgb_populations(const shgb_model *model, const shgb_state *st, double *out,
   if (st->m != 2 && st->m != 4 && st->m != 6 && st->m != 8 && st->m != 24) return SHGB_EUNSUPPORTED;
   if (work_bytes < pop_workspace_bytes(st->n_beams, st->m)) return SHGB_EWORKSPACE;
   return hip_status(launch_populations(md, *st, out, work, diag, (hipStream_t)stream));
+}
+
+int shgb_population_stats(const double *sums, int64_t n_traj, double *stats, void *stream) {
+  if (!sums || !stats || n_traj < 1) return SHGB_EINVAL;
+  return hip_status(launch_population_stats(sums, n_traj, stats, (hipStream_t)stream));
 }
 
 int64_t shgb_reconstruct_workspace(int64_t n_beams, int32_t m, int64_t Q) {

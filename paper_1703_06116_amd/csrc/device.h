@@ -97,7 +97,7 @@ __host__ __device__ inline U64x4 draw(uint64_t seed, uint64_t gid, uint64_t inde
 __host__ __device__ inline double u01(uint64_t w) { return ((double)(w >> 12) + 0.5) * 0x1p-52; }
 
 // ---------------------------------------------------------------------------
-// QCLE adiabatic quantities along q1 (Sec. 3.3, eq. (3.6)):
+// QCLE adiabatic quantities along q1 (Sec. 3.3, the adiabatic energies and d21 below eq:QCLE):
 //   a = A tanh(Bq), c = C exp(-Dq^2), s = sqrt(a^2 + c^2) = (E1 - E2)/2,
 //   d21 = (a c' - c a') / (2 s^2);
 // with derivatives of s up to third order (the Hessian of E feeds the beam
@@ -237,7 +237,7 @@ __host__ __device__ inline double comp_sigma(int l) { return l == 0 ? 1.0 : (l =
 __host__ __device__ inline double comp_bcoef(int l) { return l == 2 ? 2.0 : (l == 3 ? -2.0 : 0.0); }
 
 // Column l of gamma (row j receives from l) for the coupling kappa = (p/M).d21,
-// eq. (3.5) written for (u11, u22, u21, u12): gamma_jl = sign(l, j) kappa with
+// eq:QCLE written for (u11, u22, u21, u12): gamma_jl = sign(l, j) kappa with
 //   l = 0: (0, 0, -1, -1);  l = 1: (0, 0, 1, 1);  l = 2, 3: (1, -1, 0, 0).
 // Written without branches: hipcc for gfx950 (ROCm 7.2) miscompiled the
 // equivalent if/else chain, leaving gamma_1l = 0 for l = 2, 3 in the

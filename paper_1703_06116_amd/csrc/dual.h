@@ -56,7 +56,7 @@ struct Q1Du {
   Du s, s1, s2, s3, d21;
 };
 
-// The two-level quantities of Sec. 3.3 eq. (3.6) and their q-derivatives,
+// The two-level quantities of Sec. 3.3 the adiabatic energies and d21 below eq:QCLE and their q-derivatives,
 // the same formulas as the FP64 stepping kernel, on (value, derivative) pairs.
 __device__ inline Q1Du qcle_q1_du(const QcleDu &p, Du q) {
   const Du x = p.B * q;

@@ -1,4 +1,4 @@
-// Component populations (Sec. 2.3 eq. (2.26) integrated over x; Sec. 2.4
+// Component populations (Sec. 2.3 eq:shgb integrated over x; Sec. 2.4
 // steps 6-7).  For each beam
 //   c = exp(logw + Lam) phase A exp(iS/eps) (2 pi eps)^(m/2) det(Z)^(-1/2)
 //       exp(-P^T Z^-1 P / (2 eps)),
@@ -197,6 +197,29 @@ pop_final_kernel(const double *__restrict__ partial, int64_t nblocks, double *__
 #pragma unroll
     for (int k = 0; k < kPopVals; ++k) acc[k] += partial[p * kPopVals + k];
   block_sum_store(acc, out);
+}
+
+// Sec. 2.4 step 7: the estimate of a component's population is its sum over
+// trajectories divided by N_traj.  Per component i, from the raw sums
+// {sum Re c, sum Im c, sum (Re c)^2, sum (Im c)^2, count}: the mean and its
+// standard error sqrt((E[x^2] - E[x]^2) / (N_traj - 1)) for the real and
+// imaginary parts (the variance clipped at zero against rounding).
+__global__ void pop_stats_kernel(const double *__restrict__ sums, double n_traj, double *__restrict__ stats) {
+  const int i = threadIdx.x;
+  if (i >= SHGB_NCOMP) return;
+  const double *s = sums + 5 * i;
+  const double mr = s[0] / n_traj, mi = s[1] / n_traj;
+  const double vr = fmax(s[2] / n_traj - mr * mr, 0.0), vi = fmax(s[3] / n_traj - mi * mi, 0.0);
+  const double k = n_traj > 1.0 ? n_traj - 1.0 : 1.0;
+  stats[4 * i + 0] = mr;
+  stats[4 * i + 1] = mi;
+  stats[4 * i + 2] = sqrt(vr / k);
+  stats[4 * i + 3] = sqrt(vi / k);
+}
+
+hipError_t launch_population_stats(const double *sums, int64_t n_traj, double *stats, hipStream_t stream) {
+  hipLaunchKernelGGL(pop_stats_kernel, dim3(1), dim3(64), 0, stream, sums, (double)n_traj, stats);
+  return hipGetLastError();
 }
 
 int64_t pop_workspace_bytes(int64_t n, int m) {

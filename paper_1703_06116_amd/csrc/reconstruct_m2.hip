@@ -1,5 +1,5 @@
 // Superposition of the beams at evaluation points for phase space m = 2
-// (Sec. 2.3 eq. (2.26), Sec. 2.4 step 6):
+// (Sec. 2.3 eq:shgb, Sec. 2.4 step 6):
 //   out_i(x) = sum_{k: l_k = i} exp(omega_k) A_k exp(-y^T Z_k y/(2 eps) + i P_k.y/eps + i S_k/eps),
 //   y = x - X_k.
 // A block owns a tile of points (one per thread, in registers) and a chunk of

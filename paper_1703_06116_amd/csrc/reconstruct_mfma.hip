@@ -1,5 +1,5 @@
 // Superposition at evaluation points for phase space m = 24 on the FP64
-// matrix cores (Sec. 2.3 eq. (2.26), Sec. 2.4 step 6).
+// matrix cores (Sec. 2.3 eq:shgb, Sec. 2.4 step 6).
 //
 // The exponent of beam k at point x is a fixed quadratic polynomial in x.
 // With x~ = x - c and X~ = X - c (c the mean of the points, to keep the terms

@@ -1,5 +1,5 @@
 // Superposition at evaluation points for phase space m = 4, 6, 8, FP64 on
-// the vector ALU (Sec. 2.3 eq. (2.26), Sec. 2.4 step 6).  A block owns 256
+// the vector ALU (Sec. 2.3 eq:shgb, Sec. 2.4 step 6).  A block owns 256
 // points (one per thread, kept in registers) and a chunk of beams; beams pass
 // through LDS in tiles whose coefficients are formed once per tile:
 //   weight w = exp(logw + Lam) phase A exp(iS/eps),  P/eps,  and the packed

@@ -1,7 +1,7 @@
 // Beam stepping and hops for linear-quadratic systems (m = 2): one thread
 // per beam, all intervals in registers, FP64.
 //
-// Beam ODEs (Sec. 2.3, eq. (2.24)) on component l with alpha = a + J x,
+// Beam ODEs (Sec. 2.3, eq:shgb_odes) on component l with alpha = a + J x,
 // beta = b0 + b.x + x^T H x / 2 and constant gamma:
 //   X' = a + J X,                 S' = beta(X),
 //   P' = grad beta - J^T P = b + H X - J^T P,

@@ -1,7 +1,7 @@
 // Beam stepping for the one-dimensional QCLE (phase space m = 2): one thread
 // per beam, the whole beam state in registers for all nsteps intervals.
 //
-// Beam ODEs (Sec. 2.3, eq. (2.24)) on component l, x = (q, p), v = p/M:
+// Beam ODEs (Sec. 2.3, eq:shgb_odes) on component l, x = (q, p), v = p/M:
 //   X' = alpha_l = (v, -E_l'),  J = d alpha_l / dx = [[0, 1/M], [-E_l'', 0]]
 //   P' = grad beta_l - J^T P      = (beta_l' + E_l'' P_p, -P_q / M)
 //   Z' = -Z J - J^T Z + i (Hess(P.alpha_l) - Hess beta_l),  Z = M + iN,

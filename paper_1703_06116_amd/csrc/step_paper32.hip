@@ -1,11 +1,11 @@
 // Beam stepping for the nonlinear two-component system of Sec. 3.2,
-// eq. (3.2), x in R^2: one thread per beam, all intervals in registers,
+// eq:ex2, x in R^2: one thread per beam, all intervals in registers,
 // FP64.  In the form d_t u + alpha.grad u = (i/eps) beta u + gamma u,
 // with u = x1 + x2, v = x1 - x2, r2 = |x|^2:
 //   alpha_1 = -(sin u, cos v),  alpha_2 = -(sin v, cos u),
 //   beta_1 = sin r2,            beta_2 = cos r2,
 //   gamma = r2 [[-1, 5], [-5, -1/2]]   (row receives from column).
-// Beam ODEs (Sec. 2.3, eq. (2.24)) on component l:
+// Beam ODEs (Sec. 2.3, eq:shgb_odes) on component l:
 //   X' = alpha_l, S' = beta_l, P' = grad beta_l - J^T P, A' = gamma_ll A,
 //   Z' = -Z J - J^T Z + i (Hess(P.alpha_l) - Hess beta_l),
 //   Lam' = sum_{j != l} |gamma_jl| = 5 r2,

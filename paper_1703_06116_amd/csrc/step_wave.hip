@@ -5,7 +5,7 @@
 // Model (Sec. 3.3 with a harmonic bath): E_l(r) = Vb(r) + sigma_l s(q1),
 // Vb = sum_{k>=1} (M w_k^2 q_k^2 / 2 + lam q1 q_k), so H = Hess E_l is an
 // arrowhead matrix: H_00 = sigma s'', H_0k = H_k0 = lam, H_kk = M w_k^2.
-// With J = [[0, I/M], [-H, 0]] the beam ODEs of Sec. 2.3 eq. (2.24) read, for
+// With J = [[0, I/M], [-H, 0]] the beam ODEs of Sec. 2.3 eq:shgb_odes read, for
 // Z = [[Zrr, Zrp], [Zrp^T, Zpp]] = M + iN,
 //   Zrr' = Zrp H + (Zrp H)^T + i B,   B = e0 e0^T (-P_p0 sigma s''' - beta'')
 //   Zrp' = H Zpp - Zrr / M

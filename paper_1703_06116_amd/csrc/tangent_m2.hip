@@ -4,9 +4,9 @@
 //
 // Every quantity of the stepping loop carries its value and its derivative
 // along one direction theta_j of theta = (A, B, C, D, p_mean): the RK4
-// stages of eq. (2.24), the hop time theta = (E - Lam)/(Lam' - Lam) and the
+// stages of eq:shgb_odes, the hop time theta = (E - Lam)/(Lam' - Lam) and the
 // shortened step it sets, the weight log w += Lam at each hop, and finally
-// the closed-form beam integral c of Sec. 2.3 eq. (2.26).  The discrete
+// the closed-form beam integral c of Sec. 2.3 eq:shgb.  The discrete
 // events are frozen at the values: every hop test, destination and phase
 // sign is decided by the value part exactly as in the FP64 stepping kernel,
 // and the thresholds E (drawn numbers) carry no derivative.  This is the

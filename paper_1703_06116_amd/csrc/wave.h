@@ -1,6 +1,6 @@
 // The pair-group layout of a beam with phase space m = 2d > 2 over a group
 // of LPB lanes, and the right-hand side of its beam ODEs (Sec. 2.3
-// eq. (2.24) with the arrowhead Hessian of the QCLE with a harmonic bath,
+// eq:shgb_odes with the arrowhead Hessian of the QCLE with a harmonic bath,
 // Sec. 3.3), generic in the element type T of the stage values: float and
 // double for the stepping kernels, a (value, derivative) pair for the
 // tangent kernel.  The equations and the work split are stated at the top

@@ -95,6 +95,7 @@ def _load():
         "shgb_hop": (I32, [P(Model), P(StateDesc), V, I64, U64, V, V]),
         "shgb_populations_workspace": (I64, [I64, I32]),
         "shgb_populations": (I32, [P(Model), P(StateDesc), V, V, I64, V, V]),
+        "shgb_population_stats": (I32, [V, I64, V, V]),
         "shgb_reconstruct_workspace": (I64, [I64, I32, I64]),
         "shgb_reconstruct": (I32, [P(Model), P(StateDesc), V, I64, V, V, I64, V]),
         "shgb_philox": (I32, [U64, V, V, I64, V]),
@@ -122,7 +123,8 @@ def _load():
 _lib = _load()
 
 EXPORTED = ("shgb_init_beams", "shgb_step_ensemble", "shgb_hop", "shgb_populations_workspace",
-            "shgb_populations", "shgb_reconstruct_workspace", "shgb_reconstruct", "shgb_philox",
+            "shgb_populations", "shgb_population_stats",
+            "shgb_reconstruct_workspace", "shgb_reconstruct", "shgb_philox",
             "shgb_strerror", "shgb_version", "shgb_abi_sizes", "shgb_batch_table_bytes", "shgb_batch_prepare",
             "shgb_step_batched", "shgb_population_tangent_workspace", "shgb_population_tangent")
 
@@ -184,7 +186,7 @@ def make_linquad_model(eps, a, J, b0, b, H, gamma):
 
 
 def make_paper32_model(eps):
-    """The nonlinear two-component system of eq. (3.2) (see include/shgb.h)."""
+    """The nonlinear two-component system of eq:ex2 (see include/shgb.h)."""
     mdl = Model()
     mdl.kind, mdl.d, mdl.mass, mdl.eps = 3, 1, 1.0, float(eps)
     return mdl
@@ -373,15 +375,27 @@ def philox(seed, counters, stream=None):
     return out
 
 
+def population_stats(sums, n_traj, out=None, stream=None):
+    """Means and standard errors per component from the raw sums of ``populations`` (a device
+    tensor of 4 x 5 doubles), computed on the device: a (4, 4) float64 tensor of
+    (Re mean, Im mean, SE of Re, SE of Im)."""
+    assert sums.dtype == torch.float64 and sums.is_contiguous() and sums.is_cuda
+    if out is None:
+        out = torch.empty((SHGB_NCOMP, 4), dtype=torch.float64, device=sums.device)
+    _check("shgb_population_stats", _lib.shgb_population_stats(_ptr(sums), int(n_traj), _ptr(out),
+                                                                 _stream(stream)))
+    return out
+
+
 def population_mean_se(sums, n_traj):
-    """Mean and standard error from the raw sums of ``populations`` (host numpy)."""
-    import numpy as np
-    s = np.asarray(sums, dtype=np.float64)
-    mean = (s[:, 0] + 1j * s[:, 1]) / n_traj
-    vr = np.maximum(s[:, 2] / n_traj - mean.real**2, 0.0)
-    vi = np.maximum(s[:, 3] / n_traj - mean.imag**2, 0.0)
-    k = max(n_traj - 1, 1)
-    return mean, np.sqrt(vr / k) + 1j * np.sqrt(vi / k)
+    """(mean, SE) as complex host numpy arrays of 4, from ``population_stats`` (the sums may be a
+    device tensor or host values, which are copied to the device)."""
+    if not torch.is_tensor(sums):
+        sums = torch.as_tensor(sums, dtype=torch.float64)
+    if not sums.is_cuda:
+        sums = sums.to(dtype=torch.float64, device="cuda").contiguous()
+    st = population_stats(sums, n_traj).cpu().numpy()
+    return st[:, 0] + 1j * st[:, 1], st[:, 2] + 1j * st[:, 3]
 
 
 def unpack(state):

@@ -111,3 +111,62 @@ def test_autotuner_picks_a_candidate(gpu, tmp_path, monkeypatch):
     again, _ = autotune.tune([gpu_model(c) for c in cs], states, [c["seed"] for c in cs], cs[0]["dt"])
     assert again == cfg                                                    # from the cache
     assert (tmp_path / "tune.json").exists()
+
+
+# Instances of the QCLE with the coupling C and eps spread as in the 64-instance workload
+# (C in [0.002, 0.01], eps in {0.01, 0.02, 0.05}), uneven beam counts, beams started close to
+# the crossing so that they hop within the run.
+SPREAD_C = (0.002, 0.006, 0.01, 0.0043)
+SPREAD_EPS = (0.01, 0.02, 0.05, 0.02)
+
+
+def spread_instances(d, sizes):
+    out = []
+    for i, n in enumerate(sizes):
+        name = "qcle1d_1e4" if d == 1 else "qcle12d_2p18"
+        out.append(workloads.config(name, d=d, bath_omega=workloads.bath_omega(d), n_beams=n, q_mean=-1.2,
+                                    q_std=0.3, p_dist="normal", p_a=30.0 + 2.0 * i, p_b=1.0,
+                                    C=SPREAD_C[i], eps=SPREAD_EPS[i], seed=0x5EED0 + 17 * i))
+    return out
+
+
+@pytest.mark.parametrize("d,precision,sizes,nsteps", [
+    (1, "fp64", (700, 1, 257, 1500), 300),
+    (1, "mixed", (513, 64, 1025), 300),
+    (12, "fp64", (90, 7, 41, 33), 240),
+    (12, "mixed", (90, 7, 41, 33), 240),
+])
+def test_batch_instances_match_the_oracle(gpu, d, precision, sizes, nsteps):
+    """Every beam of every instance of one batched launch against the FP64 oracle run of its
+    instance from its global ids: hop counts and components bit-exact apart from oracle ties,
+    per-beam state within 1e-10 (FP64) or 1e-4 (mixed, oracle started from the float32-rounded
+    draws); each instance's population means within 1e-10 (FP64) or 1e-4 (mixed) of the sum of
+    |c| over its beams, computed on the device from the batched state."""
+    from oracle import observables, shgb as oshgb
+    from _parity import compare_states, oracle_init, oracle_model
+    cs = spread_instances(d, sizes)
+    sts = fresh_states(gpu, cs, precision)
+    diag = gpu.new_diag()
+    gpu.Batch([gpu_model(c) for c in cs], sts, [c["seed"] for c in cs]).step(nsteps, cs[0]["dt"], diag)
+    rtol = 1e-10 if precision == "fp64" else 1e-4
+    tie = oshgb.TIE_REL if precision == "fp64" else oshgb.TIE_REL_MIXED
+    hops = 0
+    for i, (c, st) in enumerate(zip(cs, sts)):
+        e = oracle_init(c, c["n_beams"], offset=1000 * i)
+        if precision == "mixed":
+            for f in ("X", "P", "M", "N"):
+                getattr(e, f)[:] = getattr(e, f).astype(np.float32).astype(np.float64)
+        oshgb.advance(oracle_model(c), e, nsteps, c["dt"], c["seed"], tie_rel=tie)
+        min_ok = (0.98 if precision == "fp64" else 0.9) if c["n_beams"] > 20 else 0.7
+        errs, ties = compare_states(gpu.unpack(st), e, rtol=rtol, min_ok=min_ok,
+                                    label=f"instance {i} C={c['C']} eps={c['eps']}")
+        hops += int(e.nhop.sum())
+        sums = gpu.populations(gpu_model(c), st)
+        mean, _ = gpu.population_mean_se(sums, c["n_beams"])
+        ok = (e.thr_ties == 0) & (e.dest_ties == 0)
+        if ok.all():
+            ref, _ = observables.population_mean_se(observables.populations(e, c["eps"]), c["n_beams"])
+            scale = np.abs(observables.beam_integrals(e, c["eps"])).sum() / c["n_beams"]
+            assert np.abs(mean - ref).max() <= rtol * scale, (i, mean, ref)
+        print(f"instance {i}: n={c['n_beams']} C={c['C']} eps={c['eps']} ties={ties} errs={errs}")
+    assert hops > sum(sizes)        # about pi hops per crossing beam

@@ -18,6 +18,13 @@ from _parity import (compare_states, ensemble_from_arrays, gpu_model, gpu_spec, 
 
 pytestmark = pytest.mark.gpu
 
+# Threshold ties over the whole ensemble, from the device counters (one count per hop test that
+# falls inside the tie band): FP64 trajectories against the 1e-12 band meet none in 1e6 beams;
+# FP32 trajectories against the 1e-5 band meet about 0.023 per beam over the 4000 intervals of
+# the 1e6-beam workload.  The bounds leave a margin and still catch a several-fold regression.
+MAX_TIES_PER_BEAM_FP64 = 1e-4
+MAX_TIES_PER_BEAM_MIXED = 0.035
+
 
 def run_gpu(gpu, c):
     st = gpu.State(c["n_beams"], 2 * c["d"], device="cuda")
@@ -43,10 +50,11 @@ def test_full_size_sampled_beams(gpu, name, k):
     g = {key: v[ids] for key, v in g_all.items()}
     e = oracle_init_ids(c, ids)
     oshgb.advance(oracle_model(c), e, c["nsteps"], c["dt"], c["seed"])
-    errs, ties = compare_states(g, e, min_ok=0.9, label=name)
+    errs, ties = compare_states(g, e, min_ok=0.97, label=name)
     assert e.nhop.sum() > 0
     d = diag.cpu().numpy()
     assert d[3] == 0 and d[4] == 0
+    assert d[1] <= MAX_TIES_PER_BEAM_FP64 * c["n_beams"], d
     # properties over the whole ensemble
     sums = gpu.populations(gpu_model(c), st).cpu().numpy()
     mean, se = gpu.population_mean_se(sums, c["n_beams"])
@@ -90,9 +98,10 @@ def test_full_size_d12_sampled_beams(gpu):
     g = {key: v[ids] for key, v in g_all.items()}
     e = oracle_init_ids(c, ids)
     oshgb.advance(oracle_model(c), e, c["nsteps"], c["dt"], c["seed"])
-    errs, ties = compare_states(g, e, min_ok=0.9, label="qcle12d")
+    errs, ties = compare_states(g, e, min_ok=0.95, label="qcle12d")
     d = diag.cpu().numpy()
     assert d[3] == 0 and d[4] == 0 and d[0] > c["n_beams"]
+    assert d[1] <= MAX_TIES_PER_BEAM_FP64 * c["n_beams"], d
     sums = gpu.populations(gpu_model(c), st).cpu().numpy()
     mean, se = gpu.population_mean_se(sums, c["n_beams"])
     assert abs(mean[0].real + mean[1].real - 1.0) < 4 * np.hypot(se[0].real, se[1].real)
@@ -135,7 +144,8 @@ def test_full_size_mixed_sampled_beams(gpu, name, k):
     for f in ("X", "P", "M", "N"):      # the FP64 draws as the mixed state stores them
         getattr(e, f)[:] = getattr(e, f).astype(np.float32).astype(np.float64)
     oshgb.advance(oracle_model(c), e, c["nsteps"], c["dt"], c["seed"], tie_rel=oshgb.TIE_REL_MIXED)
-    errs, ties = compare_states(g, e, rtol=1e-4, min_ok=0.8, label=f"{name} mixed")
+    errs, ties = compare_states(g, e, rtol=1e-4, min_ok=0.9, label=f"{name} mixed")
     d = diag.cpu().numpy()
     assert d[3] == 0 and d[4] == 0
+    assert d[1] <= MAX_TIES_PER_BEAM_MIXED * c["n_beams"], d
     print(name, "mixed errors", errs, "ties", ties)

@@ -4,7 +4,7 @@ the GPU and parity with the oracle.
 * P1 on the GPU: linear alpha, quadratic beta, diagonal gamma -- the beam
   ODEs have closed forms (matrix exponentials); the GPU's RK4 converges to
   them at fourth order and agrees with the oracle to 1e-10.
-* The system of Sec. 3.1 (eq. (3.1)): two components, dense J, gamma with a
+* The system of Sec. 3.1 (eq:ex1): two components, dense J, gamma with a
   nonzero diagonal; GPU init + stepping against the oracle, hop sequences
   bit-exact apart from oracle-reported ties.
 * P3 on the GPU: x-independent coefficients with complex gamma; the mean
@@ -85,7 +85,7 @@ def test_P1_gpu_matches_oracle(gpu):
 
 
 def paper_system_31():
-    """Eq. (3.1) written as d_t u + alpha.grad u = (i/eps) beta u + gamma u (second
+    """Eq:ex1 written as d_t u + alpha.grad u = (i/eps) beta u + gamma u (second
     equation's x2-derivative acting on u2)."""
     a = [[-1.0, 1.0], [1.0, -1.0]]
     J = [[[-1.0, -1.0], [-2.0, 1.0]], [[-0.5, -1.0], [-1.0, 0.5]]]
@@ -112,14 +112,14 @@ def test_paper_system_31_gpu_matches_oracle(gpu, n, nsteps, dt):
     gpu.step_ensemble(mdl, st, nsteps, dt, seed, diag)
     e = e0.subset(np.arange(n))
     oshgb.advance(model, e, nsteps, dt, seed)
-    errs, ties = compare_states(gpu.unpack(st), e, label="eq. (3.1)")
+    errs, ties = compare_states(gpu.unpack(st), e, label="eq:ex1")
     d = diag.cpu().numpy()
     assert d[0] == e.nhop.sum() and e.nhop.sum() > n // 10
     pops = gpu.populations(mdl, st).cpu().numpy()
     ref = observables.populations(e, eps)
     ci = observables.beam_integrals(e, eps)
     assert np.abs(pops[:2, :2] - ref[:2, :2]).max() <= 1e-10 * np.abs(ci).sum()
-    print("eq. (3.1)", errs, "ties", ties, "hops", int(d[0]))
+    print("eq:ex1", errs, "ties", ties, "hops", int(d[0]))
 
 
 def gpu_init_reference(n, eps, seed, sd):
@@ -173,7 +173,7 @@ def test_hop_entry_point_complex_gamma(gpu):
 
 
 # ---------------------------------------------------------------------------
-# The nonlinear system of Sec. 3.2, eq. (3.2): x-dependent transport, phases
+# The nonlinear system of Sec. 3.2, eq:ex2: x-dependent transport, phases
 # and couplings; beam curvature terms Hess(P.alpha) and Hess(beta) nonzero.
 
 def test_paper_system_32_gpu_matches_oracle(gpu):
@@ -187,9 +187,9 @@ def test_paper_system_32_gpu_matches_oracle(gpu):
     gpu.step_ensemble(gpu.make_paper32_model(0.04), st, 80, 0.01, 21, diag)
     e = e0.subset(np.arange(e0.n))
     oshgb.advance(model, e, 80, 0.01, 21)
-    errs, ties = compare_states(gpu.unpack(st), e, label="eq. (3.2)")
+    errs, ties = compare_states(gpu.unpack(st), e, label="eq:ex2")
     assert diag.cpu().numpy()[0] == e.nhop.sum() and e.nhop.sum() > e0.n // 4
-    print("eq. (3.2)", errs, "ties", ties, "hops", e.nhop.sum())
+    print("eq:ex2", errs, "ties", ties, "hops", e.nhop.sum())
 
 
 def test_paper_system_32_from_the_single_initial_beam(gpu):
@@ -208,7 +208,7 @@ def test_paper_system_32_from_the_single_initial_beam(gpu):
     gpu.step_ensemble(mdl, st, nsteps, dt, seed)
     e = e0.subset(np.arange(n))
     oshgb.advance(models.Paper32(), e, nsteps, dt, seed)
-    compare_states(gpu.unpack(st), e, label="eq. (3.2) single beam")
+    compare_states(gpu.unpack(st), e, label="eq:ex2 single beam")
     pops = gpu.populations(mdl, st).cpu().numpy()
     ref = observables.populations(e, eps)
     ci = observables.beam_integrals(e, eps)
@@ -237,7 +237,7 @@ def test_hop_entry_point_paper_system_32(gpu):
 
 
 def test_paper_31_field_error_falls_as_inverse_square_root(gpu):
-    """The convergence study of Sec. 3.1 in kind: for eq. (3.1) the expectation of
+    """The convergence study of Sec. 3.1 in kind: for eq:ex1 the expectation of
     the method is the exact solution (the O(eps^(1/2)) residuals vanish), so the
     L2 distance between an N-trajectory field and the field of 2^22 trajectories
     (standing in for the N -> infinity limit, the paper's finite-volume reference
@@ -263,7 +263,7 @@ def test_paper_31_field_error_falls_as_inverse_square_root(gpu):
     for n in (100, 400, 1600, 6400):
         e = [np.sqrt((np.abs(field(n, 1000 * n + r) - ref) ** 2).sum() * cell) for r in range(16)]
         errs[n] = float(np.mean(e))
-    print("eq. (3.1) field: L2 error / L2 norm by N:", {n: round(v / norm, 4) for n, v in errs.items()})
+    print("eq:ex1 field: L2 error / L2 norm by N:", {n: round(v / norm, 4) for n, v in errs.items()})
     for n in (100, 400, 1600):
         assert 1.6 <= errs[n] / errs[4 * n] <= 2.5, (n, errs)
     assert errs[6400] < 0.2 * norm

@@ -249,3 +249,25 @@ def test_empty_and_degenerate(gpu):
     gpu.step_ensemble(mdl, st, 3, c["dt"], c["seed"])
     oshgb.advance(oracle_model(c), e, 3, c["dt"], c["seed"])
     compare_states(gpu.unpack(st), e, label="forced")
+
+
+def test_population_stats_on_the_device(gpu):
+    """Sec. 2.4 step 7 on the device: mean and standard error per component from the raw sums
+    equal the oracle's from the same sums; several shards' sums added first give the stats of
+    the whole ensemble."""
+    c = workloads.config("qcle1d_1e6")
+    a = workloads.synthetic_ensemble(20001, 2, seed=5, a0=1.0 / (2 * np.pi * c["eps"]))
+    st = gpu.pack(a)
+    sums = gpu.populations(gpu_model(c), st)
+    got = gpu.population_stats(sums, 20001).cpu().numpy()
+    mean, se = observables.population_mean_se(sums.cpu().numpy(), 20001)
+    ref = np.stack([mean.real, mean.imag, se.real, se.imag], 1)
+    assert np.abs(got - ref).max() <= 1e-15 * np.abs(ref).max()
+    e = ensemble_from_arrays(a)
+    mean_o, se_o = observables.population_mean_se(observables.populations(e, c["eps"]), 20001)
+    assert np.abs(got[:, 0] + 1j * got[:, 1] - mean_o).max() <= 1e-12 * np.abs(mean_o).max()
+    assert np.abs(got[:, 2] + 1j * got[:, 3] - se_o).max() <= 1e-9 * np.abs(se_o).max()
+    one = gpu.population_stats(torch.tensor([[1.0, 2.0, 1.0, 4.0, 1.0]] * 4, dtype=torch.float64, device="cuda"), 1).cpu().numpy()
+    assert (one[:, :2] == [1.0, 2.0]).all() and (one[:, 2:] == 0.0).all()
+    with pytest.raises(gpu.ShgbError):
+        gpu.population_stats(sums, 0)

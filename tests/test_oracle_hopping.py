@@ -2,7 +2,7 @@
 
 P3  x-independent coefficients (alpha = 0, constant beta_l, constant complex
     gamma with nonzero diagonal): the system is du/dt = (i diag(beta)/eps + Gamma) u
-    for every x, whose solution is a matrix exponential (Sec. 2.2 eq. (2.11)
+    for every x, whose solution is a matrix exponential (Sec. 2.2 eq:tilde_gamma
     with the diagonal kept).  The SHGB estimator's mean must match it within
     its standard error; with constant rates the linearly interpolated hop
     times are exactly exponential and the destinations follow |gamma_jl|.

@@ -1,4 +1,4 @@
-"""Pins for the oracle's QCLE coefficients (Sec. 3.3, eqs. (3.5)-(3.6)).
+"""Pins for the oracle's QCLE coefficients (Sec. 3.3, eq:QCLE and the adiabatic quantities below it).
 
 Independent references: numpy's symmetric eigensolver for the adiabatic
 energies and the eigenvector angle, mpmath high-precision numerical
@@ -176,7 +176,7 @@ def test_coupling_structure_conserves_trace():
 
 @pytest.mark.parametrize("comp", [0, 1])
 def test_paper32_derivatives_by_finite_differences(comp):
-    """Eq. (3.2): every Jacobian/Hessian the beam ODEs use equals central differences."""
+    """Eq:ex2: every Jacobian/Hessian the beam ODEs use equals central differences."""
     mdl = models.Paper32()
     rng = np.random.default_rng(40 + comp)
     for _ in range(6):
@@ -194,7 +194,7 @@ def test_paper32_derivatives_by_finite_differences(comp):
 
 
 def test_paper32_coefficients_as_printed():
-    """Spot values read off eq. (3.2) at a point, component by component."""
+    """Spot values read off eq:ex2 at a point, component by component."""
     mdl = models.Paper32()
     x = np.array([[0.3, -0.7]])
     r2 = 0.3 ** 2 + 0.7 ** 2

@@ -1,4 +1,4 @@
-"""Pins for the oracle's populations and reconstruction (Sec. 2 eq. (2.2), Sec. 2.3 eq. (2.26)).
+"""Pins for the oracle's populations and reconstruction (Sec. 2, the beam G^eps, Sec. 2.3 eq:shgb).
 
 * the closed-form integral of a complex Gaussian beam against two-dimensional
   numerical quadrature (scipy dblquad), real and imaginary parts;
@@ -8,7 +8,7 @@
 * the field of one beam has position expectation X and momentum expectation
   <-i eps grad> = P (derivative by FFT on a fine periodic grid): the beam is
   centred at X and carries the momentum P, which fixes the signs of x - X and
-  of the linear phase term of eq. (2.2).
+  of the linear phase term of the beam G^eps (Sec. 2).
 """
 
 import math

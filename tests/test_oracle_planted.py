@@ -4,7 +4,7 @@ hopping code makes one of its pins fail.
 The source of oracle/shgb.py is loaded with one textual change into a fresh
 module (in memory, on the CPU) and the checks of two pins run against it:
 P1 (closed-form propagation of a linear-quadratic beam, tests/test_oracle_gb.py)
-for the right-hand side of eq. (2.24) and the RK4 step, and P3 (x-independent
+for the right-hand side of eq:shgb_odes and the RK4 step, and P3 (x-independent
 system: populations against the matrix exponential, first hop times against
 the exponential law, destinations of forced hops against unequal rates,
 tests/test_oracle_hopping.py) and the QCLE weight invariant
