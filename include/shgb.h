@@ -229,6 +229,19 @@ int shgb_populations(const shgb_model *model, const shgb_state *st, double *out,
  * Errors: EINVAL. */
 int shgb_population_stats(const double *sums, int64_t n_traj, double *stats, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): shgb_populations
+ * with its partial sums in a 320 KiB array that the library holds on each
+ * GPU until the process ends, instead of a caller workspace.  Same result,
+ * bitwise, as shgb_populations.  The array has room for the partials of any
+ * ensemble size (SHGB_EWORKSPACE otherwise); it allocates nothing and every
+ * partial is rewritten by each call.  All calls on one GPU share the array:
+ * calls that overlap on a GPU (other streams or threads) race and must be
+ * serialised by the caller.  Errors: EINVAL, EUNSUPPORTED (m not in
+ * {2, 4, 6, 8, 24}), EHIP (the array's device address could not be found). */
+int shgb_populations_noalloc(const shgb_model *model, const shgb_state *st, double *out, uint64_t *diag,
+                             void *stream);
+
 /* Superposition at Q evaluation points (Sec. 2.3 eq:shgb, Sec. 2.4 step 6):
  * out[(i*Q + q)*2 + {0,1}] = Re, Im of sum_{k: l_k = i} exp(omega_k) G_k(x_q),
  * G(x) = A exp(-(x-X)^T Z (x-X)/(2 eps) + i P.(x-X)/eps + i S/eps), unnormalised

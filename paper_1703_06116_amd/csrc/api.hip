@@ -21,7 +21,9 @@ hipError_t launch_hop(const DevModel &, const shgb_state &, const int32_t *, int
 hipError_t launch_philox(uint64_t, const uint64_t *, uint64_t *, int64_t, hipStream_t);
 int64_t pop_workspace_bytes(int64_t, int);
 hipError_t launch_populations(const DevModel &, const shgb_state &, double *, void *, uint64_t *, hipStream_t);
+int64_t pop_scratch_bytes();
 hipError_t launch_population_stats(const double *, int64_t, double *, hipStream_t);
+hipError_t pop_scratch_ptr(void **);
 int64_t recon_m2_workspace_bytes(int64_t, int64_t);
 hipError_t launch_recon_m2(const DevModel &, const shgb_state &, const double *, int64_t, double *, void *,
                            hipStream_t);
@@ -249,6 +251,20 @@ int shgb_populations(const shgb_model *model, const shgb_state *st, double *out,
   if (!out || !work) return SHGB_EINVAL;
   if (st->m != 2 && st->m != 4 && st->m != 6 && st->m != 8 && st->m != 24) return SHGB_EUNSUPPORTED;
   if (work_bytes < pop_workspace_bytes(st->n_beams, st->m)) return SHGB_EWORKSPACE;
+  return hip_status(launch_populations(md, *st, out, work, diag, (hipStream_t)stream));
+}
+
+int shgb_populations_noalloc(const shgb_model *model, const shgb_state *st, double *out, uint64_t *diag,
+                             void *stream) {
+  DevModel md;
+  int rc = to_dev_model(model, md);
+  if (rc) return rc;
+  if ((rc = check_state(st, md))) return rc;
+  if (!out) return SHGB_EINVAL;
+  if (st->m != 2 && st->m != 4 && st->m != 6 && st->m != 8 && st->m != 24) return SHGB_EUNSUPPORTED;
+  if (pop_workspace_bytes(st->n_beams, st->m) > pop_scratch_bytes()) return SHGB_EWORKSPACE;
+  void *work = nullptr;
+  if (pop_scratch_ptr(&work) != hipSuccess) return SHGB_EHIP;
   return hip_status(launch_populations(md, *st, out, work, diag, (hipStream_t)stream));
 }
 

@@ -11,6 +11,8 @@
 // block writes its partial sums and one block adds the partials in a fixed
 // order, so the result is bitwise reproducible.  The arithmetic is FP64 for
 // either trajectory precision (TS: the element type of the stored X, P, Z).
+#include <mutex>
+
 #include "cplx.h"
 #include "device.h"
 
@@ -225,6 +227,36 @@ hipError_t launch_population_stats(const double *sums, int64_t n_traj, double *s
 int64_t pop_workspace_bytes(int64_t n, int m) {
   const int64_t blocks = (m == 2) ? pop_blocks(n) : pop_blocks((n + kPopWaves - 1) / kPopWaves * kPopThreads);
   return blocks * kPopVals * (int64_t)sizeof(double);
+}
+
+// Partial sums of the allocation-free entry point: one array per GPU for the
+// life of the process.  pop_blocks() never exceeds kPopMaxBlocks, so these
+// 320 KiB hold the partials of any ensemble size.  Every block writes its
+// own partial before the final kernel reads it: nothing must start at zero.
+static __device__ __align__(256) double scratch[kPopMaxBlocks * kPopVals];
+
+constexpr int kMaxDevices = 64;
+int64_t pop_scratch_bytes() { return (int64_t)sizeof(scratch); }
+
+// Device address of `scratch` on the current device (the host symbol is only a
+// stand-in), looked up once per device with that device current.
+hipError_t pop_scratch_ptr(void **ptr) {
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_populations(const DevModel &md, const shgb_state &st, double *out, void *work,

@@ -95,6 +95,7 @@ def _load():
         "shgb_hop": (I32, [P(Model), P(StateDesc), V, I64, U64, V, V]),
         "shgb_populations_workspace": (I64, [I64, I32]),
         "shgb_populations": (I32, [P(Model), P(StateDesc), V, V, I64, V, V]),
+        "shgb_populations_noalloc": (I32, [P(Model), P(StateDesc), V, V, V]),
         "shgb_population_stats": (I32, [V, I64, V, V]),
         "shgb_reconstruct_workspace": (I64, [I64, I32, I64]),
         "shgb_reconstruct": (I32, [P(Model), P(StateDesc), V, I64, V, V, I64, V]),
@@ -123,7 +124,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = ("shgb_init_beams", "shgb_step_ensemble", "shgb_hop", "shgb_populations_workspace",
-            "shgb_populations", "shgb_population_stats",
+            "shgb_populations", "shgb_populations_noalloc", "shgb_population_stats",
             "shgb_reconstruct_workspace", "shgb_reconstruct", "shgb_philox",
             "shgb_strerror", "shgb_version", "shgb_abi_sizes", "shgb_batch_table_bytes", "shgb_batch_prepare",
             "shgb_step_batched", "shgb_population_tangent_workspace", "shgb_population_tangent")
@@ -279,6 +280,16 @@ def populations(model, state, out=None, work=None, diag=None, stream=None):
     d = state.desc()
     _check("shgb_populations", _lib.shgb_populations(ctypes.byref(model), ctypes.byref(d), _ptr(out),
                                                      _ptr(work), work.numel(), _ptr(diag), _stream(stream)))
+    return out
+
+
+def populations_noalloc(model, state, out, diag=None, stream=None):
+    """``populations`` through the entry point that allocates nothing: partial sums in the
+    library's own device array (see include/shgb.h).  out: a (4, 5) float64 device tensor."""
+    assert out.dtype == torch.float64 and out.numel() >= SHGB_NCOMP * 5 and out.is_contiguous()
+    d = state.desc()
+    _check("shgb_populations_noalloc", _lib.shgb_populations_noalloc(ctypes.byref(model), ctypes.byref(d),
+                                                                     _ptr(out), _ptr(diag), _stream(stream)))
     return out
 
 
