@@ -284,6 +284,33 @@ int shgb_population_tangent(const shgb_model *model, const shgb_state *st, int32
                             uint64_t seed, uint32_t dir_mask, double *out, void *work, int64_t work_bytes,
                             uint64_t *diag, void *stream);
 
+/* ---- reverse-mode (adjoint) derivative of the populations ---------------
+ * The gradient of a scalar objective of the populations after nsteps
+ * intervals (Sec. 2.3 eq:shgb integrated over x, Sec. 2.4 steps 3-7),
+ *   L = sum_i (cot[2i] Re U_i + cot[2i+1] Im U_i),
+ *   U_i = (1 / n_traj) sum_{l_k = i} c_k   (c_k as in shgb_populations),
+ * with respect to theta = (A, B, C, D, p_mean), in one reverse sweep for all
+ * five.  The derivative is the one shgb_population_tangent propagates
+ * forwards (events frozen at the values, thresholds without derivative,
+ * hop times moving through theta = (E - Lam)/(Lam' - Lam)).
+ *
+ * Use: shgb_step_checkpointed advances the ensemble exactly as
+ * shgb_step_ensemble does and writes the whole state before every segment
+ * of `every` intervals into ckpt (caller memory of shgb_checkpoint_bytes);
+ * shgb_population_adjoint then takes the stepped state, the checkpoints and
+ * the same nsteps, dt, seed and every, runs each segment forward again from
+ * its checkpoint and sweeps it backwards.  cot: device double[SHGB_NCOMP * 2];
+ * out: device double[6] = dL/dA, dL/dB, dL/dC, dL/dD, dL/dp_mean, L.
+ * QCLE, FP64 state, d in {1, 2, 3, 4, 12} (the workspace query returns -1
+ * for other m).  Errors: EINVAL, EWORKSPACE, EUNSUPPORTED. */
+int64_t shgb_checkpoint_bytes(int64_t n_beams, int32_t m, int32_t nsteps, int32_t every);
+int shgb_step_checkpointed(const shgb_model *model, const shgb_state *st, int32_t nsteps, double dt, uint64_t seed,
+                           int32_t every, void *ckpt, int64_t ckpt_bytes, uint64_t *diag, void *stream);
+int64_t shgb_population_adjoint_workspace(int64_t n_beams, int32_t m, int32_t every);
+int shgb_population_adjoint(const shgb_model *model, const shgb_state *st, const void *ckpt, int32_t nsteps, double dt,
+                            uint64_t seed, int32_t every, const double *cot, int64_t n_traj, double *out, void *work,
+                            int64_t work_bytes, void *stream);
+
 /* ---- batches: many instances in one persistent launch ------------------
  * A batch is n_inst independent QCLE instances (model, state, seed) of one
  * dimension d and one precision; models may differ in every parameter and

@@ -1,0 +1,60 @@
+// Checkpointed forward run for the reverse-mode derivative, and the final
+// sum of the reverse kernels' block partials.
+//
+// The forward run is the ordinary stepping (shgb_step_ensemble's kernels,
+// called once per segment of `every` intervals); before each segment the
+// whole state is copied into its checkpoint.  Splitting the run into calls
+// leaves an FP64 state bitwise as one call would.
+#include "adjoint.h"
+
+namespace shgb {
+
+hipError_t launch_step_m2(const DevModel &, const shgb_state &, int, double, uint64_t, uint64_t *, hipStream_t);
+hipError_t launch_step_wave(const DevModel &, const shgb_state &, int, double, uint64_t, uint64_t *, hipStream_t);
+
+// Copy the FP64 state (rows of ld) into a checkpoint (rows of n).
+__global__ void __launch_bounds__(256) ckpt_save_kernel(const double *__restrict__ f64, const int32_t *__restrict__ comp,
+                                                        const uint32_t *__restrict__ nhop, int64_t n, int64_t ld,
+                                                        int64_t rows, char *__restrict__ dst) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  double *d = (double *)dst;
+  for (int64_t f = 0; f < rows; ++f) d[f * n + b] = f64[f * ld + b];
+  int32_t *di = (int32_t *)(dst + rows * n * 8);
+  di[b] = comp[b];
+  di[n + b] = (int32_t)nhop[b];
+}
+
+hipError_t launch_step_checkpointed(const DevModel &md, const shgb_state &st, int nsteps, double dt, uint64_t seed,
+                                    int every, void *ckpt, uint64_t *diag, hipStream_t stream) {
+  const CkptLayout cl = ckpt_layout(st.n_beams, st.m, nsteps, every);
+  if (st.n_beams == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((st.n_beams + 255) / 256);
+  for (int c = 0; c < cl.n_ckpt; ++c) {
+    hipLaunchKernelGGL(ckpt_save_kernel, dim3(blocks), dim3(256), 0, stream, st.f64, st.comp, st.nhop, st.n_beams,
+                       st.ld, cl.rows, (char *)ckpt + (int64_t)c * cl.stride_bytes);
+    const int len = nsteps - c * every < every ? nsteps - c * every : every;
+    const hipError_t e = st.m == 2 ? launch_step_m2(md, st, len, dt, seed, diag, stream)
+                                   : launch_step_wave(md, st, len, dt, seed, diag, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+// Sum the block partials (kAdjVals per block) in block order.
+
+__global__ void __launch_bounds__(64) adj_final_kernel(const double *__restrict__ partial, int64_t nblocks,
+                                                       double *__restrict__ out) {
+  const int k = threadIdx.x;
+  if (k >= 6) return;
+  double s = 0.0;
+  for (int64_t b = 0; b < nblocks; ++b) s += partial[b * kAdjVals + k];
+  out[k] = s;
+}
+
+hipError_t launch_adj_final(const double *partial, int64_t nblocks, double *out, hipStream_t stream) {
+  hipLaunchKernelGGL(adj_final_kernel, dim3(1), dim3(64), 0, stream, partial, nblocks, out);
+  return hipGetLastError();
+}
+
+}  // namespace shgb

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "adjoint.h"
 #include "batch.h"
 
 namespace shgb {
@@ -42,6 +43,15 @@ hipError_t launch_tangent_wave(const DevModel &, const shgb_state &, int, double
 hipError_t launch_tangent_m2(const DevModel &, const shgb_state &, int, double, uint64_t, uint32_t, double *, void *,
                              uint64_t *, hipStream_t);
 int m2_tile_beams(int wpb);
+hipError_t launch_step_checkpointed(const DevModel &, const shgb_state &, int, double, uint64_t, int, void *, uint64_t *,
+                                    hipStream_t);
+int64_t adj_m2_workspace_bytes(int64_t, int);
+int64_t adj_wave_workspace_bytes(int64_t, int, int);
+bool adjoint_wave_supported(int d);
+hipError_t launch_adjoint_wave(const DevModel &, const shgb_state &, const void *, int, double, uint64_t, int,
+                               const double *, int64_t, double *, void *, hipStream_t);
+hipError_t launch_adjoint_m2(const DevModel &, const shgb_state &, const void *, int, double, uint64_t, int,
+                             const double *, int64_t, double *, void *, hipStream_t);
 hipError_t launch_step_wave_batched(int d, bool mixed_state, int wpb, const BatchItem *items, int n_items,
                                     int64_t total_tiles, int grab, int blocks, int nsteps, double dt,
                                     unsigned long long *queue, uint64_t *diag, hipStream_t stream);
@@ -328,6 +338,53 @@ int shgb_population_tangent(const shgb_model *model, const shgb_state *st, int32
   if (md.d == 1)
     return hip_status(launch_tangent_m2(md, *st, nsteps, dt, seed, dir_mask, out, work, diag, (hipStream_t)stream));
   return hip_status(launch_tangent_wave(md, *st, nsteps, dt, seed, dir_mask, out, work, diag, (hipStream_t)stream));
+}
+
+static bool adjoint_supported(const DevModel &md, const shgb_state *st) {
+  return md.kind == SHGB_MODEL_QCLE && st->precision == SHGB_FP64 && (md.d == 1 || adjoint_wave_supported(md.d));
+}
+
+int64_t shgb_checkpoint_bytes(int64_t n_beams, int32_t m, int32_t nsteps, int32_t every) {
+  if (n_beams < 0 || m < 2 || m > 2 * SHGB_MAX_D || (m & 1) || nsteps < 0 || every < 1) return -1;
+  const CkptLayout cl = ckpt_layout(n_beams, m, nsteps, every);
+  return (int64_t)cl.n_ckpt * cl.stride_bytes;
+}
+
+int shgb_step_checkpointed(const shgb_model *model, const shgb_state *st, int32_t nsteps, double dt, uint64_t seed,
+                           int32_t every, void *ckpt, int64_t ckpt_bytes, uint64_t *diag, void *stream) {
+  DevModel md;
+  int rc = to_dev_model(model, md);
+  if (rc) return rc;
+  if ((rc = check_state(st, md))) return rc;
+  if (nsteps < 0 || !finite_pos(dt) || every < 1) return SHGB_EINVAL;
+  if (!adjoint_supported(md, st)) return SHGB_EUNSUPPORTED;
+  const int64_t need = shgb_checkpoint_bytes(st->n_beams, st->m, nsteps, every);
+  if (need > 0 && (!ckpt || ckpt_bytes < need)) return SHGB_EWORKSPACE;
+  return hip_status(launch_step_checkpointed(md, *st, nsteps, dt, seed, every, ckpt, diag, (hipStream_t)stream));
+}
+
+int64_t shgb_population_adjoint_workspace(int64_t n_beams, int32_t m, int32_t every) {
+  if (n_beams < 0 || m < 2 || m > 2 * SHGB_MAX_D || (m & 1) || every < 1) return -1;
+  if (m != 2 && !adjoint_wave_supported(m / 2)) return -1;
+  return m == 2 ? adj_m2_workspace_bytes(n_beams, every) : adj_wave_workspace_bytes(n_beams, m, every);
+}
+
+int shgb_population_adjoint(const shgb_model *model, const shgb_state *st, const void *ckpt, int32_t nsteps, double dt,
+                            uint64_t seed, int32_t every, const double *cot, int64_t n_traj, double *out, void *work,
+                            int64_t work_bytes, void *stream) {
+  DevModel md;
+  int rc = to_dev_model(model, md);
+  if (rc) return rc;
+  if ((rc = check_state(st, md))) return rc;
+  if (nsteps < 0 || !finite_pos(dt) || every < 1 || n_traj < 1 || !cot || !out) return SHGB_EINVAL;
+  if (!adjoint_supported(md, st)) return SHGB_EUNSUPPORTED;
+  if (shgb_checkpoint_bytes(st->n_beams, st->m, nsteps, every) > 0 && !ckpt) return SHGB_EINVAL;
+  if (!work || work_bytes < shgb_population_adjoint_workspace(st->n_beams, st->m, every)) return SHGB_EWORKSPACE;
+  if (st->m == 2)
+    return hip_status(launch_adjoint_m2(md, *st, ckpt, nsteps, dt, seed, every, cot, n_traj, out, work,
+                                        (hipStream_t)stream));
+  return hip_status(launch_adjoint_wave(md, *st, ckpt, nsteps, dt, seed, every, cot, n_traj, out, work,
+                                        (hipStream_t)stream));
 }
 
 int64_t shgb_batch_table_bytes(int32_t n_inst) {

@@ -1,12 +1,16 @@
 """Populations as differentiable functions of the model and initial-data
-parameters (torch.autograd), through the pathwise tangent kernel.
+parameters (torch.autograd), through the reverse-mode (adjoint) kernel.
 
-``population(theta, cfg, component)`` returns the population of one
-component after the configured run, as a function of
-theta = (A, B, C, D, p_mean); its backward multiplies the incoming gradient
-by the derivative shgb_population_tangent computes (hop sequences frozen,
-see include/shgb.h).  The forward pass samples a fresh ensemble with the
-configured seed each call, so repeated calls with one theta agree exactly.
+``populations(theta, cfg)`` returns the (Re, Im) population means of the four
+components after the configured run, a (4, 2) float64 device tensor, as a
+function of theta = (A, B, C, D, p_mean).  Its forward pass samples the
+ensemble with the configured seed (repeated calls with one theta agree
+exactly), steps it with checkpoints every ``every`` intervals and forms the
+means on the device; its backward pass launches the reverse sweep
+(shgb_population_adjoint) with the incoming gradient as the cotangent, one
+sweep for all five parameters (hop sequences frozen, see include/shgb.h).
+``population_and_tangent`` gives the same derivative by forward (tangent)
+propagation, one pass per parameter: the check of the adjoint.
 """
 
 import torch
@@ -36,8 +40,8 @@ def theta_of(cfg):
 
 
 def population_and_tangent(theta, cfg, device="cuda"):
-    """(sums, derivatives) for the run of cfg at theta: sums (4, 2) = (Re, Im) of sum c per
-    component; derivatives (5, 4, 2) along each theta_j.  Host float64 tensors."""
+    """(sums, derivatives) for the run of cfg at theta by the tangent kernel: sums (4, 2) = (Re, Im)
+    of sum c per component; derivatives (5, 4, 2) along each theta_j.  Host float64 tensors."""
     mdl = _model(theta, cfg)
     st = shgb.State(cfg["n_beams"], 2 * cfg["d"], device=device)
     shgb.init_beams(mdl, _spec(theta, cfg), st, cfg["seed"])
@@ -45,21 +49,35 @@ def population_and_tangent(theta, cfg, device="cuda"):
     return out[0, :, 0:2].clone(), out[:, :, 2:4].clone()
 
 
-class _Population(torch.autograd.Function):
+class _Populations(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, theta, cfg, component):
-        sums, deriv = population_and_tangent(theta.detach().cpu().tolist(), cfg)
-        n = cfg["n_beams"]
-        ctx.save_for_backward(deriv[:, component, 0].to(theta) / n)
-        return (sums[component, 0] / n).to(theta)
+    def forward(ctx, theta, cfg, every):
+        th = theta.detach().cpu().tolist()
+        mdl = _model(th, cfg)
+        st = shgb.State(cfg["n_beams"], 2 * cfg["d"])
+        shgb.init_beams(mdl, _spec(th, cfg), st, cfg["seed"])
+        ckpt = shgb.step_checkpointed(mdl, st, cfg["nsteps"], cfg["dt"], cfg["seed"], every=every)
+        stats = shgb.population_stats(shgb.populations(mdl, st), cfg["n_beams"])
+        ctx.run = (mdl, st, ckpt, cfg, every)
+        ctx.theta_like = (theta.dtype, theta.device)
+        return stats[:, 0:2].contiguous()
 
     @staticmethod
     def backward(ctx, grad):
-        (g,) = ctx.saved_tensors
-        return grad * g, None, None
+        mdl, st, ckpt, cfg, every = ctx.run
+        cot = grad.to(dtype=torch.float64).contiguous().view(-1)
+        out = shgb.population_adjoint(mdl, st, ckpt, cfg["nsteps"], cfg["dt"], cfg["seed"], cot, cfg["n_beams"],
+                                      every=every)
+        dtype, device = ctx.theta_like
+        return out[:5].to(dtype=dtype, device=device), None, None
 
 
-def population(theta, cfg, component=0):
-    """Re of the population of `component` (0 = upper surface) after the run of cfg, differentiable
-    in theta = (A, B, C, D, p_mean) (a float64 tensor of 5)."""
-    return _Population.apply(theta, cfg, component)
+def populations(theta, cfg, every=100):
+    """(Re, Im) population means of the four components after the run of cfg, a (4, 2) device
+    tensor, differentiable in theta = (A, B, C, D, p_mean) (a float64 tensor of 5)."""
+    return _Populations.apply(theta, cfg, every)
+
+
+def population(theta, cfg, component=0, every=100):
+    """Re of the population of `component` (0 = upper surface), differentiable in theta."""
+    return populations(theta, cfg, every)[component, 0]

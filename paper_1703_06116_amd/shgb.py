@@ -105,6 +105,10 @@ def _load():
         "shgb_abi_sizes": (None, [V]),
         "shgb_population_tangent_workspace": (I64, [I64]),
         "shgb_population_tangent": (I32, [P(Model), P(StateDesc), I32, D, U64, ctypes.c_uint32, V, V, I64, V, V]),
+        "shgb_checkpoint_bytes": (I64, [I64, I32, I32, I32]),
+        "shgb_step_checkpointed": (I32, [P(Model), P(StateDesc), I32, D, U64, I32, V, I64, V, V]),
+        "shgb_population_adjoint_workspace": (I64, [I64, I32, I32]),
+        "shgb_population_adjoint": (I32, [P(Model), P(StateDesc), V, I32, D, U64, I32, V, I64, V, V, I64, V]),
         "shgb_batch_table_bytes": (I64, [I32]),
         "shgb_batch_prepare": (I32, [P(Model), P(StateDesc), P(U64), I32, P(BatchConfig), V, I64, P(BatchDesc)]),
         "shgb_step_batched": (I32, [P(BatchDesc), I32, D, V, I64, V, V]),
@@ -127,7 +131,9 @@ EXPORTED = ("shgb_init_beams", "shgb_step_ensemble", "shgb_hop", "shgb_populatio
             "shgb_populations", "shgb_populations_noalloc", "shgb_population_stats",
             "shgb_reconstruct_workspace", "shgb_reconstruct", "shgb_philox",
             "shgb_strerror", "shgb_version", "shgb_abi_sizes", "shgb_batch_table_bytes", "shgb_batch_prepare",
-            "shgb_step_batched", "shgb_population_tangent_workspace", "shgb_population_tangent")
+            "shgb_step_batched", "shgb_population_tangent_workspace", "shgb_population_tangent",
+            "shgb_checkpoint_bytes", "shgb_step_checkpointed", "shgb_population_adjoint_workspace",
+            "shgb_population_adjoint")
 
 
 def _check(fn, rc):
@@ -341,6 +347,45 @@ def population_tangent(model, state, nsteps, dt, seed, dirs=range(5), out=None, 
 
 
 DEFAULT_BATCH_CONFIG = (4, 2, 1)   # waves per block, blocks per CU, tiles per grab
+
+
+def checkpoint_bytes(n, m, nsteps, every):
+    return int(_lib.shgb_checkpoint_bytes(n, m, nsteps, every))
+
+
+def step_checkpointed(model, state, nsteps, dt, seed, every=100, ckpt=None, diag=None, stream=None):
+    """step_ensemble that also writes the state before every `every` intervals into a checkpoint
+    buffer (a uint8 device tensor, allocated here if not given); returns the buffer."""
+    nb = checkpoint_bytes(state.n, state.m, nsteps, every)
+    if ckpt is None:
+        ckpt = torch.empty(max(nb, 8), dtype=torch.uint8, device=state.f64.device)
+    d = state.desc()
+    _check("shgb_step_checkpointed", _lib.shgb_step_checkpointed(ctypes.byref(model), ctypes.byref(d), nsteps,
+                                                                 float(dt), seed, every, _ptr(ckpt), ckpt.numel(),
+                                                                 _ptr(diag), _stream(stream)))
+    return ckpt
+
+
+def population_adjoint_workspace(n, m, every):
+    return int(_lib.shgb_population_adjoint_workspace(n, m, every))
+
+
+def population_adjoint(model, state, ckpt, nsteps, dt, seed, cot, n_traj, every=100, out=None, work=None,
+                       stream=None):
+    """Reverse sweep: (dL/dA, dL/dB, dL/dC, dL/dD, dL/dp_mean, L) as a device tensor of 6, for
+    L = sum_i cot[2i] Re U_i + cot[2i+1] Im U_i (cot: 8 doubles on the device)."""
+    dev = state.f64.device
+    assert cot.dtype == torch.float64 and cot.is_contiguous() and cot.numel() >= 2 * SHGB_NCOMP
+    if out is None:
+        out = torch.empty(6, dtype=torch.float64, device=dev)
+    nb = population_adjoint_workspace(state.n, state.m, every)
+    if work is None:
+        work = torch.empty(max(nb, 8), dtype=torch.uint8, device=dev)
+    d = state.desc()
+    _check("shgb_population_adjoint", _lib.shgb_population_adjoint(
+        ctypes.byref(model), ctypes.byref(d), _ptr(ckpt), nsteps, float(dt), seed, every, _ptr(cot), int(n_traj),
+        _ptr(out), _ptr(work), work.numel(), _stream(stream)))
+    return out
 
 
 class Batch:

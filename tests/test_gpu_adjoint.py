@@ -1,0 +1,100 @@
+"""Reverse-mode (adjoint) derivative of the populations: one forward run that
+writes checkpoints, one reverse sweep for all five parameters
+theta = (A, B, C, D, p_mean).
+
+The reverse sweep computes the same derivative as the tangent kernel (events
+frozen at the values, thresholds without derivative, hop times moving with
+the state), so for any cotangent w the gradient of L = sum_i w_i . U_i must
+equal w applied to the tangent's derivatives of the populations, to 1e-10 of
+the gradient's size; it must equal the oracle's central differences (common
+random numbers, events checked identical) to 1e-5; the objective it reports
+must equal the populations of the checkpointed forward run, and that run
+must leave the state bitwise as shgb_step_ensemble does.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1703_06116_amd import gradient
+
+from _parity import gpu_model, gpu_spec
+from test_gpu_gradient import crossing_cfg, oracle_populations, shifted
+
+pytestmark = pytest.mark.gpu
+
+
+def adjoint_run(gpu, cfg, cot, every):
+    mdl = gpu_model(cfg)
+    st = gpu.State(cfg["n_beams"], 2 * cfg["d"])
+    gpu.init_beams(mdl, gpu_spec(cfg), st, cfg["seed"])
+    ref = gpu.State(cfg["n_beams"], 2 * cfg["d"])
+    gpu.init_beams(mdl, gpu_spec(cfg), ref, cfg["seed"])
+    ckpt = gpu.step_checkpointed(mdl, st, cfg["nsteps"], cfg["dt"], cfg["seed"], every=every)
+    gpu.step_ensemble(mdl, ref, cfg["nsteps"], cfg["dt"], cfg["seed"])
+    assert torch.equal(st.f64, ref.f64) and torch.equal(st.comp, ref.comp) and torch.equal(st.nhop, ref.nhop)
+    pops = gpu.populations(mdl, st).cpu().numpy()
+    c = torch.tensor(cot, dtype=torch.float64, device="cuda")
+    out = gpu.population_adjoint(mdl, st, ckpt, cfg["nsteps"], cfg["dt"], cfg["seed"], c, cfg["n_beams"],
+                                 every=every).cpu().numpy()
+    return out, pops
+
+
+def tangent_gradient(cfg, cot):
+    _, deriv = gradient.population_and_tangent(gradient.theta_of(cfg), cfg)
+    d = deriv.numpy()                                  # (5, 4, 2): d sum Re c_i, d sum Im c_i
+    w = np.asarray(cot).reshape(4, 2)
+    return (d * w[None]).sum((1, 2)) / cfg["n_beams"]
+
+
+@pytest.mark.parametrize("d,n,nsteps,every", [(1, 2 * 256 + 37, 600, 100), (1, 300, 257, 37), (1, 64, 250, 400),
+                                              (2, 2 * 128 + 5, 500, 100), (12, 2 * 64 + 3, 450, 100),
+                                              (12, 37, 330, 64)])
+def test_adjoint_equals_tangent(gpu, d, n, nsteps, every):
+    cfg = crossing_cfg(n, nsteps, d=d)
+    rng = np.random.default_rng(7)
+    for cot in ([1.0, 0, 0, 0, 0, 0, 0, 0], list(rng.normal(size=8))):
+        out, pops = adjoint_run(gpu, cfg, cot, every)
+        w = np.asarray(cot).reshape(4, 2)
+        L = ((pops[:, :2] * w).sum()) / n
+        assert abs(out[5] - L) <= 1e-12 * (np.abs(pops[:, :2]).sum() * np.abs(w).max() / n + 1e-300)
+        tan = tangent_gradient(cfg, cot)
+        scale = np.abs(tan).max()
+        assert scale > 0
+        print(d, n, nsteps, every, "adjoint", out[:5], "tangent", tan, "rel", np.abs(out[:5] - tan).max() / scale)
+        assert np.abs(out[:5] - tan).max() <= 1e-10 * scale, (out[:5], tan)
+
+
+@pytest.mark.parametrize("d,n,nsteps", [(1, 48, 300), (12, 24, 400)])
+def test_adjoint_matches_oracle_central_differences(gpu, d, n, nsteps):
+    cfg = crossing_cfg(n, nsteps, d=d)
+    out, _ = adjoint_run(gpu, cfg, [1.0, 0, 0, 0, 0, 0, 0, 0], 100)
+    theta = gradient.theta_of(cfg)
+    for j in range(5):
+        h = 1e-6 * abs(theta[j])
+        pp, nhp, cp = oracle_populations(shifted(cfg, j, h))
+        pm, nhm, cm = oracle_populations(shifted(cfg, j, -h))
+        assert (nhp == nhm).all() and (cp == cm).all(), f"event flipped for theta_{j}"
+        fd = (pp[0].real - pm[0].real) / (2 * h) / n
+        assert abs(fd - out[j]) <= 1e-5 * np.abs(out[:5]).max(), (j, fd, out[j])
+
+
+def test_adjoint_edge_cases(gpu):
+    cfg = crossing_cfg(5, 10)
+    mdl = gpu_model(cfg)
+    cot = torch.ones(8, dtype=torch.float64, device="cuda")
+    # no intervals: no checkpoint, the gradient is zero and L the initial populations
+    st = gpu.State(5, 2)
+    gpu.init_beams(mdl, gpu_spec(cfg), st, cfg["seed"])
+    ck = gpu.step_checkpointed(mdl, st, 0, 0.5, cfg["seed"])
+    out = gpu.population_adjoint(mdl, st, ck, 0, 0.5, cfg["seed"], cot, 5).cpu().numpy()
+    assert (out[:5] == 0).all() and abs(out[5] - 1.0) < 1e-12
+    # an empty ensemble
+    e = gpu.State(0, 2)
+    ck = gpu.step_checkpointed(mdl, e, 10, 0.5, 1)
+    out = gpu.population_adjoint(mdl, e, ck, 10, 0.5, 1, cot, 1).cpu().numpy()
+    assert (out == 0).all()
+    # a mixed state is not supported
+    mx = gpu.State(5, 2, precision="mixed")
+    with pytest.raises(gpu.ShgbError):
+        gpu.step_checkpointed(mdl, mx, 10, 0.5, 1)

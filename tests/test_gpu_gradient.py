@@ -7,7 +7,8 @@ path (Richardson-extrapolated over h and h/2: the phase S/eps makes the
 third derivative in p_mean large) and of the oracle, both under common
 random numbers and with the hop sequences of the shifted runs checked
 identical (otherwise the difference quotient measures a jump, not the
-derivative); and the torch.autograd wrapper returns the tangent.
+derivative); and the torch.autograd wrapper (whose backward is the reverse-mode kernel)
+returns the tangent's derivative.
 """
 
 import numpy as np
@@ -97,16 +98,23 @@ def test_tangent_matches_oracle_central_differences(gpu, d, n, nsteps):
 
 
 @pytest.mark.parametrize("d", [1, 12])
-def test_autograd_function_returns_the_tangent(gpu, d):
+def test_autograd_backward_is_the_adjoint_and_equals_the_tangent(gpu, d):
     cfg = crossing_cfg(300 if d == 1 else 70, 400, d=d)
     theta = torch.tensor(gradient.theta_of(cfg), dtype=torch.float64, requires_grad=True)
     pop = gradient.population(theta, cfg, component=0)
     pop.backward()
     _, deriv = gradient.population_and_tangent(gradient.theta_of(cfg), cfg)
-    np.testing.assert_allclose(theta.grad.numpy(), deriv[:, 0, 0].numpy() / cfg["n_beams"], rtol=0, atol=0)
+    tan = deriv[:, 0, 0].numpy() / cfg["n_beams"]
+    assert np.abs(theta.grad.numpy() - tan).max() <= 1e-10 * np.abs(tan).max()
     # a second call at the same theta gives the same value (fresh ensemble, same seed)
     assert gradient.population(theta.detach(), cfg).item() == pop.item()
     assert abs(pop.item()) < 5.0      # a Monte Carlo estimate with signed weights, not a probability
+    # a cotangent over all four components at once
+    theta.grad = None
+    w = torch.tensor([[0.3, -1.0], [2.0, 0.5], [-0.7, 0.2], [1.1, -0.4]], dtype=torch.float64, device="cuda")
+    (gradient.populations(theta, cfg) * w).sum().backward()
+    want = (deriv.numpy() * w.cpu().numpy()[None]).sum((1, 2)) / cfg["n_beams"]
+    assert np.abs(theta.grad.numpy() - want).max() <= 1e-10 * np.abs(want).max()
 
 
 @pytest.mark.parametrize("d", [1, 12])
