@@ -208,7 +208,7 @@ def cpu_baselines(names, pool):
     for name in names:
         if name == "qcle1d_1e6":
             c = workloads.config(name)
-            r = sharded(c, 256, c["nsteps"], "")
+            r = sharded(c, 768, c["nsteps"], "")
             pts = workloads.grid_points_2d()
             t0 = time.perf_counter()
             pool.map(_field_run, [(c, 64, pts)] * cores)
@@ -218,21 +218,21 @@ def cpu_baselines(names, pool):
             out[name] = r
         elif name == "qcle12d_2p18":
             c = workloads.config(name)
-            out[name] = sharded(c, 16, c["nsteps"], "")
+            out[name] = sharded(c, 128, c["nsteps"], "")
         elif name == "batch64_d12":
             cs = workloads.batch_instances(name)
-            jobs = [(cs[i], 16, 0, cs[i]["nsteps"]) for i in range(0, len(cs), max(1, len(cs) // cores))][:cores]
+            jobs = [(cs[i], 256, 0, cs[i]["nsteps"]) for i in range(0, len(cs), max(1, len(cs) // cores))][:cores]
             t0 = time.perf_counter()
             pool.map(_shard_run, jobs)
             wall = time.perf_counter() - t0
-            n = 16 * len(jobs)
+            n = 256 * len(jobs)
             out[name] = {"value": n * cs[0]["nsteps"] / wall, "unit": "beam-steps/s", "cores": len(jobs),
                          "cpu_model": model, "kind": "oracle", "seconds": round(wall, 2),
-                         "sample": f"16 beams of each of {len(jobs)} instances x {cs[0]['nsteps']} intervals, "
+                         "sample": f"256 beams of each of {len(jobs)} instances x {cs[0]['nsteps']} intervals, "
                                    "FP64, one process per instance"}
         elif name == "qcle12d_grad":
             c = workloads.config(name)
-            n = 8
+            n = 96
             jobs = [(c, n, -1, 0)] + [(c, n, j, s) for j in range(5) for s in (1, -1)]
             t0 = time.perf_counter()
             pool.map(_cd_run, jobs)

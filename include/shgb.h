@@ -196,6 +196,18 @@ int shgb_init_beams(const shgb_model *model, const shgb_init_spec *spec,
 int shgb_step_ensemble(const shgb_model *model, const shgb_state *st, int32_t nsteps,
                        double dt, uint64_t seed, uint64_t *diag, void *stream);
 
+/* shgb_step_ensemble with a choice of Runge-Kutta scheme: SHGB_SCHEME_RK4
+ * (classical, as shgb_step_ensemble) or SHGB_SCHEME_RK3 (Kutta's third-order
+ * method: Sec. 2.4 integrates the system with a third-order Runge-Kutta
+ * method without naming it; k1 = f(y), k2 = f(y + h k1/2),
+ * k3 = f(y - h k1 + 2h k2), y + h (k1 + 4 k2 + k3)/6), every trial and
+ * shortened step of the interval algorithm taken with it.  RK3: QCLE, d = 1,
+ * FP64 state.  Errors: EINVAL (also an unknown scheme), EUNSUPPORTED. */
+#define SHGB_SCHEME_RK4 4
+#define SHGB_SCHEME_RK3 3
+int shgb_step_ensemble_scheme(const shgb_model *model, const shgb_state *st, int32_t nsteps, double dt,
+                              uint64_t seed, int32_t scheme, uint64_t *diag, void *stream);
+
 /* Apply one hop (Sec. 2.4 step 5) to each listed beam at its current state:
  * destination j != l drawn with probability |gamma_jl| / sum_k |gamma_kl|
  * (inverse CDF over j ascending, uniform U from draw nhop+1), phase times

@@ -11,7 +11,8 @@ Follows Cai & Lu Sec. 2.3-2.4.  Per beam the state is
 Readings taken where the paper leaves a choice:
 
 * time stepping: fixed intervals [t_n, t_n + dt]; classical RK4 (the
-  workloads prescribe RK4; Sec. 2.4 mentions a third-order method).
+  workloads prescribe RK4); Kutta's third-order method as an option (Sec.
+  2.4 integrates with "a third-order Runge-Kutta method", variant unnamed).
 * step 3/4: the trial step covers the rest of the interval; the hop test
   exp(omega~ - omega(t+dt)) <= 1 - Y reads Lam' >= E with E = -log(1-Y).
 * step 4 "interpolation of omega": linear in Lam over the trial step,
@@ -127,6 +128,19 @@ def rk4(model, comp, y, h):
                  for a, b1, b2, b3, b4 in zip(y, k1, k2, k3, k4))
 
 
+def rk3(model, comp, y, h):
+    """One step of Kutta's third-order Runge-Kutta method (Sec. 2.4 integrates the system with a
+    third-order Runge-Kutta method without naming the variant): k1 = f(y), k2 = f(y + h k1 / 2),
+    k3 = f(y - h k1 + 2 h k2), y + h (k1 + 4 k2 + k3) / 6."""
+    k1 = rhs(model, comp, y)
+    k2 = rhs(model, comp, _axpy(y, 0.5 * h, k1))
+    k3 = rhs(model, comp, _axpy(_axpy(y, -h, k1), 2.0 * h, k2))
+    return tuple(a + _bcast(h / 6.0, a) * (b1 + 4.0 * b2 + b3) for a, b1, b2, b3 in zip(y, k1, k2, k3))
+
+
+STEPPERS = {"rk4": rk4, "rk3": rk3}
+
+
 def threshold(Y):
     """Waiting-time threshold: the hop test exp(-Lam) <= 1 - Y, i.e. Lam >= -log(1 - Y)."""
     return -np.log(1.0 - Y)
@@ -183,8 +197,10 @@ def hop_event(model, ens, idx, seed, times=None, tie_rel=TIE_REL):
         ens.hop_log[b].append((ens.interval, dest, None if times is None else float(times[t])))
 
 
-def advance_interval(model, ens, dt, seed, cap=HOP_CAP, tie_rel=TIE_REL):
-    """Advance every beam over one interval of length dt (Sec. 2.4 steps 3-5)."""
+def advance_interval(model, ens, dt, seed, cap=HOP_CAP, tie_rel=TIE_REL, scheme="rk4"):
+    """Advance every beam over one interval of length dt (Sec. 2.4 steps 3-5) with the
+    Runge-Kutta scheme named by `scheme` ("rk4" classical, "rk3" Kutta's third order)."""
+    step = STEPPERS[scheme]
     n = ens.n
     rem = np.full(n, float(dt))
     hops_here = np.zeros(n, dtype=np.int64)
@@ -193,7 +209,7 @@ def advance_interval(model, ens, dt, seed, cap=HOP_CAP, tie_rel=TIE_REL):
         ia = np.flatnonzero(active)
         y0 = ens.ode(ia)
         comp = ens.comp[ia]
-        yt = rk4(model, comp, y0, rem[ia])
+        yt = step(model, comp, y0, rem[ia])
         L0, L1, E = y0[-1], yt[-1], ens.E[ia]
         capped = hops_here[ia] >= cap
         tie = (~capped) & (np.abs(L1 - E) <= tie_rel * E)
@@ -214,7 +230,7 @@ def advance_interval(model, ens, dt, seed, cap=HOP_CAP, tie_rel=TIE_REL):
         ynew = tuple(v[cross] for v in y0)
         part = (theta > 0.0) & (theta < 1.0)
         if part.any():
-            yp = rk4(model, comp[cross][part], tuple(v[part] for v in ynew),
+            yp = step(model, comp[cross][part], tuple(v[part] for v in ynew),
                      theta[part] * rem[ic][part])
             ynew = tuple(_put(v, part, w) for v, w in zip(ynew, yp))
         full = theta >= 1.0
@@ -236,7 +252,7 @@ def _put(v, mask, w):
     return v
 
 
-def advance(model, ens, nsteps, dt, seed, cap=HOP_CAP, tie_rel=TIE_REL):
+def advance(model, ens, nsteps, dt, seed, cap=HOP_CAP, tie_rel=TIE_REL, scheme="rk4"):
     for _ in range(int(nsteps)):
-        advance_interval(model, ens, dt, seed, cap, tie_rel)
+        advance_interval(model, ens, dt, seed, cap, tie_rel, scheme)
     return ens

@@ -18,115 +18,116 @@
 
 namespace shgb {
 
-// A value and its partial derivatives along (q1, A, B, C, D).
-constexpr int kJ5 = 5;
-struct D5 {
-  double v, d[kJ5];
-};
-
-__host__ __device__ inline D5 d5c(double x) {
-  D5 r;
-  r.v = x;
-  for (int i = 0; i < kJ5; ++i) r.d[i] = 0.0;
-  return r;
-}
-__host__ __device__ inline D5 d5var(double x, int i) {
-  D5 r = d5c(x);
-  r.d[i] = 1.0;
-  return r;
-}
-__host__ __device__ inline D5 operator+(const D5 &a, const D5 &b) {
-  D5 r;
-  r.v = a.v + b.v;
-  for (int i = 0; i < kJ5; ++i) r.d[i] = a.d[i] + b.d[i];
-  return r;
-}
-__host__ __device__ inline D5 operator-(const D5 &a, const D5 &b) {
-  D5 r;
-  r.v = a.v - b.v;
-  for (int i = 0; i < kJ5; ++i) r.d[i] = a.d[i] - b.d[i];
-  return r;
-}
-__host__ __device__ inline D5 operator-(const D5 &a) {
-  D5 r;
-  r.v = -a.v;
-  for (int i = 0; i < kJ5; ++i) r.d[i] = -a.d[i];
-  return r;
-}
-__host__ __device__ inline D5 operator*(const D5 &a, const D5 &b) {
-  D5 r;
-  r.v = a.v * b.v;
-  for (int i = 0; i < kJ5; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
-  return r;
-}
-__host__ __device__ inline D5 operator*(double s, const D5 &a) {
-  D5 r;
-  r.v = s * a.v;
-  for (int i = 0; i < kJ5; ++i) r.d[i] = s * a.d[i];
-  return r;
-}
-// f(a) with f(a.v) = fv and f'(a.v) = fd
-__host__ __device__ inline D5 d5chain(const D5 &a, double fv, double fd) {
-  D5 r;
-  r.v = fv;
-  for (int i = 0; i < kJ5; ++i) r.d[i] = fd * a.d[i];
-  return r;
-}
-__host__ __device__ inline D5 d5exp(const D5 &a) {
-  const double e = exp(a.v);
-  return d5chain(a, e, e);
-}
-__host__ __device__ inline D5 d5recip(const D5 &a) {
-  const double r = 1.0 / a.v;
-  return d5chain(a, r, -r * r);
-}
-__host__ __device__ inline D5 d5rsqrt(const D5 &a) {
-  const double r = 1.0 / sqrt(a.v);
-  return d5chain(a, r, -0.5 * r * r * r);
-}
-__host__ __device__ inline D5 d5abs(const D5 &a) { return a.v < 0.0 ? -a : a; }
-
-// The two-level quantities (s, s', s'', s''', d21) of Sec. 3.3 (the adiabatic
-// energies and d21 below eq:QCLE) as functions of (q1, A, B, C, D):
-// out[o] for o = s, s1, s2, s3, d21.  The formulas are those of qcle_q1,
-// differentiated by the chain rule; only the partials are used.
-__host__ __device__ inline void qcle_q1_d5(const DevModel &md, double q1, D5 out[5]) {
-  const D5 q = d5var(q1, 0), A = d5var(md.A, 1), B = d5var(md.B, 2), C = d5var(md.C, 3), D = d5var(md.D, 4);
-  const D5 x = B * q;
-  const D5 e = d5exp(-2.0 * d5abs(x));
-  const D5 r = d5recip(d5c(1.0) + e);
-  D5 th = (d5c(1.0) - e) * r;
-  if (x.v < 0.0) th = -th;
-  const D5 sech2 = 4.0 * (e * r * r);
-  const D5 AB = A * B;
-  const D5 a = A * th;
-  const D5 a1 = AB * sech2;
-  const D5 a2 = -2.0 * (AB * B * th * sech2);
-  const D5 a3 = -2.0 * (AB * B * B * sech2 * (d5c(1.0) - 3.0 * (th * th)));
-  const D5 qq = q * q;
-  const D5 c = C * d5exp(-(D * qq));
-  const D5 c1 = -2.0 * (D * q * c);
-  const D5 c2 = (4.0 * (D * D * qq) - 2.0 * D) * c;
-  const D5 c3 = q * (12.0 * (D * D) - 8.0 * (D * D * D * qq)) * c;
-  const D5 ss = a * a + c * c;
-  const D5 rs = d5rsqrt(ss);
-  out[0] = ss * rs;
-  out[1] = (a * a1 + c * c1) * rs;
-  out[2] = ((a1 * a1 + a * a2) + (c1 * c1 + c * c2) - out[1] * out[1]) * rs;
-  out[3] = (3.0 * (a1 * a2 + c1 * c2) + (a * a3 + c * c3) - 3.0 * (out[1] * out[2])) * rs;
-  out[4] = 0.5 * ((a * c1 - c * a1) * rs * rs);
-}
-
-// Adjoints (sb[o], o = s, s1, s2, s3, d21) of the two-level quantities
-// pulled back to q1 (returned) and to (A, B, C, D) (added to th[0..3]).
-__host__ __device__ inline double q1_pullback(const DevModel &md, double q1, const double sb[5], double th[4]) {
-  D5 o[5];
-  qcle_q1_d5(md, q1, o);
-  double qb = 0.0;
-  for (int k = 0; k < 5; ++k) {
-    qb += sb[k] * o[k].d[0];
-    for (int j = 0; j < 4; ++j) th[j] += sb[k] * o[k].d[1 + j];
-  }
+// Adjoints (sb[o], o = s, s1, s2, s3, d21) of the two-level quantities of
+// Sec. 3.3 (the adiabatic energies and d21 below eq:QCLE, as qcle_q1 forms
+// them) pulled back to q1 (returned) and to (A, B, C, D) (added to th_out),
+// by a reverse sweep through the scalar formulas: th = tanh(x) and sech2 = 1 - th^2 with x = B q1 have th' = sech2 and
+// sech2' = -2 th sech2; c = C exp(-D q1^2).
+__host__ __device__ inline double q1_pullback_rev(const DevModel &md, double q, const double sb[5], double th_out[4]) {
+  const double A = md.A, B = md.B, C = md.C, D = md.D;
+  // forward values (as qcle_q1 forms them)
+  const double x = B * q;
+  const double e = exp(-2.0 * fabs(x));
+  const double r = 1.0 / (1.0 + e);
+  const double th = copysign((1.0 - e) * r, x);
+  const double sech2 = 4.0 * e * r * r;
+  const double AB = A * B;
+  const double a = A * th, a1 = AB * sech2, a2 = -2.0 * AB * B * th * sech2;
+  const double u = 1.0 - 3.0 * th * th;
+  const double a3 = -2.0 * AB * B * B * sech2 * u;
+  const double qq = q * q;
+  const double E = exp(-D * qq);
+  const double c = C * E;
+  const double c1 = -2.0 * D * q * c;
+  const double w2 = 4.0 * D * D * qq - 2.0 * D;
+  const double c2 = w2 * c;
+  const double w3 = 12.0 * D * D - 8.0 * D * D * D * qq;
+  const double c3 = q * w3 * c;
+  const double ss = a * a + c * c;
+  const double rs = 1.0 / sqrt(ss);
+  const double N1 = a * a1 + c * c1;
+  const double s1 = N1 * rs;
+  const double N2 = (a1 * a1 + a * a2) + (c1 * c1 + c * c2) - s1 * s1;
+  const double s2 = N2 * rs;
+  const double N3 = 3.0 * (a1 * a2 + c1 * c2) + (a * a3 + c * c3) - 3.0 * s1 * s2;
+  // reverse sweep
+  double ab = 0, a1b = 0, a2b = 0, a3b = 0, cb = 0, c1b = 0, c2b = 0, c3b = 0, rsb = 0, ssb = 0;
+  // d21 = (a c1 - c a1) rs^2 / 2
+  const double sd = sb[4];
+  ab += 0.5 * c1 * rs * rs * sd;
+  c1b += 0.5 * a * rs * rs * sd;
+  cb -= 0.5 * a1 * rs * rs * sd;
+  a1b -= 0.5 * c * rs * rs * sd;
+  rsb += (a * c1 - c * a1) * rs * sd;
+  // s3 = N3 rs
+  const double n3b = sb[3] * rs;
+  rsb += N3 * sb[3];
+  a1b += 3.0 * a2 * n3b;
+  a2b += 3.0 * a1 * n3b;
+  c1b += 3.0 * c2 * n3b;
+  c2b += 3.0 * c1 * n3b;
+  ab += a3 * n3b;
+  a3b += a * n3b;
+  cb += c3 * n3b;
+  c3b += c * n3b;
+  const double s2b = sb[2] - 3.0 * s1 * n3b;
+  double s1b = sb[1] - 3.0 * s2 * n3b;
+  // s2 = N2 rs
+  const double n2b = s2b * rs;
+  rsb += N2 * s2b;
+  a1b += 2.0 * a1 * n2b;
+  ab += a2 * n2b;
+  a2b += a * n2b;
+  c1b += 2.0 * c1 * n2b;
+  cb += c2 * n2b;
+  c2b += c * n2b;
+  s1b -= 2.0 * s1 * n2b;
+  // s1 = N1 rs
+  const double n1b = s1b * rs;
+  rsb += N1 * s1b;
+  ab += a1 * n1b;
+  a1b += a * n1b;
+  cb += c1 * n1b;
+  c1b += c * n1b;
+  // s = ss rs, rs = ss^(-1/2), ss = a^2 + c^2
+  ssb += rs * sb[0];
+  rsb += ss * sb[0];
+  ssb += -0.5 * rs * rs * rs * rsb;
+  ab += 2.0 * a * ssb;
+  cb += 2.0 * c * ssb;
+  // the tanh chain
+  double Ab = th * ab, ABb = sech2 * a1b, Bb = 0.0, thb = A * ab, sechb = AB * a1b;
+  ABb += -2.0 * B * th * sech2 * a2b;
+  Bb += -2.0 * AB * th * sech2 * a2b;
+  thb += -2.0 * AB * B * sech2 * a2b;
+  sechb += -2.0 * AB * B * th * a2b;
+  ABb += -2.0 * B * B * sech2 * u * a3b;
+  Bb += -4.0 * AB * B * sech2 * u * a3b;
+  sechb += -2.0 * AB * B * B * u * a3b;
+  thb += 12.0 * AB * B * B * sech2 * th * a3b;
+  Ab += B * ABb;
+  Bb += A * ABb;
+  const double xb = thb * sech2 - 2.0 * th * sech2 * sechb;
+  double qb = B * xb;
+  Bb += q * xb;
+  // the Gaussian chain
+  double Db = 0.0;
+  cb += -2.0 * D * q * c1b;
+  Db += -2.0 * q * c * c1b;
+  qb += -2.0 * D * c * c1b;
+  cb += w2 * c2b;
+  Db += (8.0 * D * qq - 2.0) * c * c2b;
+  qb += 8.0 * D * D * q * c * c2b;
+  cb += q * w3 * c3b;
+  qb += (w3 - 16.0 * D * D * D * qq) * c * c3b;
+  Db += q * (24.0 * D - 24.0 * D * D * qq) * c * c3b;
+  const double Cb = E * cb, Eb = C * cb;
+  Db += -qq * E * Eb;
+  qb += -2.0 * D * q * E * Eb;
+  th_out[0] += Ab;
+  th_out[1] += Bb;
+  th_out[2] += Cb;
+  th_out[3] += Db;
   return qb;
 }
 

@@ -118,7 +118,7 @@ __host__ __device__ inline A2 a2_vjp(const DevModel &md, int l, const A2 &y, con
   r.zi12 = 2.0 * E2 * g.zi11 - 2.0 * im * g.zi22;
   r.zr22 = E2 * g.zr12;
   r.zi22 = E2 * g.zi12;
-  r.q = q1_pullback(md, y.q, sb, th);
+  r.q = q1_pullback_rev(md, y.q, sb, th);
   return r;
 }
 
@@ -195,9 +195,9 @@ __host__ __device__ inline int a2_legs(const DevModel &md, A2 &y, HopScalars &h,
 // Reverse sweep of one interval that starts at (ys, hs): yb is the adjoint
 // of the interval's end state on entry and of its start on return; logwb is
 // the adjoint of the final log weight (every hop adds Lam to it).
-__host__ __device__ inline void a2_interval_rev(const DevModel &md, const A2 &ys, const HopScalars &hs, uint64_t gid,
-                                                uint64_t seed, double dt, A2 &yb, double logwb, double th[4],
-                                                Counters &cnt) {
+__host__ __device__ __noinline__ void a2_interval_rev_general(const DevModel &md, const A2 &ys, const HopScalars &hs,
+                                                              uint64_t gid, uint64_t seed, double dt, A2 &yb,
+                                                              double logwb, double th[4]) {
   A2 y = ys;
   HopScalars h = hs;
   double rem;
@@ -251,7 +251,23 @@ __host__ __device__ inline void a2_interval_rev(const DevModel &md, const A2 &ys
     yb = ybi;
     remb = rb;
   }
-  (void)cnt;
+}
+
+// An interval without a hop (its trial step ends it) swept inline, the
+// others by the general sweep.
+__host__ __device__ inline void a2_interval_rev(const DevModel &md, const A2 &ys, const HopScalars &hs, uint64_t gid,
+                                                uint64_t seed, double dt, A2 &yb, double logwb, double th[4]) {
+  A2Rec rt;
+  A2 yt;
+  a2_rk4(md, hs.comp, ys, dt, yt, &rt);
+  if (!(yt.Lam >= hs.E)) {
+    A2 ybi;
+    double hb;
+    a2_rk4_rev(md, hs.comp, rt, dt, yb, false, ybi, hb, th);
+    yb = ybi;
+    return;
+  }
+  a2_interval_rev_general(md, ys, hs, gid, seed, dt, yb, logwb, th);
 }
 
 // Adjoint of one beam's contribution Re(w c) to the objective, c the beam

@@ -110,7 +110,7 @@ adjoint_m2_kernel(DevModel md, const double *__restrict__ fin, const int32_t *__
         hs.E = sl[12 * nthr];
         hs.comp = (int)sl[13 * nthr];
         hs.nhop = (uint32_t)sl[14 * nthr];
-        a2_interval_rev(md, ys, hs, gid, seed, dt, yb, logwb, th, cnt);
+        a2_interval_rev(md, ys, hs, gid, seed, dt, yb, logwb, th);
       }
     }
     acc[0] += th[0];

@@ -308,7 +308,7 @@ __device__ inline void aw_vjp(const DevModel &md, int l, const typename AwT<D>::
   sb[2] = sg * Hb - bc * gi00;
   sb[3] = -sg * Pp0 * gi00;
   sb[4] = 2.0 * sgn * v * gL;
-  const double qb = q1_pullback(md, q0, sb, th);
+  const double qb = q1_pullback_rev(md, q0, sb, th);
   yb.x[0] = Xb + (lane == 0 ? qb : 0.0);
   yb.p[0] = Pb;
 #pragma unroll
@@ -403,9 +403,10 @@ __device__ inline void aw_hop(const DevModel &md, typename AwT<D>::Y &y, HopScal
 // One interval from (y, h) as the FP64 stepping kernel runs it, stopping at
 // the start of leg `stop` (if reached); returns the number of legs run.
 template <int D>
-__device__ inline int aw_legs(const DevModel &md, const typename AwT<D>::Cx &cx, typename AwT<D>::Y &y,
-                              HopScalars &h, uint64_t gid, uint64_t seed, double dt, int stop, double &rem,
-                              typename AwT<D>::Lds &s, Counters &cnt) {
+__device__ inline int aw_legs_general(const DevModel &md, const typename AwT<D>::Cx &cx,
+                                            typename AwT<D>::Y &y, HopScalars &h, uint64_t gid, uint64_t seed,
+                                            double dt, int stop, double &rem, typename AwT<D>::Lds &s) {
+  Counters cnt;
   rem = dt;
   int leg = 0;
   for (;;) {
@@ -431,25 +432,39 @@ __device__ inline int aw_legs(const DevModel &md, const typename AwT<D>::Cx &cx,
   }
 }
 
+// The whole interval: the trial step inline (most intervals have no hop),
+// the rest out of line.
+template <int D>
+__device__ inline void aw_interval(const DevModel &md, const typename AwT<D>::Cx &cx, typename AwT<D>::Y &y,
+                                   HopScalars &h, uint64_t gid, uint64_t seed, double dt, typename AwT<D>::Lds &s) {
+  typename AwT<D>::Y yt;
+  aw_rk4<D>(md, h.comp, cx, y, dt, yt, s, nullptr);
+  if (!(yt.Lam >= h.E)) {
+    y = yt;
+    return;
+  }
+  double rem;
+  aw_legs_general<D>(md, cx, y, h, gid, seed, dt, -1, rem, s);
+}
+
 // Reverse sweep of one interval starting at (ys, hs); yb: adjoint of its end
 // on entry, of its start on return.
 template <int D>
-__device__ inline void aw_interval_rev(const DevModel &md, const typename AwT<D>::Cx &cx,
+__device__ inline void aw_interval_rev_general(const DevModel &md, const typename AwT<D>::Cx &cx,
                                        const typename AwT<D>::Y &ys, const HopScalars &hs, uint64_t gid,
                                        uint64_t seed, double dt, typename AwT<D>::Y &yb, double logwb, double th[4],
                                        AwLds<D> &lds) {
   using Y = typename AwT<D>::Y;
-  Counters scratch;
   Y y = ys;
   HopScalars h = hs;
   double rem;
-  const int L = aw_legs<D>(md, cx, y, h, gid, seed, dt, -1, rem, lds.x, scratch);
+  const int L = aw_legs_general<D>(md, cx, y, h, gid, seed, dt, -1, rem, lds.x);
   double remb = 0.0;
   for (int j = L - 1; j >= 0; --j) {
     if (j > 0 || L > 1) {
       y = ys;
       h = hs;
-      aw_legs<D>(md, cx, y, h, gid, seed, dt, j, rem, lds.x, scratch);
+      aw_legs_general<D>(md, cx, y, h, gid, seed, dt, j, rem, lds.x);
     } else {
       y = ys;
       h = hs;
@@ -498,6 +513,25 @@ __device__ inline void aw_interval_rev(const DevModel &md, const typename AwT<D>
     yb = ybi;
     remb = rb;
   }
+}
+
+// An interval without a hop (the trial step ends it) swept inline; the
+// others by the general sweep.
+template <int D>
+__device__ inline void aw_interval_rev(const DevModel &md, const typename AwT<D>::Cx &cx,
+                                       const typename AwT<D>::Y &ys, const HopScalars &hs, uint64_t gid,
+                                       uint64_t seed, double dt, typename AwT<D>::Y &yb, double logwb, double th[4],
+                                       AwLds<D> &lds) {
+  typename AwT<D>::Y yt;
+  aw_rk4<D>(md, hs.comp, cx, ys, dt, yt, lds.x, lds.scr);
+  if (!(yt.Lam >= hs.E)) {
+    typename AwT<D>::Y ybi;
+    double hb;
+    aw_rk4_rev<D>(md, hs.comp, cx, ys, lds.scr, dt, yb, false, ybi, hb, th, lds.x);
+    yb = ybi;
+    return;
+  }
+  aw_interval_rev_general<D>(md, cx, ys, hs, gid, seed, dt, yb, logwb, th, lds);
 }
 
 // Load one beam's state (trajectory rows of f with leading dimension ld,
@@ -691,7 +725,6 @@ adjoint_wave_kernel(DevModel md, const double *__restrict__ fin, const int32_t *
                                   {fs[kRowAre * ld + b], fs[kRowAim * ld + b]}, w, yb, logwb, lds);
     double th[4] = {0.0, 0.0, 0.0, 0.0};
     const uint64_t gid = gid0 + (uint64_t)b;
-    Counters cnt;
     for (int c = cl.n_ckpt - 1; c >= 0; --c) {
       const int start = c * every, len = nsteps - start < every ? nsteps - start : every;
       const char *base = ckpt + (int64_t)c * cl.stride_bytes;
@@ -715,8 +748,7 @@ adjoint_wave_kernel(DevModel md, const double *__restrict__ fin, const int32_t *
           sl[(AwT<D>::NF + 1) * kAwLanes] = (double)hs.comp;
           sl[(AwT<D>::NF + 2) * kAwLanes] = (double)hs.nhop;
         }
-        double rem;
-        aw_legs<D>(md, cx, ys, hs, gid, seed, dt, -1, rem, lds.x, cnt);
+        aw_interval<D>(md, cx, ys, hs, gid, seed, dt, lds.x);
       }
       for (int i = len - 1; i >= 0; --i) {
         const double *sl = myslots + (int64_t)i * AwT<D>::NSLOT * kAwLanes;

@@ -15,6 +15,7 @@ hipError_t launch_hop_p32(const shgb_state &, const int32_t *, int64_t, uint64_t
 hipError_t launch_hop_lq(const DevLQ &, const shgb_state &, const int32_t *, int64_t, uint64_t, uint64_t *,
                          hipStream_t);
 hipError_t launch_step_m2(const DevModel &, const shgb_state &, int, double, uint64_t, uint64_t *, hipStream_t);
+hipError_t launch_step_m2_rk3(const DevModel &, const shgb_state &, int, double, uint64_t, uint64_t *, hipStream_t);
 hipError_t launch_step_wave(const DevModel &, const shgb_state &, int, double, uint64_t, uint64_t *, hipStream_t);
 bool step_wave_supported(int d);
 hipError_t launch_hop(const DevModel &, const shgb_state &, const int32_t *, int64_t, uint64_t, uint64_t *,
@@ -226,6 +227,19 @@ int shgb_step_ensemble(const shgb_model *model, const shgb_state *st, int32_t ns
   if (md.d == 1) return hip_status(launch_step_m2(md, *st, nsteps, dt, seed, diag, (hipStream_t)stream));
   if (!step_wave_supported(md.d)) return SHGB_EUNSUPPORTED;
   return hip_status(launch_step_wave(md, *st, nsteps, dt, seed, diag, (hipStream_t)stream));
+}
+
+int shgb_step_ensemble_scheme(const shgb_model *model, const shgb_state *st, int32_t nsteps, double dt,
+                              uint64_t seed, int32_t scheme, uint64_t *diag, void *stream) {
+  if (scheme == SHGB_SCHEME_RK4) return shgb_step_ensemble(model, st, nsteps, dt, seed, diag, stream);
+  if (scheme != SHGB_SCHEME_RK3) return SHGB_EINVAL;
+  DevModel md;
+  int rc = to_dev_model(model, md);
+  if (rc) return rc;
+  if ((rc = check_state(st, md))) return rc;
+  if (nsteps < 0 || !finite_pos(dt)) return SHGB_EINVAL;
+  if (md.kind != SHGB_MODEL_QCLE || md.d != 1 || st->precision != SHGB_FP64) return SHGB_EUNSUPPORTED;
+  return hip_status(launch_step_m2_rk3(md, *st, nsteps, dt, seed, diag, (hipStream_t)stream));
 }
 
 int shgb_hop(const shgb_model *model, const shgb_state *st, const int32_t *idx, int64_t n_idx, uint64_t seed,

@@ -80,6 +80,59 @@ __host__ __device__ inline void rk4_2(const DevModel &md, HopCtx &hc, Counters &
   for (int st = 0; st < 4; ++st) stage2(md, hc, cnt, y, ys, out, st, st == 2 ? h : 0.5 * h, h6);
 }
 
+// The derivative of the beam ODEs at stage values ys on the beam's
+// component (the formulas of stage2); the first evaluation of a step
+// completes a pending hop at ys, the state where it began.
+__host__ __device__ inline Ode2 deriv2(const DevModel &md, HopCtx &hc, Counters &cnt, const Ode2 &ys, bool first) {
+  const Q1 k = qcle_q1(md, ys.q);
+  const double v = ys.p * md.inv_mass;
+  if (first && hc.pending) {
+    hop_choose(v * k.d21, hc.h, hc.gid, hc.seed, cnt, kTieRel);
+    hc.pending = false;
+  }
+  const int l = hc.h.comp;
+  const double sg = comp_sigma(l), bc = comp_bcoef(l);
+  const double E1 = sg * k.s1, E2 = sg * k.s2, E3 = sg * k.s3;
+  const double b0 = bc * k.s, b1 = bc * k.s1, b2 = bc * k.s2;
+  Ode2 d;
+  d.q = v;
+  d.p = -E1;
+  d.Pq = b1 + E2 * ys.Pp;
+  d.Pp = -ys.Pq * md.inv_mass;
+  d.zr11 = 2.0 * ys.zr12 * E2;
+  d.zi11 = 2.0 * ys.zi12 * E2 - ys.Pp * E3 - b2;
+  d.zr12 = ys.zr22 * E2 - ys.zr11 * md.inv_mass;
+  d.zi12 = ys.zi22 * E2 - ys.zi11 * md.inv_mass;
+  d.zr22 = -2.0 * ys.zr12 * md.inv_mass;
+  d.zi22 = -2.0 * ys.zi12 * md.inv_mass;
+  d.S = b0;
+  d.Lam = 2.0 * fabs(v * k.d21);
+  return d;
+}
+
+// One step of Kutta's third-order Runge-Kutta method (Sec. 2.4 integrates
+// with a third-order method without naming it): k1 = f(y),
+// k2 = f(y + h k1 / 2), k3 = f(y + h (2 k2 - k1)), y + h (k1 + 4 k2 + k3) / 6.
+__host__ __device__ inline void rk3_2(const DevModel &md, HopCtx &hc, Counters &cnt, const Ode2 &y, double h,
+                                      Ode2 &out) {
+#define SHGB_ODE2_FIELDS(F) F(q) F(p) F(Pq) F(Pp) F(zr11) F(zr12) F(zr22) F(zi11) F(zi12) F(zi22) F(S) F(Lam)
+  const Ode2 k1 = deriv2(md, hc, cnt, y, true);
+  Ode2 ys;
+  const double hh = 0.5 * h, h6 = h * (1.0 / 6.0);
+#define F(f) ys.f = y.f + hh * k1.f;
+  SHGB_ODE2_FIELDS(F)
+#undef F
+  const Ode2 k2 = deriv2(md, hc, cnt, ys, false);
+#define F(f) ys.f = y.f + h * (2.0 * k2.f - k1.f);
+  SHGB_ODE2_FIELDS(F)
+#undef F
+  const Ode2 k3 = deriv2(md, hc, cnt, ys, false);
+#define F(f) out.f = y.f + h6 * (k1.f + 4.0 * k2.f + k3.f);
+  SHGB_ODE2_FIELDS(F)
+#undef F
+#undef SHGB_ODE2_FIELDS
+}
+
 // Complete a hop still pending at the end of a call.
 __host__ __device__ inline void hop_finish(const DevModel &md, HopCtx &hc, double q, double p, Counters &cnt,
                                            double tie_rel) {
@@ -89,7 +142,9 @@ __host__ __device__ inline void hop_finish(const DevModel &md, HopCtx &hc, doubl
   hc.pending = false;
 }
 
-// One interval [t_n, t_n + dt] for one beam.
+// One interval [t_n, t_n + dt] for one beam with the classical RK4 step
+// (RK = 4) or Kutta's third-order step (RK = 3).
+template <int RK = 4>
 __host__ __device__ inline void interval2(const DevModel &md, Ode2 &y, HopCtx &hc, double dt, Counters &cnt) {
   double rem = dt;      // time left in the interval
   double hstep = dt;    // size of the next RK4 call
@@ -98,7 +153,8 @@ __host__ __device__ inline void interval2(const DevModel &md, Ode2 &y, HopCtx &h
   int hops = 0;
   Ode2 yn;
   for (;;) {
-    rk4_2(md, hc, cnt, y, hstep, yn);
+    if constexpr (RK == 3) rk3_2(md, hc, cnt, y, hstep, yn);
+    else rk4_2(md, hc, cnt, y, hstep, yn);
     const double E = hc.h.E;
     if (!partial) {
       const bool capped = hops >= SHGB_HOP_CAP;
@@ -128,6 +184,7 @@ __host__ __device__ inline void interval2(const DevModel &md, Ode2 &y, HopCtx &h
 }
 
 // All nsteps intervals of beam b (one thread), FP64.
+template <int RK = 4>
 __device__ inline void m2_beam(const DevModel &md, double *__restrict__ tr, double *__restrict__ sc,
                                int32_t *__restrict__ comp, uint32_t *__restrict__ nhop, int64_t n, int64_t ld,
                                uint64_t gid0, int nsteps, double dt, uint64_t seed, int64_t b, Counters &cnt) {
@@ -158,7 +215,7 @@ __device__ inline void m2_beam(const DevModel &md, double *__restrict__ tr, doub
     hc.pending = false;
     hc.gid = gid0 + (uint64_t)b;
     hc.seed = seed;
-    for (int s = 0; s < nsteps; ++s) interval2(md, y, hc, dt, cnt);
+    for (int s = 0; s < nsteps; ++s) interval2<RK>(md, y, hc, dt, cnt);
     hop_finish(md, hc, y.q, y.p, cnt, kTieRel);
     const double chk = y.q + y.p + y.Pq + y.Pp + y.zr11 + y.zr12 + y.zr22 + y.zi11 + y.zi12 +
                        y.zi22 + y.S + y.Lam + h.logw;
@@ -194,6 +251,17 @@ step_m2_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ sc, in
   Counters cnt;
   m2_beam(md, tr, sc, comp, nhop, n, ld, gid0, nsteps, dt, seed, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
           cnt);
+  flush_counters(cnt, diag);
+}
+
+// The same with Kutta's third-order step.
+__global__ void __launch_bounds__(256)
+step_m2_rk3_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
+                   uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps,
+                   double dt, uint64_t seed, uint64_t *diag) {
+  Counters cnt;
+  m2_beam<3>(md, tr, sc, comp, nhop, n, ld, gid0, nsteps, dt, seed,
+             (int64_t)blockIdx.x * blockDim.x + threadIdx.x, cnt);
   flush_counters(cnt, diag);
 }
 
@@ -458,6 +526,17 @@ hipError_t launch_step_m2_batched(bool mixed_state, int wpb, const BatchItem *it
     SHGB_M2B(256)
   }
 #undef SHGB_M2B
+  return hipGetLastError();
+}
+
+hipError_t launch_step_m2_rk3(const DevModel &md, const shgb_state &st, int nsteps, double dt, uint64_t seed,
+                              uint64_t *diag, hipStream_t stream) {
+  if (st.n_beams == 0 || nsteps == 0) return hipSuccess;
+  const int threads = 256;
+  const int64_t blocks = (st.n_beams + threads - 1) / threads;
+  hipLaunchKernelGGL(step_m2_rk3_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, md, st.f64,
+                     scalar_block(st), st.comp, st.nhop, st.n_beams, st.ld, st.beam_id_offset, nsteps, dt, seed,
+                     diag);
   return hipGetLastError();
 }
 

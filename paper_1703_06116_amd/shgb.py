@@ -25,6 +25,7 @@ SHGB_NDIAG = 8
 SHGB_SCALAR_FIELDS = 8
 PRECISION = {"fp64": 0, "mixed": 1}
 DIST = {"normal": 0, "uniform": 1}
+SHGB_SCHEME_RK4, SHGB_SCHEME_RK3 = 4, 3
 DIAG_NAMES = ("hops", "thr_ties", "dest_ties", "cap_overflow", "nonfinite", "nonspd",
               "zero_rate", "bad_index")
 
@@ -93,6 +94,7 @@ def _load():
         "shgb_init_beams": (I32, [P(Model), P(InitSpec), P(StateDesc), U64, V]),
         "shgb_step_ensemble": (I32, [P(Model), P(StateDesc), I32, D, U64, V, V]),
         "shgb_hop": (I32, [P(Model), P(StateDesc), V, I64, U64, V, V]),
+        "shgb_step_ensemble_scheme": (I32, [P(Model), P(StateDesc), I32, D, U64, I32, V, V]),
         "shgb_populations_workspace": (I64, [I64, I32]),
         "shgb_populations": (I32, [P(Model), P(StateDesc), V, V, I64, V, V]),
         "shgb_populations_noalloc": (I32, [P(Model), P(StateDesc), V, V, V]),
@@ -127,7 +129,7 @@ def _load():
 
 _lib = _load()
 
-EXPORTED = ("shgb_init_beams", "shgb_step_ensemble", "shgb_hop", "shgb_populations_workspace",
+EXPORTED = ("shgb_init_beams", "shgb_step_ensemble", "shgb_step_ensemble_scheme", "shgb_hop", "shgb_populations_workspace",
             "shgb_populations", "shgb_populations_noalloc", "shgb_population_stats",
             "shgb_reconstruct_workspace", "shgb_reconstruct", "shgb_philox",
             "shgb_strerror", "shgb_version", "shgb_abi_sizes", "shgb_batch_table_bytes", "shgb_batch_prepare",
@@ -258,10 +260,17 @@ def init_beams(model, spec, state, seed, stream=None):
                                                    ctypes.byref(d), seed, _stream(stream)))
 
 
-def step_ensemble(model, state, nsteps, dt, seed, diag=None, stream=None):
+def step_ensemble(model, state, nsteps, dt, seed, diag=None, stream=None, scheme="rk4"):
+    """Advance every beam by nsteps intervals of dt; scheme "rk4" (classical) or "rk3" (Kutta)."""
     d = state.desc()
-    _check("shgb_step_ensemble", _lib.shgb_step_ensemble(ctypes.byref(model), ctypes.byref(d), int(nsteps),
-                                                         float(dt), seed, _ptr(diag), _stream(stream)))
+    if scheme == "rk4":
+        _check("shgb_step_ensemble", _lib.shgb_step_ensemble(ctypes.byref(model), ctypes.byref(d), int(nsteps),
+                                                             float(dt), seed, _ptr(diag), _stream(stream)))
+        return
+    code = {"rk3": SHGB_SCHEME_RK3}[scheme]
+    _check("shgb_step_ensemble_scheme", _lib.shgb_step_ensemble_scheme(ctypes.byref(model), ctypes.byref(d),
+                                                                       int(nsteps), float(dt), seed, code,
+                                                                       _ptr(diag), _stream(stream)))
 
 
 def hop(model, state, idx, seed, diag=None, stream=None):

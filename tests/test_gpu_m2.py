@@ -271,3 +271,27 @@ def test_population_stats_on_the_device(gpu):
     assert (one[:, :2] == [1.0, 2.0]).all() and (one[:, 2:] == 0.0).all()
     with pytest.raises(gpu.ShgbError):
         gpu.population_stats(sums, 0)
+
+
+def test_rk3_scheme_matches_oracle(gpu):
+    """Kutta's third-order scheme (the paper's "third-order Runge-Kutta method") on the GPU
+    against the oracle run with the same scheme: beams near the crossing, about three hops each,
+    per-beam state within 1e-10, hop counts and components bit-exact apart from oracle ties; and
+    the scheme changes the result (it is not the RK4 path)."""
+    c = workloads.config("qcle1d_1e4", n_beams=300, nsteps=500, q_mean=-2.5, q_std=0.3, p_a=30.0)
+    mdl = gpu_model(c)
+    st = gpu.State(c["n_beams"], 2)
+    gpu.init_beams(mdl, gpu_spec(c), st, c["seed"])
+    diag = gpu.new_diag()
+    gpu.step_ensemble(mdl, st, c["nsteps"], c["dt"], c["seed"], diag, scheme="rk3")
+    e = oracle_init(c, c["n_beams"])
+    oshgb.advance(oracle_model(c), e, c["nsteps"], c["dt"], c["seed"], scheme="rk3")
+    errs, ties = compare_states(gpu.unpack(st), e, label="rk3")
+    assert e.nhop.sum() > 2 * c["n_beams"] and diag[0].item() == e.nhop.sum()
+    st4 = gpu.State(c["n_beams"], 2)
+    gpu.init_beams(mdl, gpu_spec(c), st4, c["seed"])
+    gpu.step_ensemble(mdl, st4, c["nsteps"], c["dt"], c["seed"])
+    assert not torch.equal(st4.f64, st.f64)
+    with pytest.raises(gpu.ShgbError):
+        gpu.step_ensemble(mdl, gpu.State(4, 2, precision="mixed"), 1, 0.5, 1, scheme="rk3")
+    print("rk3 errors", errs, "ties", ties)

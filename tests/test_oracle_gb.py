@@ -83,10 +83,10 @@ def exact_beam(model, ens, T):
     return XT, PT, ZT, ens.S[0] + S_int, AT
 
 
-def run_rk4(model, ens, T, nsteps):
+def run_rk4(model, ens, T, nsteps, scheme="rk4"):
     e = ens.subset([0])
     for _ in range(nsteps):
-        shgb.advance_interval(model, e, T / nsteps, seed=1)
+        shgb.advance_interval(model, e, T / nsteps, seed=1, scheme=scheme)
     return e
 
 
@@ -109,6 +109,23 @@ def test_P1_exact_propagation_and_order4(m):
     np.testing.assert_allclose(e.X[0], XT, rtol=0, atol=1e-11)
     np.testing.assert_allclose(e.M[0] + 1j * e.N[0], ZT, rtol=0, atol=1e-11 * np.abs(ZT).max())
     assert abs(e.S[0] - ST) < 1e-10 and abs(e.A[0] - AT) < 1e-11
+
+
+@pytest.mark.parametrize("m", [2, 4])
+def test_P1_exact_propagation_and_order3(m):
+    """Kutta's third-order scheme against the same closed form: error ratio 8 on halving."""
+    model = random_linquad(m, seed=m)
+    ens = one_beam(m, seed=m)
+    T = 1.5
+    XT, PT, ZT, ST, AT = exact_beam(model, ens, T)
+    errs = []
+    for n in (40, 80, 160):
+        e = run_rk4(model, ens, T, n, scheme="rk3")
+        errs.append(max(np.abs(e.X[0] - XT).max(), np.abs(e.P[0] - PT).max(),
+                        np.abs(e.M[0] + 1j * e.N[0] - ZT).max(), abs(e.S[0] - ST), abs(e.A[0] - AT)))
+    assert errs[-1] < 1e-4
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 6.5 < e1 / e2 < 9.5, errs            # third order: ratio 8
 
 
 def exact_field(model, ens0, eps, T, x):

@@ -296,3 +296,40 @@ BATH_MISTAKES = {
 def test_bath_law_catches_planted_mistake(name):
     z_energy, z_parts, corr, p_ks = qcle.bath_law(load(*BATH_MISTAKES[name], original=sampling_base))
     assert z_energy > 8.0 or z_parts > 8.0 or corr > 8.0 or p_ks < 1e-6, (name, z_energy, z_parts, corr, p_ks)
+
+
+def p1_error_rk3(mod, m=2, n=160, T=1.5):
+    """Max error of a beam after n third-order steps against its closed form (the order-3 pin: 1e-4)."""
+    model, ens = gb.random_linquad(m, seed=m), gb.one_beam(m, seed=m)
+    XT, PT, ZT, ST, AT = gb.exact_beam(model, ens, T)
+    e = ens.subset([0])
+    for _ in range(n):
+        mod.advance_interval(model, e, T / n, seed=1, scheme="rk3")
+    return max(np.abs(e.X[0] - XT).max(), np.abs(e.P[0] - PT).max(), np.abs(e.M[0] + 1j * e.N[0] - ZT).max(),
+               abs(e.S[0] - ST), abs(e.A[0] - AT))
+
+
+def rk3_order_check(mod):
+    """(error at 160 steps, error ratio from 80 to 160 steps): the pin wants < 1e-4 and about 8."""
+    e80, e160 = p1_error_rk3(mod, n=80), p1_error_rk3(mod, n=160)
+    return e160, e80 / e160
+
+
+def test_unchanged_source_passes_the_order3_check():
+    err, ratio = rk3_order_check(load())
+    assert err < 1e-4 and 6.5 < ratio < 9.5
+
+
+RK3_MISTAKES = {
+    "RK3: middle weight 2 instead of 4": ("(b1 + 4.0 * b2 + b3)", "(b1 + 2.0 * b2 + b3)"),
+    "RK3: third stage at y + h k2": ("k3 = rhs(model, comp, _axpy(_axpy(y, -h, k1), 2.0 * h, k2))",
+                                     "k3 = rhs(model, comp, _axpy(y, h, k2))"),
+    "RK3: second stage at the full step": ("k2 = rhs(model, comp, _axpy(y, 0.5 * h, k1))\n    k3 = rhs(model, comp, _axpy(_axpy(",
+                                           "k2 = rhs(model, comp, _axpy(y, h, k1))\n    k3 = rhs(model, comp, _axpy(_axpy("),
+}
+
+
+@pytest.mark.parametrize("name", list(RK3_MISTAKES))
+def test_P1_order3_catches_planted_rk3_mistake(name):
+    err, ratio = rk3_order_check(load(*RK3_MISTAKES[name]))
+    assert err > 1e-3 or not 6.5 < ratio < 9.5, (name, err, ratio)
