@@ -267,6 +267,22 @@ int64_t shgb_reconstruct_workspace(int64_t n_beams, int32_t m, int64_t Q);
 int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double *points,
                      int64_t Q, double *out, void *work, int64_t work_bytes, void *stream);
 
+/* shgb_reconstruct with a choice of arithmetic.  SHGB_FIELD_DEFAULT: as
+ * shgb_reconstruct.  SHGB_FIELD_FP32_MATRIX (m = 24): the exponents on the
+ * FP32 matrix cores about a centre per tile of 64 beams, the beam weights in
+ * FP64, exp and sincos in FP32, FP64 sums.  Its error is stated, not bounded
+ * by the FP64 bar: on the 2^18-beam, 2000-interval d = 12 ensemble about
+ * 1e-3 of sum_k |exp(omega_k) G_k(x)| at worst and 1e-4 in relative L2
+ * norm (squeezed beams lose digits in the quadratic form).  Same workspace
+ * rules, queried with shgb_reconstruct_workspace_mode.  Errors: as
+ * shgb_reconstruct; EINVAL for an unknown mode, EUNSUPPORTED for the FP32
+ * mode with m != 24. */
+#define SHGB_FIELD_DEFAULT 0
+#define SHGB_FIELD_FP32_MATRIX 1
+int64_t shgb_reconstruct_workspace_mode(int64_t n_beams, int32_t m, int64_t Q, int32_t mode);
+int shgb_reconstruct_mode(const shgb_model *model, const shgb_state *st, const double *points, int64_t Q,
+                          double *out, void *work, int64_t work_bytes, int32_t mode, void *stream);
+
 /* ---- pathwise derivative of the populations ----------------------------
  * The derivative of the population sums (Sec. 2.3 eq:shgb integrated,
  * as shgb_populations) after nsteps intervals, with respect to

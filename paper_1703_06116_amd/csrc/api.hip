@@ -65,6 +65,10 @@ hipError_t launch_step_m2_batched(bool mixed_state, int wpb, const BatchItem *it
 __global__ void batch_reset_kernel(unsigned long long *queue) { queue[0] = 0ull; }
 hipError_t launch_recon_mfma(const DevModel &, const shgb_state &, const double *, int64_t, double *, void *,
                              hipStream_t);
+int64_t recon_mfma32_workspace_bytes(int64_t, int64_t);
+bool recon_mfma32_supported(int64_t, int64_t);
+hipError_t launch_recon_mfma32(const DevModel &, const shgb_state &, const double *, int64_t, double *, void *,
+                               hipStream_t);
 }  // namespace shgb
 
 using namespace shgb;
@@ -324,6 +328,27 @@ int shgb_reconstruct(const shgb_model *model, const shgb_state *st, const double
   if (!recon_wave_supported(st->m)) return SHGB_EUNSUPPORTED;
   if (work_bytes < recon_wave_workspace_bytes(st->n_beams, st->m, Q)) return SHGB_EWORKSPACE;
   return hip_status(launch_recon_wave(md, *st, points, Q, out, work, (hipStream_t)stream));
+}
+
+int64_t shgb_reconstruct_workspace_mode(int64_t n_beams, int32_t m, int64_t Q, int32_t mode) {
+  if (mode == SHGB_FIELD_DEFAULT) return shgb_reconstruct_workspace(n_beams, m, Q);
+  if (mode != SHGB_FIELD_FP32_MATRIX || m != 24 || n_beams < 0 || Q < 0) return -1;
+  return recon_mfma32_workspace_bytes(n_beams, Q);
+}
+
+int shgb_reconstruct_mode(const shgb_model *model, const shgb_state *st, const double *points, int64_t Q, double *out,
+                          void *work, int64_t work_bytes, int32_t mode, void *stream) {
+  if (mode == SHGB_FIELD_DEFAULT) return shgb_reconstruct(model, st, points, Q, out, work, work_bytes, stream);
+  if (mode != SHGB_FIELD_FP32_MATRIX) return SHGB_EINVAL;
+  DevModel md;
+  int rc = to_dev_model(model, md);
+  if (rc) return rc;
+  if ((rc = check_state(st, md))) return rc;
+  if (Q < 0 || (Q > 0 && (!points || !out || !work))) return SHGB_EINVAL;
+  if (Q > (int64_t)INT32_MAX) return SHGB_EINVAL;
+  if (st->m != 24 || !recon_mfma32_supported(st->n_beams, Q)) return SHGB_EUNSUPPORTED;
+  if (work_bytes < recon_mfma32_workspace_bytes(st->n_beams, Q)) return SHGB_EWORKSPACE;
+  return hip_status(launch_recon_mfma32(md, *st, points, Q, out, work, (hipStream_t)stream));
 }
 
 // enough for either tangent form (the query does not know m)

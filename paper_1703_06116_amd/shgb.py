@@ -26,6 +26,7 @@ SHGB_SCALAR_FIELDS = 8
 PRECISION = {"fp64": 0, "mixed": 1}
 DIST = {"normal": 0, "uniform": 1}
 SHGB_SCHEME_RK4, SHGB_SCHEME_RK3 = 4, 3
+SHGB_FIELD_DEFAULT, SHGB_FIELD_FP32_MATRIX = 0, 1
 DIAG_NAMES = ("hops", "thr_ties", "dest_ties", "cap_overflow", "nonfinite", "nonspd",
               "zero_rate", "bad_index")
 
@@ -101,6 +102,8 @@ def _load():
         "shgb_population_stats": (I32, [V, I64, V, V]),
         "shgb_reconstruct_workspace": (I64, [I64, I32, I64]),
         "shgb_reconstruct": (I32, [P(Model), P(StateDesc), V, I64, V, V, I64, V]),
+        "shgb_reconstruct_workspace_mode": (I64, [I64, I32, I64, I32]),
+        "shgb_reconstruct_mode": (I32, [P(Model), P(StateDesc), V, I64, V, V, I64, I32, V]),
         "shgb_philox": (I32, [U64, V, V, I64, V]),
         "shgb_strerror": (ctypes.c_char_p, [I32]),
         "shgb_version": (I32, []),
@@ -131,7 +134,8 @@ _lib = _load()
 
 EXPORTED = ("shgb_init_beams", "shgb_step_ensemble", "shgb_step_ensemble_scheme", "shgb_hop", "shgb_populations_workspace",
             "shgb_populations", "shgb_populations_noalloc", "shgb_population_stats",
-            "shgb_reconstruct_workspace", "shgb_reconstruct", "shgb_philox",
+            "shgb_reconstruct_workspace", "shgb_reconstruct", "shgb_reconstruct_workspace_mode",
+            "shgb_reconstruct_mode", "shgb_philox",
             "shgb_strerror", "shgb_version", "shgb_abi_sizes", "shgb_batch_table_bytes", "shgb_batch_prepare",
             "shgb_step_batched", "shgb_population_tangent_workspace", "shgb_population_tangent",
             "shgb_checkpoint_bytes", "shgb_step_checkpointed", "shgb_population_adjoint_workspace",
@@ -308,23 +312,28 @@ def populations_noalloc(model, state, out, diag=None, stream=None):
     return out
 
 
-def reconstruct_workspace(n, m, Q):
-    return int(_lib.shgb_reconstruct_workspace(n, m, Q))
+FIELD_MODES = {"default": SHGB_FIELD_DEFAULT, "fp32": SHGB_FIELD_FP32_MATRIX}
 
 
-def reconstruct(model, state, points, out=None, work=None, stream=None):
-    """Unnormalised sums per component at the points: a (4, Q) complex128 device tensor."""
+def reconstruct_workspace(n, m, Q, mode="default"):
+    return int(_lib.shgb_reconstruct_workspace_mode(n, m, Q, FIELD_MODES[mode]))
+
+
+def reconstruct(model, state, points, out=None, work=None, stream=None, mode="default"):
+    """Unnormalised sums per component at the points: a (4, Q) complex128 device tensor.
+    mode "fp32" (m = 24): the exponents on the FP32 matrix cores (error stated in include/shgb.h)."""
     assert points.dtype == torch.float64 and points.is_contiguous() and points.shape[1] == state.m
     Q = points.shape[0]
     dev = state.f64.device
     if out is None:
         out = torch.empty((SHGB_NCOMP, Q, 2), dtype=torch.float64, device=dev)
-    nb = reconstruct_workspace(state.n, state.m, Q)
+    nb = reconstruct_workspace(state.n, state.m, Q, mode)
     if work is None:
         work = torch.empty(max(nb, 8), dtype=torch.uint8, device=dev)
     d = state.desc()
-    _check("shgb_reconstruct", _lib.shgb_reconstruct(ctypes.byref(model), ctypes.byref(d), _ptr(points), Q,
-                                                     _ptr(out), _ptr(work), work.numel(), _stream(stream)))
+    _check("shgb_reconstruct_mode", _lib.shgb_reconstruct_mode(ctypes.byref(model), ctypes.byref(d), _ptr(points),
+                                                               Q, _ptr(out), _ptr(work), work.numel(),
+                                                               FIELD_MODES[mode], _stream(stream)))
     return torch.view_as_complex(out)
 
 

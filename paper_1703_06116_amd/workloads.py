@@ -102,6 +102,20 @@ def points_near(centres, eps, n, seed):
     return np.ascontiguousarray(centres[k] + np.sqrt(eps) * rng.normal(size=(n, centres.shape[1])))
 
 
+def points_in_beams(centres, M, eps, n, seed):
+    """n points drawn from the beams' own Gaussians: x = X_k + y, k a random beam, y ~ N(0, eps M_k^-1)
+    (M_k the real part of beam k's Hessian), so that |G_k(x)| is about exp(-m/4) on average instead
+    of vanishing in the beam's stiff directions."""
+    rng = np.random.default_rng(seed)
+    centres = np.asarray(centres, dtype=np.float64)
+    M = np.asarray(M, dtype=np.float64)
+    k = rng.integers(0, centres.shape[0], n)
+    xi = rng.normal(size=(n, centres.shape[1]))
+    L = np.linalg.cholesky(M[k])                                        # M = L L^T
+    y = np.linalg.solve(np.swapaxes(L, 1, 2), xi[..., None])[..., 0]     # L^T y = xi: y ~ N(0, M^-1)
+    return np.ascontiguousarray(centres[k] + np.sqrt(eps) * y)
+
+
 def points_near_final(c, n, seed):
     """n evaluation points around a stand-in for the final ensemble of a QCLE workload.
 
