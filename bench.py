@@ -309,10 +309,38 @@ def run_plain(name, steps, warmup, with_mixed):
                     for i, n in enumerate(names)}
         s = stats.cpu().numpy()
         field = rec.cpu().numpy() if Q else None
+        f32 = None
+        if precision == "mixed" and m == 24 and Q:
+            # the same field on the FP32 matrix cores (error stated, not the default)
+            w32 = torch.empty(max(shgb.reconstruct_workspace(N, m, Q, "fp32"), 8), dtype=torch.uint8, device=dev)
+            r32 = torch.empty((4, Q, 2), dtype=torch.float64, device=dev)
+            shgb.reconstruct(mdl, st, pts, out=r32, work=w32, mode="fp32")
+            ev = [_timer() for _ in range(2)]
+            torch.cuda.synchronize()
+            ev[0].record()
+            for _ in range(steps):
+                shgb.reconstruct(mdl, st, pts, out=r32, work=w32, mode="fp32")
+            ev[1].record()
+            torch.cuda.synchronize()
+            f32_ms = ev[0].elapsed_time(ev[1]) / steps
+            v32 = r32.cpu().numpy()
+            f32 = {"ms": f32_ms, "evals_per_s": N * Q / (f32_ms / 1e3),
+                   "speedup_vs_fp64_matrix_field": phase_ms["reconstruct"] / f32_ms,
+                   "rel_l2_vs_fp64_matrix_field": float(np.linalg.norm(v32 - field) / max(np.linalg.norm(field),
+                                                                                           1e-300)),
+                   "roofline": {"bound": "mfma", "kernel": "rm32_gemm_kernel (FP32 MFMA 16x16x4)",
+                                "achieved": FLOPS_PER_EVAL_M24 * N * Q / (f32_ms / 1e3) / 1e12,
+                                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                                "frac": FLOPS_PER_EVAL_M24 * N * Q / (f32_ms / 1e3) / 1e12 / PEAK_FP32_TFLOPS,
+                                "note": "whole field call (beam weights, GEMM, reduction) against the FP32 matrix "
+                                        "peak"},
+                   "stated_error": "1e-3 of sum |terms| at worst, 1e-4 relative L2 against the FP64 oracle "
+                                   "(tests/test_gpu_field32.py)"}
+            del w32, r32
         del st, rec_work, pop_work
         torch.cuda.empty_cache()
         return dict(ms_per_step=(t1 - t0) * 1e3 / steps, phase_ms=phase_ms, mean=s[:, 0] + 1j * s[:, 1],
-                    se=s[:, 2] + 1j * s[:, 3], diag=diag.cpu().numpy() // max(steps, 1), field=field)
+                    se=s[:, 2] + 1j * s[:, 3], diag=diag.cpu().numpy() // max(steps, 1), field=field, f32=f32)
 
     r64 = timed_run("fp64")
     ms_per_step, phase_ms = r64["ms_per_step"], r64["phase_ms"]
@@ -385,6 +413,8 @@ def run_plain(name, steps, warmup, with_mixed):
                                            max(np.linalg.norm(r64["field"]), 1e-300))),
             "diag_per_step": {n: int(v) for n, v in zip(shgb.DIAG_NAMES, rmx["diag"])},
         }
+        if rmx["f32"] is not None:
+            line["mixed"]["field_fp32_matrix"] = rmx["f32"]
     return line
 
 
