@@ -41,19 +41,31 @@ hipError_t launch_step_checkpointed(const DevModel &md, const shgb_state &st, in
   return hipGetLastError();
 }
 
-// Sum the block partials (kAdjVals per block) in block order.
-
-__global__ void __launch_bounds__(64) adj_final_kernel(const double *__restrict__ partial, int64_t nblocks,
-                                                       double *__restrict__ out) {
-  const int k = threadIdx.x;
-  if (k >= 6) return;
-  double s = 0.0;
-  for (int64_t b = 0; b < nblocks; ++b) s += partial[b * kAdjVals + k];
-  out[k] = s;
+// Sum the partial rows (kAdjVals doubles each: per block or per beam) into
+// the six outputs: 256 lanes take rows k, k + 256, ... in order, then a
+// fixed tree over the lanes (the same order on every call).
+__global__ void __launch_bounds__(256) adj_final_kernel(const double *__restrict__ partial, int64_t nrows,
+                                                        double *__restrict__ out) {
+  __shared__ double red[6][256];
+  const int t = threadIdx.x;
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t r = t; r < nrows; r += 256)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s[k] += partial[r * kAdjVals + k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) red[k][t] = s[k];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) red[k][t] += red[k][t + h];
+    __syncthreads();
+  }
+  if (t < 6) out[t] = red[t][0];
 }
 
 hipError_t launch_adj_final(const double *partial, int64_t nblocks, double *out, hipStream_t stream) {
-  hipLaunchKernelGGL(adj_final_kernel, dim3(1), dim3(64), 0, stream, partial, nblocks, out);
+  hipLaunchKernelGGL(adj_final_kernel, dim3(1), dim3(256), 0, stream, partial, nblocks, out);
   return hipGetLastError();
 }
 

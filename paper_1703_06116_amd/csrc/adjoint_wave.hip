@@ -21,12 +21,17 @@
 //
 // Per beam: the adjoint of its final contribution (c from an LDL-type
 // elimination of Z, with G = -Z^-1/2 + u u^T/(2 eps), u = Z^-1 P), then the
-// segments last to first: each segment is run forward from its checkpoint
-// with every interval's start going to the wave's slot store, and the
-// intervals are swept in reverse through their legs (adjoint.h): the trial
-// step, the shortened step to the hop time and the weight update, with the
-// hop time t = (E - Lam)/(Lam' - Lam) carrying the adjoint of the time left.
-// The stage inputs of the step being swept sit in LDS.
+// segments last to first.  Three kernels, one wavefront per beam over a chunk
+// of beams: the seed; per segment the replay from its checkpoint, which
+// writes each interval's stage records (what the vector-Jacobian products
+// read of a stage value: q1, p1, the momentum component of P and the column
+// d of Z) and whether the interval has a hop; and the reverse sweep, which
+// takes the intervals without a hop from their records alone (four stage
+// products per RK4 step) and the few with one out of line, through their
+// legs (adjoint.h): the trial step, the shortened step to the hop time and
+// the weight update, with the hop time t = (E - Lam)/(Lam' - Lam) carrying
+// the adjoint of the time left.  Splitting the phases gives each its own
+// register allocation.
 #include "adjoint.h"
 #include "wave.h"
 
@@ -34,7 +39,6 @@ namespace shgb {
 
 constexpr int kAwLanes = 64;   // one beam per wavefront
 constexpr int kAwWaves = 4;    // waves per block
-constexpr int64_t kAwMaxBlocks = 512;
 
 template <int D>
 struct AwT {
@@ -44,18 +48,34 @@ struct AwT {
   using Lds = PgLds<D, double>;
   static constexpr int M = 2 * D;
   static constexpr int NF = C::NG * kGrpN + 2 * C::NXP + 2;   // doubles per lane of a Y
-  static constexpr int NSLOT = NF + 3;                        // + E, comp, nhop
-  // stage inputs 1..3 of the step being swept, per lane; the seed's
-  // elimination reuses the space
+  static constexpr int NSLOT = NF + 4;                        // + E, comp, nhop, hop flag
+  // What the vector-Jacobian product reads of a stage value: q1, p1 and the
+  // momentum component of P (the centre enters through them only), and the
+  // column d of Z: Zrp_a0 and Zpp_0a for a < d (the Hessian enters only
+  // through dL/dH00).  One record per RK4 stage.
+  static constexpr int SR = 3 + 4 * D;
+  static constexpr int RREC = 4 * SR;                         // one RK4 step
+  // full stage inputs 1..3 of a step with a hop (the step-size adjoint needs
+  // the slopes), per lane, in the wave's workspace
   static constexpr int REC = 3 * NF * kAwLanes;
+  // the seed's elimination of [Z | I | P], in LDS
   static constexpr int ELIM = M * (2 * M + 2) * 2;
-  static constexpr int SCR = REC > ELIM ? REC : ELIM;
+  // the wave's exchange buffer with the out-of-line hop intervals: two
+  // states, the hop scalars and the parameter adjoints
+  static constexpr int IO = 2 * NF * kAwLanes + 16;
 };
+
+// Doubles per beam of the buffers of an interval with a hop: its full stage
+// inputs, its stage records and the exchange buffer io.
+template <int D>
+__host__ __device__ inline int64_t aw_gen_doubles() {
+  return AwT<D>::REC + AwT<D>::RREC + AwT<D>::IO;
+}
 
 template <int D>
 struct AwLds {
   typename AwT<D>::Lds x;
-  double scr[AwT<D>::SCR];
+  double scr[AwT<D>::ELIM];
 };
 
 // ---- per-lane state helpers -------------------------------------------------
@@ -182,16 +202,39 @@ __device__ inline void aw_rhs(const DevModel &md, int l, const typename AwT<D>::
   wave_lds_sync();
 }
 
+// The stage record of stage value y (AwT::SR doubles at q): q1, p1, P_p1
+// from the lanes that own them, then Zrp_a0 and Zpp_0a of group (0, a) from
+// lane a, one row of d values per part.
+template <int D>
+__device__ inline void aw_record(const typename AwT<D>::Cx &cx, const typename AwT<D>::Y &y, double *q) {
+  const int r = cx.r;
+  if (r == 0) q[0] = y.x[0];
+  if (r == D) {
+    q[1] = y.x[0];
+    q[2] = y.p[0];
+  }
+  if (r < D) {
+    q[3 + r] = y.g[0].v[kBaR];
+    q[3 + D + r] = y.g[0].v[kBaI];
+    q[3 + 2 * D + r] = y.g[0].v[kPpR];
+    q[3 + 3 * D + r] = y.g[0].v[kPpI];
+  }
+}
+
 // One classical RK4 step of size h on component l, folded as the FP64
-// stepping kernel folds it; stage inputs 1..3 go to rec (per lane) when given.
+// stepping kernel folds it; stage inputs 1..3 go to rec (per lane) and the
+// four stage records to rr, when given.
 template <int D>
 __device__ inline void aw_rk4(const DevModel &md, int l, const typename AwT<D>::Cx &cx, const typename AwT<D>::Y &y,
-                              double h, typename AwT<D>::Y &out, typename AwT<D>::Lds &s, double *rec) {
+                              double h, typename AwT<D>::Y &out, typename AwT<D>::Lds &s, double *rec,
+                              double *rr = nullptr) {
   using C = typename AwT<D>::C;
   typename AwT<D>::Y ys = y;
   const double h6 = h * (1.0 / 6.0);
+#pragma nounroll
   for (int st = 0; st < 4; ++st) {
     if (rec && st > 0) aw_put<D>(ys, rec + (st - 1) * AwT<D>::NF * kAwLanes, cx.r);
+    if (rr) aw_record<D>(cx, ys, rr + st * AwT<D>::SR);
     pg_publish(cx, ys, s);
     const StageCoef<double> sc = aw_coef<D>(md, l, s);
     const double c = st == 2 ? h : 0.5 * h;
@@ -223,33 +266,36 @@ __device__ inline void aw_rk4(const DevModel &md, int l, const typename AwT<D>::
   }
 }
 
-// Vector-Jacobian product of the right-hand side at stage value y: yb gets
-// g^T d(rhs)/dy, th (replicated over the lanes) gets g^T d(rhs)/d(A, B, C, D).
+// Vector-Jacobian product of the right-hand side at the stage value whose
+// record is q: yb gets g^T d(rhs)/dy, th (replicated over the lanes) gets
+// g^T d(rhs)/d(A, B, C, D).
 template <int D>
-__device__ inline void aw_vjp(const DevModel &md, int l, const typename AwT<D>::Cx &cx, const typename AwT<D>::Y &y,
+__device__ inline void aw_vjp(const DevModel &md, int l, const typename AwT<D>::Cx &cx, const double *q,
                               const typename AwT<D>::Y &g, typename AwT<D>::Y &yb, double th[4],
                               typename AwT<D>::Lds &s) {
   using C = typename AwT<D>::C;
   const int lane = cx.r;
-  const double q0 = __shfl(y.x[0], 0, 64), p0 = __shfl(y.x[0], D, 64), Pp0 = __shfl(y.p[0], D, 64);
+  const double q0 = q[0], p0 = q[1], Pp0 = q[2];
   const Q1 k = qcle_q1(md, q0);
   const double im = md.inv_mass, lam = md.lam;
   const double sg = comp_sigma(l), bc = comp_bcoef(l), H00 = sg * k.s2;
-  // the Hessian part: the forward update of the exchanged adjoint, exchanged back
-  typename AwT<D>::Y gs;
-  aw_zero<D>(gs);
+  // the Hessian part: the forward update of the exchanged adjoint, exchanged
+  // back; the exchange is done in the writes to the exchange area and per
+  // group below (the coordinates of the exchange area are not read here)
 #pragma unroll
   for (int e = 0; e < C::NG; ++e) {
-    gs.g[e].v[kRrR] = g.g[e].v[kPpR];
-    gs.g[e].v[kRrI] = g.g[e].v[kPpI];
-    gs.g[e].v[kAbR] = g.g[e].v[kBaR];
-    gs.g[e].v[kAbI] = g.g[e].v[kBaI];
-    gs.g[e].v[kBaR] = g.g[e].v[kAbR];
-    gs.g[e].v[kBaI] = g.g[e].v[kAbI];
-    gs.g[e].v[kPpR] = g.g[e].v[kRrR];
-    gs.g[e].v[kPpI] = g.g[e].v[kRrI];
+    const int a = cx.a[e], b = cx.b[e];
+    if ((e + 1) * kAwLanes <= C::NGRP || a >= 0) {
+      const double *v = g.g[e].v;
+      s.rp[a][b] = Cx2<double>{v[kBaR], v[kBaI]};
+      s.rp[b][a] = Cx2<double>{v[kAbR], v[kAbI]};
+      s.pp[a][b] = Cx2<double>{v[kRrR], v[kRrI]};
+      s.pp[b][a] = Cx2<double>{v[kRrR], v[kRrI]};
+    }
   }
-  pg_publish(cx, gs, s);
+  wave_lds_sync();
+  pg_sums(cx, s);
+  wave_lds_sync();
   StageCoef<double> c0;
   c0.k = Q1T<double>{k.s, k.s1, k.s2, k.s3, k.d21};
   c0.im = im;
@@ -258,12 +304,13 @@ __device__ inline void aw_vjp(const DevModel &md, int l, const typename AwT<D>::
   c0.H00 = H00;
   c0.lam = lam;
   c0.B00 = 0.0;
-  double hb = 0.0;
 #pragma unroll
   for (int e = 0; e < C::NG; ++e) {
     const bool live = cx.a[e] >= 0;
+    const double *v = g.g[e].v;
+    const double gs[kGrpN] = {v[kPpR], v[kPpI], v[kBaR], v[kBaI], v[kAbR], v[kAbI], v[kRrR], v[kRrI]};
     double d[kGrpN];
-    grp_deriv<D, double>(live ? cx.a[e] : 0, live ? cx.b[e] : 0, c0, gs.g[e].v, s, d);
+    grp_deriv<D, double>(live ? cx.a[e] : 0, live ? cx.b[e] : 0, c0, gs, s, d);
     yb.g[e].v[kRrR] = live ? d[kPpR] : 0.0;
     yb.g[e].v[kRrI] = live ? d[kPpI] : 0.0;
     yb.g[e].v[kAbR] = live ? d[kBaR] : 0.0;
@@ -272,12 +319,14 @@ __device__ inline void aw_vjp(const DevModel &md, int l, const typename AwT<D>::
     yb.g[e].v[kBaI] = live ? d[kAbI] : 0.0;
     yb.g[e].v[kPpR] = live ? d[kRrR] : 0.0;
     yb.g[e].v[kPpI] = live ? d[kRrI] : 0.0;
-    // dL/dH00 = 2 sum_a G_a0 Z_a,d: groups (0, k) hold G_k0 (rr) with Z_k,d (Zrp_k0, slot ba)
-    // and G_d+k,0 (Zrp_0k, slot ab) with Z_d+k,d (Zpp_k0)
-    if (live && cx.a[e] == 0)
-      hb += g.g[e].v[kRrR] * y.g[e].v[kBaR] + g.g[e].v[kRrI] * y.g[e].v[kBaI] + g.g[e].v[kAbR] * y.g[e].v[kPpR] +
-            g.g[e].v[kAbI] * y.g[e].v[kPpI];
   }
+  // dL/dH00 = 2 sum_a G_a0 Z_a,d: group (0, a) (lane a, first slot) holds
+  // G_a0 (rr) with Z_a,d (Zrp_a0, slot ba) and G_d+a,0 (Zrp_0a, slot ab)
+  // with Z_d+a,d (Zpp_a0)
+  double hb = 0.0;
+  if (lane < D)
+    hb = g.g[0].v[kRrR] * q[3 + lane] + g.g[0].v[kRrI] * q[3 + D + lane] + g.g[0].v[kAbR] * q[3 + 2 * D + lane] +
+         g.g[0].v[kAbI] * q[3 + 3 * D + lane];
   wave_lds_sync();
   double Hb = 2.0 * aw_wave_sum(hb);
   const double gi00 = __shfl(g.g[0].v[kRrI], 0, 64);   // Im G_00: group (0, 0) is lane 0's first
@@ -317,11 +366,49 @@ __device__ inline void aw_vjp(const DevModel &md, int l, const typename AwT<D>::
   yb.Lam = 0.0;
 }
 
-// Reverse sweep of one RK4 step whose stage inputs 1..3 are in rec and whose
-// start is y: ybi = adjoint of the start, hb = adjoint of h (when need_h).
+// Reverse sweep of one RK4 step of size h from its four stage records rr
+// (no step-size adjoint): yb holds the adjoint of the step's end on entry
+// and that of its start on return.  The stages are swept last to first in a
+// loop that is not unrolled, so that one stage's work is live at a time:
+// stage i gets the cotangent a_i ybo + b_i Yb_(i+1) (Yb_(i+1) the previous
+// product), with (a, b) = (h/6, 0), (h/3, h), (h/3, h/2), (h/6, h/2) for
+// stages 4, 3, 2, 1.
+template <int D>
+__device__ inline void aw_rk4_rev_fast(const DevModel &md, int l, const typename AwT<D>::Cx &cx, const double *rr,
+                                       double h, typename AwT<D>::Y &yb, double th[4], typename AwT<D>::Lds &s) {
+  using C = typename AwT<D>::C;
+  using Y = typename AwT<D>::Y;
+  const double h6 = h * (1.0 / 6.0);
+  const Y ybo = yb;
+  Y Yb;
+  aw_zero<D>(Yb);
+#pragma nounroll
+  for (int st = 3; st >= 0; --st) {
+    const double ca = (st == 3 || st == 0) ? h6 : 2.0 * h6;
+    const double cb = st == 3 ? 0.0 : (st == 2 ? h : 0.5 * h);
+    Y g;
+#pragma unroll
+    for (int e = 0; e < C::NG; ++e)
+#pragma unroll
+      for (int j = 0; j < kGrpN; ++j) g.g[e].v[j] = ca * ybo.g[e].v[j] + cb * Yb.g[e].v[j];
+#pragma unroll
+    for (int j = 0; j < C::NXP; ++j) {
+      g.x[j] = ca * ybo.x[j] + cb * Yb.x[j];
+      g.p[j] = ca * ybo.p[j] + cb * Yb.p[j];
+    }
+    g.S = ca * ybo.S + cb * Yb.S;
+    g.Lam = ca * ybo.Lam + cb * Yb.Lam;
+    aw_vjp<D>(md, l, cx, rr + st * AwT<D>::SR, g, Yb, th, s);
+    aw_axpy<D>(yb, 1.0, Yb);
+  }
+}
+
+// Reverse sweep of one RK4 step whose stage records are in rr, whose stage
+// inputs 1..3 are in rec and whose start is y: ybi = adjoint of the start,
+// hb = adjoint of h (when need_h).
 template <int D>
 __device__ inline void aw_rk4_rev(const DevModel &md, int l, const typename AwT<D>::Cx &cx,
-                                  const typename AwT<D>::Y &y, const double *rec, double h,
+                                  const typename AwT<D>::Y &y, const double *rec, const double *rr, double h,
                                   const typename AwT<D>::Y &ybo, bool need_h, typename AwT<D>::Y &ybi, double &hb,
                                   double th[4], typename AwT<D>::Lds &s) {
   using Y = typename AwT<D>::Y;
@@ -333,8 +420,7 @@ __device__ inline void aw_rk4_rev(const DevModel &md, int l, const typename AwT<
   // stage 4 (input rec[2]), then 3, 2, 1; kb carries the adjoint of the previous stage's slope
   aw_zero<D>(g);
   aw_axpy<D>(g, h6, ybo);
-  aw_get<D>(Ys, rec + 2 * AwT<D>::NF * kAwLanes, lane);
-  aw_vjp<D>(md, l, cx, Ys, g, Yb, th, s);
+  aw_vjp<D>(md, l, cx, rr + 3 * AwT<D>::SR, g, Yb, th, s);
   aw_axpy<D>(ybi, 1.0, Yb);
   double kdot = 0.0;
   if (need_h) {
@@ -346,8 +432,7 @@ __device__ inline void aw_rk4_rev(const DevModel &md, int l, const typename AwT<
   aw_zero<D>(g);
   aw_axpy<D>(g, 2.0 * h6, ybo);
   aw_axpy<D>(g, h, Yb);
-  aw_get<D>(Ys, rec + 1 * AwT<D>::NF * kAwLanes, lane);
-  aw_vjp<D>(md, l, cx, Ys, g, Yb, th, s);
+  aw_vjp<D>(md, l, cx, rr + 2 * AwT<D>::SR, g, Yb, th, s);
   aw_axpy<D>(ybi, 1.0, Yb);
   if (need_h) {
     Y k2;
@@ -358,8 +443,7 @@ __device__ inline void aw_rk4_rev(const DevModel &md, int l, const typename AwT<
   aw_zero<D>(g);
   aw_axpy<D>(g, 2.0 * h6, ybo);
   aw_axpy<D>(g, 0.5 * h, Yb);
-  aw_get<D>(Ys, rec, lane);
-  aw_vjp<D>(md, l, cx, Ys, g, Yb, th, s);
+  aw_vjp<D>(md, l, cx, rr + AwT<D>::SR, g, Yb, th, s);
   aw_axpy<D>(ybi, 1.0, Yb);
   if (need_h) {
     Y k1;
@@ -369,7 +453,7 @@ __device__ inline void aw_rk4_rev(const DevModel &md, int l, const typename AwT<
   aw_zero<D>(g);
   aw_axpy<D>(g, h6, ybo);
   aw_axpy<D>(g, 0.5 * h, Yb);
-  aw_vjp<D>(md, l, cx, y, g, Yb, th, s);
+  aw_vjp<D>(md, l, cx, rr, g, Yb, th, s);
   aw_axpy<D>(ybi, 1.0, Yb);
   if (need_h) {
     // ybo . (k1 + 2 k2 + 2 k3 + k4) / 6 = ybo . (out - y) / h with out recomputed
@@ -432,19 +516,96 @@ __device__ inline int aw_legs_general(const DevModel &md, const typename AwT<D>:
   }
 }
 
-// The whole interval: the trial step inline (most intervals have no hop),
-// the rest out of line.
+// Orders the wave's own global-memory writes before its later reads of the
+// same workspace (the exchange with the out-of-line parts, the replay's
+// records before the reverse sweep): a workgroup-scope fence waits for the
+// stores to complete.
+__device__ inline void aw_mem_sync() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup"); }
+
+// The exchange area of the calling wave, as one LDS array shared by the
+// replay and reverse kernels and the out-of-line parts they call (which then
+// address it as LDS, not through generic pointers).
 template <int D>
-__device__ inline void aw_interval(const DevModel &md, const typename AwT<D>::Cx &cx, typename AwT<D>::Y &y,
-                                   HopScalars &h, uint64_t gid, uint64_t seed, double dt, typename AwT<D>::Lds &s) {
-  typename AwT<D>::Y yt;
-  aw_rk4<D>(md, h.comp, cx, y, dt, yt, s, nullptr);
-  if (!(yt.Lam >= h.E)) {
-    y = yt;
-    return;
+__device__ inline typename AwT<D>::Lds &aw_lds() {
+  __shared__ typename AwT<D>::Lds lds_all[kAwWaves];
+  return lds_all[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
+}
+
+// The lane's pair groups: lane r owns groups r + 64 e (a <= b in row order).
+template <int D>
+__device__ inline typename AwT<D>::Cx aw_ctx(int lane) {
+  using C = typename AwT<D>::C;
+  typename AwT<D>::Cx cx;
+  cx.r = lane;
+#pragma unroll
+  for (int e = 0; e < C::NG; ++e) {
+    const int gi = lane + kAwLanes * e;
+    cx.a[e] = cx.b[e] = -1;
+    if (gi < C::NGRP) {
+      int a = 0, rem = gi;
+      while (rem >= D - a) { rem -= D - a; ++a; }
+      cx.a[e] = a;
+      cx.b[e] = a + rem;
+    }
   }
+  return cx;
+}
+
+// Makes the lane's group context opaque to the compiler at the top of an
+// interval, so that the exchange-area and workspace addresses derived from
+// it are formed again in each interval rather than held (and spilled) over
+// the whole kernel.
+template <int D>
+__device__ inline void aw_opaque(typename AwT<D>::Cx &cx) {
+  asm volatile("" : "+v"(cx.r));
+#pragma unroll
+  for (int e = 0; e < AwT<D>::C::NG; ++e) asm volatile("" : "+v"(cx.a[e]), "+v"(cx.b[e]));
+}
+
+// The out-of-line parts (an interval with a hop: a few in a thousand)
+// exchange their state with the calling loop through the beam's buffer io:
+// a state at io, a second one at io + NF 64, the hop scalars at io + 2 NF 64
+// and the parameter adjoints at io + 2 NF 64 + 8, so that the loop's
+// registers are not tied to memory.
+template <int D>
+__device__ inline void aw_put_h(const HopScalars &h, double *q, int lane) {
+  if (lane == 0) {
+    q[0] = h.logw;
+    q[1] = h.phre;
+    q[2] = h.phim;
+    q[3] = h.Lam;
+    q[4] = h.E;
+    q[5] = (double)h.comp;
+    q[6] = (double)h.nhop;
+  }
+}
+
+__device__ inline void aw_get_h(HopScalars &h, const double *q) {
+  h.logw = q[0];
+  h.phre = q[1];
+  h.phim = q[2];
+  h.Lam = q[3];
+  h.E = q[4];
+  h.comp = (int)q[5];
+  h.nhop = (uint32_t)q[6];
+}
+
+// An interval with a hop, forwards, from the state and hop scalars in io
+// (replaced by the interval's end).
+template <int D>
+__device__ __attribute__((noinline)) void aw_interval_hop(const DevModel &md, double *io, uint64_t gid,
+                                                          uint64_t seed, double dt) {
+  constexpr int NF = AwT<D>::NF;
+  const typename AwT<D>::Cx cx = aw_ctx<D>(threadIdx.x & 63);
+  typename AwT<D>::Y y;
+  HopScalars h;
+  aw_get<D>(y, io, cx.r);
+  aw_get_h(h, io + 2 * NF * kAwLanes);
   double rem;
-  aw_legs_general<D>(md, cx, y, h, gid, seed, dt, -1, rem, s);
+  aw_legs_general<D>(md, cx, y, h, gid, seed, dt, -1, rem, aw_lds<D>());
+  aw_put<D>(y, io, cx.r);
+  aw_put_h<D>(h, io + 2 * NF * kAwLanes, cx.r);
+  aw_mem_sync();
 }
 
 // Reverse sweep of one interval starting at (ys, hs); yb: adjoint of its end
@@ -453,18 +614,18 @@ template <int D>
 __device__ inline void aw_interval_rev_general(const DevModel &md, const typename AwT<D>::Cx &cx,
                                        const typename AwT<D>::Y &ys, const HopScalars &hs, uint64_t gid,
                                        uint64_t seed, double dt, typename AwT<D>::Y &yb, double logwb, double th[4],
-                                       AwLds<D> &lds) {
+                                       typename AwT<D>::Lds &s, double *rec, double *rr) {
   using Y = typename AwT<D>::Y;
   Y y = ys;
   HopScalars h = hs;
   double rem;
-  const int L = aw_legs_general<D>(md, cx, y, h, gid, seed, dt, -1, rem, lds.x);
+  const int L = aw_legs_general<D>(md, cx, y, h, gid, seed, dt, -1, rem, s);
   double remb = 0.0;
   for (int j = L - 1; j >= 0; --j) {
     if (j > 0 || L > 1) {
       y = ys;
       h = hs;
-      aw_legs_general<D>(md, cx, y, h, gid, seed, dt, j, rem, lds.x);
+      aw_legs_general<D>(md, cx, y, h, gid, seed, dt, j, rem, s);
     } else {
       y = ys;
       h = hs;
@@ -472,11 +633,12 @@ __device__ inline void aw_interval_rev_general(const DevModel &md, const typenam
     }
     const int l = h.comp;
     Y yt, ybi;
-    aw_rk4<D>(md, l, cx, y, rem, yt, lds.x, lds.scr);
+    aw_rk4<D>(md, l, cx, y, rem, yt, s, rec, rr);
+    aw_mem_sync();
     const bool need = j > 0;
     double hb = 0.0, rb = 0.0;
     if (j >= SHGB_HOP_CAP || !(yt.Lam >= h.E)) {
-      aw_rk4_rev<D>(md, l, cx, y, lds.scr, rem, yb, need, ybi, hb, th, lds.x);
+      aw_rk4_rev<D>(md, l, cx, y, rec, rr, rem, yb, need, ybi, hb, th, s);
       rb = hb;
     } else {
       const double t = (h.E <= y.Lam) ? 0.0 : (h.E - y.Lam) / (yt.Lam - y.Lam);
@@ -487,8 +649,9 @@ __device__ inline void aw_interval_rev_general(const DevModel &md, const typenam
         rb = (1.0 - t) * remb;
         const double lamt = yt.Lam, lam0 = y.Lam;
         Y yp;
-        aw_rk4<D>(md, l, cx, y, t * rem, yp, lds.x, lds.scr);
-        aw_rk4_rev<D>(md, l, cx, y, lds.scr, t * rem, ym, true, ybi, hb, th, lds.x);
+        aw_rk4<D>(md, l, cx, y, t * rem, yp, s, rec, rr);
+        aw_mem_sync();
+        aw_rk4_rev<D>(md, l, cx, y, rec, rr, t * rem, ym, true, ybi, hb, th, s);
         tb += rem * hb;
         rb += t * hb;
         const double den = lamt - lam0;
@@ -496,14 +659,15 @@ __device__ inline void aw_interval_rev_general(const DevModel &md, const typenam
         Y e;
         aw_zero<D>(e);
         e.Lam = -tb * t / den;
-        aw_rk4<D>(md, l, cx, y, rem, yt, lds.x, lds.scr);   // the trial step's stage inputs again
+        aw_rk4<D>(md, l, cx, y, rem, yt, s, rec, rr);   // the trial step's stage inputs again
+        aw_mem_sync();
         Y yb2;
         double hb2 = 0.0;
-        aw_rk4_rev<D>(md, l, cx, y, lds.scr, rem, e, need, yb2, hb2, th, lds.x);
+        aw_rk4_rev<D>(md, l, cx, y, rec, rr, rem, e, need, yb2, hb2, th, s);
         aw_axpy<D>(ybi, 1.0, yb2);
         rb += hb2;
       } else if (t >= 1.0) {
-        aw_rk4_rev<D>(md, l, cx, y, lds.scr, rem, ym, need, ybi, hb, th, lds.x);
+        aw_rk4_rev<D>(md, l, cx, y, rec, rr, rem, ym, need, ybi, hb, th, s);
         rb = hb;
       } else {
         ybi = ym;
@@ -515,23 +679,17 @@ __device__ inline void aw_interval_rev_general(const DevModel &md, const typenam
   }
 }
 
-// An interval without a hop (the trial step ends it) swept inline; the
-// others by the general sweep.
-template <int D>
-__device__ inline void aw_interval_rev(const DevModel &md, const typename AwT<D>::Cx &cx,
-                                       const typename AwT<D>::Y &ys, const HopScalars &hs, uint64_t gid,
-                                       uint64_t seed, double dt, typename AwT<D>::Y &yb, double logwb, double th[4],
-                                       AwLds<D> &lds) {
-  typename AwT<D>::Y yt;
-  aw_rk4<D>(md, hs.comp, cx, ys, dt, yt, lds.x, lds.scr);
-  if (!(yt.Lam >= hs.E)) {
-    typename AwT<D>::Y ybi;
-    double hb;
-    aw_rk4_rev<D>(md, hs.comp, cx, ys, lds.scr, dt, yb, false, ybi, hb, th, lds.x);
-    yb = ybi;
-    return;
-  }
-  aw_interval_rev_general<D>(md, cx, ys, hs, gid, seed, dt, yb, logwb, th, lds);
+// Hop scalars of a beam at a checkpoint.
+__device__ inline HopScalars aw_ckpt_h(const double *cf, const int32_t *ci, int64_t tro, int64_t n, int64_t b) {
+  HopScalars hs;
+  hs.logw = 0.0;
+  hs.phre = 1.0;
+  hs.phim = 0.0;
+  hs.Lam = 0.0;
+  hs.E = cf[(tro + kRowE) * n + b];
+  hs.comp = ci[b];
+  hs.nhop = (uint32_t)ci[n + b];
+  return hs;
 }
 
 // Load one beam's state (trajectory rows of f with leading dimension ld,
@@ -561,6 +719,44 @@ __device__ inline void aw_load(const typename AwT<D>::Cx &cx, const double *f, c
   }
   y.S = sc[kRowS * ld + b];
   y.Lam = sc[kRowLam * ld + b];
+}
+
+// Reverse sweep of interval i of a segment that has a hop: its start is
+// found again by running the segment from its checkpoint (cf, ci; the beam's
+// column b), the adjoint of its end is at io + NF 64 (replaced by that of its
+// start), the parameter adjoints it adds go to io + 2 NF 64 + 8; rec and rr
+// hold the stage values of one step.
+template <int D>
+__device__ __attribute__((noinline)) void aw_interval_rev_hop(const DevModel &md, const double *cf, const int32_t *ci,
+                                                              int64_t n, int64_t b, int i, double *io, uint64_t gid,
+                                                              uint64_t seed, double dt, double logwb, double *rec,
+                                                              double *rr) {
+  using Y = typename AwT<D>::Y;
+  constexpr int NF = AwT<D>::NF;
+  constexpr int M = 2 * D;
+  const typename AwT<D>::Cx cx = aw_ctx<D>(threadIdx.x & 63);
+  typename AwT<D>::Lds &s = aw_lds<D>();
+  const int64_t tro = (int64_t)(2 * M + M * (M + 1));
+  Y ys, yb;
+  aw_load<D>(cx, cf, cf + tro * n, n, b, ys);
+  HopScalars hs = aw_ckpt_h(cf, ci, tro, n, b);
+  for (int k = 0; k < i; ++k) {
+    Y yt;
+    aw_rk4<D>(md, hs.comp, cx, ys, dt, yt, s, nullptr);
+    if (!(yt.Lam >= hs.E)) {
+      ys = yt;
+    } else {
+      double rem;
+      aw_legs_general<D>(md, cx, ys, hs, gid, seed, dt, -1, rem, s);
+    }
+  }
+  aw_get<D>(yb, io + NF * kAwLanes, cx.r);
+  double th[4] = {0.0, 0.0, 0.0, 0.0};
+  aw_interval_rev_general<D>(md, cx, ys, hs, gid, seed, dt, yb, logwb, th, s, rec, rr);
+  aw_put<D>(yb, io + NF * kAwLanes, cx.r);
+  if (cx.r == 0)
+    for (int k = 0; k < 4; ++k) io[2 * NF * kAwLanes + 8 + k] = th[k];
+  aw_mem_sync();
 }
 
 // Adjoint of one beam's contribution Re(w c) (the populations' per-beam term):
@@ -670,115 +866,160 @@ __device__ inline double aw_seed(const DevModel &md, const typename AwT<D>::Cx &
   return wc.re;
 }
 
+// ---- kernels -----------------------------------------------------------------
+// One wavefront per beam, kAwWaves per block, over a chunk of beams
+// [b0, b0 + nb); per beam of the chunk (index w): its row of kAdjVals
+// doubles in bsc (the parameter adjoints dA, dB, dC, dD, that of p_mean,
+// the objective, the adjoint of logw), its adjoint state in ybuf, the stage
+// records of the current segment in recs and the buffers of an interval with
+// a hop in gen.
+constexpr int kBscLogwb = 6;
+
 template <int D>
-int64_t aw_blocks(int64_t n) {
-  int64_t b = (n + kAwWaves - 1) / kAwWaves;
-  if (b < 1) b = 1;
-  return b < kAwMaxBlocks ? b : kAwMaxBlocks;
+__global__ void __launch_bounds__(kAwLanes * kAwWaves)
+aw_seed_kernel(DevModel md, const double *__restrict__ fin, const int32_t *__restrict__ fcomp, int64_t ld,
+               int64_t b0, int64_t nb, const double *__restrict__ cot, double inv_ntraj, double *__restrict__ ybuf,
+               double *__restrict__ bsc) {
+  constexpr int M = 2 * D;
+  __shared__ AwLds<D> lds_all[kAwWaves];
+  const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t w = (int64_t)blockIdx.x * kAwWaves + wid;
+  if (w >= nb) return;   // uniform over the wave
+  AwLds<D> &lds = lds_all[wid];
+  const typename AwT<D>::Cx cx = aw_ctx<D>(lane);
+  pg_fill_const<D, kAwLanes, double>(lane, md.bath_k, lds.x);
+  const int64_t b = b0 + w;
+  const int64_t tro = (int64_t)(2 * M + M * (M + 1));
+  typename AwT<D>::Y y, yb;
+  aw_load<D>(cx, fin, fin + tro * ld, ld, b, y);
+  const double *fs = fin + tro * ld;
+  const int l = fcomp[b];
+  const cd wgt = {cot[2 * l] * inv_ntraj, -cot[2 * l + 1] * inv_ntraj};
+  double logwb;
+  const double val = aw_seed<D>(md, cx, y, fs[kRowLogw * ld + b], {fs[kRowPhre * ld + b], fs[kRowPhim * ld + b]},
+                                {fs[kRowAre * ld + b], fs[kRowAim * ld + b]}, wgt, yb, logwb, lds);
+  aw_put<D>(yb, ybuf + w * AwT<D>::NF * kAwLanes, lane);
+  if (lane < kAdjVals) {
+    double v = 0.0;
+    if (lane == 5) v = val;
+    if (lane == kBscLogwb) v = logwb;
+    bsc[b * kAdjVals + lane] = v;
+  }
+}
+
+// Replay of segment [start, start + len) from its checkpoint: each interval's
+// trial-step stage records, its component and whether it has a hop.
+template <int D>
+__global__ void __launch_bounds__(kAwLanes * kAwWaves)
+aw_replay_kernel(DevModel md, const double *__restrict__ cf, const int32_t *__restrict__ ci, int64_t n, int len,
+                 int every, int64_t b0, int64_t nb, uint64_t gid0, uint64_t seed, double dt, double *__restrict__ recs,
+                 double *__restrict__ gen) {
+  using Y = typename AwT<D>::Y;
+  constexpr int M = 2 * D, NF = AwT<D>::NF, RS = AwT<D>::RREC + 2;
+  const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t w = (int64_t)blockIdx.x * kAwWaves + wid;
+  if (w >= nb) return;
+  typename AwT<D>::Lds &s = aw_lds<D>();
+  typename AwT<D>::Cx cx = aw_ctx<D>(lane);
+  pg_fill_const<D, kAwLanes, double>(lane, md.bath_k, s);
+  const int64_t b = b0 + w;
+  const uint64_t gid = gid0 + (uint64_t)b;
+  const int64_t tro = (int64_t)(2 * M + M * (M + 1));
+  double *rw = recs + w * (int64_t)every * RS;
+  double *io = gen + w * aw_gen_doubles<D>() + AwT<D>::REC + AwT<D>::RREC;
+  Y ys;
+  aw_load<D>(cx, cf, cf + tro * n, n, b, ys);
+  HopScalars hs = aw_ckpt_h(cf, ci, tro, n, b);
+  for (int i = 0; i < len; ++i) {
+    aw_opaque<D>(cx);
+    double *r = rw + (int64_t)i * RS;
+    Y yt;
+    aw_rk4<D>(md, hs.comp, cx, ys, dt, yt, s, nullptr, r);
+    const bool hop = yt.Lam >= hs.E;
+    if (lane == 0) {
+      r[AwT<D>::RREC] = (double)hs.comp;
+      r[AwT<D>::RREC + 1] = hop ? 1.0 : 0.0;
+    }
+    if (!hop) {
+      ys = yt;
+    } else {
+      aw_put<D>(ys, io, lane);
+      aw_put_h<D>(hs, io + 2 * NF * kAwLanes, lane);
+      aw_mem_sync();
+      aw_interval_hop<D>(md, io, gid, seed, dt);
+      aw_get<D>(ys, io, lane);
+      aw_get_h(hs, io + 2 * NF * kAwLanes);
+    }
+  }
+}
+
+// Reverse sweep of the segment from its records; the adjoint state in ybuf
+// and the beam's row of bsc are read and written back.  After the first
+// segment (start 0) the adjoint of the initial p1 goes to the row.
+template <int D>
+__global__ void __launch_bounds__(kAwLanes * kAwWaves)
+aw_reverse_kernel(DevModel md, const double *__restrict__ cf, const int32_t *__restrict__ ci, int64_t n, int len,
+                  int every, int first, int64_t b0, int64_t nb, uint64_t gid0, uint64_t seed, double dt,
+                  const double *__restrict__ recs, double *__restrict__ ybuf, double *__restrict__ bsc,
+                  double *__restrict__ gen) {
+  using Y = typename AwT<D>::Y;
+  constexpr int NF = AwT<D>::NF, RS = AwT<D>::RREC + 2;
+  const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t w = (int64_t)blockIdx.x * kAwWaves + wid;
+  if (w >= nb) return;
+  typename AwT<D>::Lds &s = aw_lds<D>();
+  typename AwT<D>::Cx cx = aw_ctx<D>(lane);
+  pg_fill_const<D, kAwLanes, double>(lane, md.bath_k, s);
+  const int64_t b = b0 + w;
+  const uint64_t gid = gid0 + (uint64_t)b;
+  const double *rw = recs + w * (int64_t)every * RS;
+  double *g = gen + w * aw_gen_doubles<D>();
+  double *io = g + AwT<D>::REC + AwT<D>::RREC;
+  double *row = bsc + b * kAdjVals;
+  Y yb;
+  aw_get<D>(yb, ybuf + w * NF * kAwLanes, lane);
+  double th[4] = {row[0], row[1], row[2], row[3]};
+  const double logwb = row[kBscLogwb];
+  for (int i = len - 1; i >= 0; --i) {
+    aw_opaque<D>(cx);
+    const double *r = rw + (int64_t)i * RS;
+    if (r[AwT<D>::RREC + 1] == 0.0) {
+      aw_rk4_rev_fast<D>(md, (int)r[AwT<D>::RREC], cx, r, dt, yb, th, s);
+    } else {
+      aw_put<D>(yb, io + NF * kAwLanes, lane);
+      aw_mem_sync();
+      aw_interval_rev_hop<D>(md, cf, ci, n, b, i, io, gid, seed, dt, logwb, g, g + AwT<D>::REC);
+      aw_get<D>(yb, io + NF * kAwLanes, lane);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) th[k] += io[2 * NF * kAwLanes + 8 + k];
+    }
+  }
+  aw_put<D>(yb, ybuf + w * NF * kAwLanes, lane);
+  const double pb = __shfl(yb.x[0], D, 64);   // adjoint of p1 at the segment's start
+  if (lane == 0) {
+    row[0] = th[0];
+    row[1] = th[1];
+    row[2] = th[2];
+    row[3] = th[3];
+    if (first) row[4] = pb;
+  }
+}
+
+// Chunk of beams per pass: bounds the workspace (the records of one segment
+// for every beam of the chunk) while keeping many wavefronts per SIMD.
+constexpr int64_t kAwChunk = 8192;
+
+template <int D>
+int64_t aw_chunk(int64_t n) {
+  return n < kAwChunk ? (n < 1 ? 1 : n) : kAwChunk;
 }
 
 template <int D>
 int64_t aw_workspace_bytes(int64_t n, int every) {
-  const int64_t waves = aw_blocks<D>(n) * kAwWaves;
-  return waves * (int64_t)every * AwT<D>::NSLOT * kAwLanes * 8 + aw_blocks<D>(n) * kAdjVals * 8;
-}
-
-template <int D>
-__global__ void __launch_bounds__(kAwLanes * kAwWaves)
-adjoint_wave_kernel(DevModel md, const double *__restrict__ fin, const int32_t *__restrict__ fcomp, int64_t n,
-                    int64_t ld, uint64_t gid0, const char *__restrict__ ckpt, CkptLayout cl, int nsteps, double dt,
-                    uint64_t seed, int every, const double *__restrict__ cot, double inv_ntraj,
-                    double *__restrict__ slots, double *__restrict__ partial) {
-  using C = typename AwT<D>::C;
-  using Y = typename AwT<D>::Y;
-  constexpr int M = 2 * D;
-  __shared__ AwLds<D> lds_all[kAwWaves];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  AwLds<D> &lds = lds_all[wid];
-  const int64_t nwaves = (int64_t)gridDim.x * kAwWaves;
-  const int64_t wv = (int64_t)blockIdx.x * kAwWaves + wid;
-  double *myslots = slots + wv * (int64_t)every * AwT<D>::NSLOT * kAwLanes;
-  typename AwT<D>::Cx cx;
-  cx.r = lane;
-#pragma unroll
-  for (int e = 0; e < C::NG; ++e) {
-    const int gi = lane + kAwLanes * e;
-    cx.a[e] = cx.b[e] = -1;
-    if (gi < C::NGRP) {
-      int a = 0, rem = gi;
-      while (rem >= D - a) { rem -= D - a; ++a; }
-      cx.a[e] = a;
-      cx.b[e] = a + rem;
-    }
-  }
-  pg_fill_const<D, kAwLanes, double>(lane, md.bath_k, lds.x);
-  const int64_t tro = (int64_t)(2 * M + M * (M + 1));   // trajectory rows
-  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t b = wv; b < n; b += nwaves) {   // uniform across the wave
-    Y y, yb;
-    aw_load<D>(cx, fin, fin + tro * ld, ld, b, y);
-    const double *fs = fin + tro * ld;
-    const int l = fcomp[b];
-    const cd w = {cot[2 * l] * inv_ntraj, -cot[2 * l + 1] * inv_ntraj};
-    double logwb;
-    const double val = aw_seed<D>(md, cx, y, fs[kRowLogw * ld + b], {fs[kRowPhre * ld + b], fs[kRowPhim * ld + b]},
-                                  {fs[kRowAre * ld + b], fs[kRowAim * ld + b]}, w, yb, logwb, lds);
-    double th[4] = {0.0, 0.0, 0.0, 0.0};
-    const uint64_t gid = gid0 + (uint64_t)b;
-    for (int c = cl.n_ckpt - 1; c >= 0; --c) {
-      const int start = c * every, len = nsteps - start < every ? nsteps - start : every;
-      const char *base = ckpt + (int64_t)c * cl.stride_bytes;
-      const double *cf = (const double *)base;
-      const int32_t *ci = (const int32_t *)(base + cl.rows * n * 8);
-      Y ys;
-      aw_load<D>(cx, cf, cf + tro * n, n, b, ys);
-      HopScalars hs;
-      hs.logw = 0.0;
-      hs.phre = 1.0;
-      hs.phim = 0.0;
-      hs.Lam = 0.0;
-      hs.E = cf[(tro + kRowE) * n + b];
-      hs.comp = ci[b];
-      hs.nhop = (uint32_t)ci[n + b];
-      for (int i = 0; i < len; ++i) {
-        double *sl = myslots + (int64_t)i * AwT<D>::NSLOT * kAwLanes;
-        aw_put<D>(ys, sl, lane);
-        if (lane == 0) {
-          sl[AwT<D>::NF * kAwLanes] = hs.E;
-          sl[(AwT<D>::NF + 1) * kAwLanes] = (double)hs.comp;
-          sl[(AwT<D>::NF + 2) * kAwLanes] = (double)hs.nhop;
-        }
-        aw_interval<D>(md, cx, ys, hs, gid, seed, dt, lds.x);
-      }
-      for (int i = len - 1; i >= 0; --i) {
-        const double *sl = myslots + (int64_t)i * AwT<D>::NSLOT * kAwLanes;
-        aw_get<D>(ys, sl, lane);
-        hs.E = sl[AwT<D>::NF * kAwLanes];
-        hs.comp = (int)sl[(AwT<D>::NF + 1) * kAwLanes];
-        hs.nhop = (uint32_t)sl[(AwT<D>::NF + 2) * kAwLanes];
-        aw_interval_rev<D>(md, cx, ys, hs, gid, seed, dt, yb, logwb, th, lds);
-      }
-    }
-    if (lane == 0) {
-      acc[0] += th[0];
-      acc[1] += th[1];
-      acc[2] += th[2];
-      acc[3] += th[3];
-      acc[5] += val;
-    }
-    const double pb = __shfl(yb.x[0], D, 64);   // adjoint of the initial p1
-    if (lane == 0) acc[4] += pb;
-  }
-  __shared__ double red[kAwWaves][6];
-  if (lane == 0)
-    for (int k = 0; k < 6; ++k) red[wid][k] = acc[k];
-  __syncthreads();
-  if (threadIdx.x < kAdjVals) {
-    double s = 0.0;
-    if (threadIdx.x < 6)
-      for (int w2 = 0; w2 < kAwWaves; ++w2) s += red[w2][threadIdx.x];
-    partial[(int64_t)blockIdx.x * kAdjVals + threadIdx.x] = s;
-  }
+  const int64_t c = aw_chunk<D>(n);
+  const int64_t dbl = c * ((int64_t)every * (AwT<D>::RREC + 2) + AwT<D>::NF * kAwLanes + aw_gen_doubles<D>()) +
+                      (n < 1 ? 1 : n) * kAdjVals;
+  return dbl * 8;
 }
 
 hipError_t launch_adj_final(const double *, int64_t, double *, hipStream_t);
@@ -787,14 +1028,30 @@ template <int D>
 hipError_t launch_aw(const DevModel &md, const shgb_state &fin, const void *ckpt, int nsteps, double dt, uint64_t seed,
                      int every, const double *cot, int64_t n_traj, double *out, void *work, hipStream_t stream) {
   const int64_t n = fin.n_beams;
-  const int64_t blocks = aw_blocks<D>(n);
-  double *slots = (double *)work;
-  double *partial = slots + blocks * kAwWaves * (int64_t)every * AwT<D>::NSLOT * kAwLanes;
+  const int64_t chunk = aw_chunk<D>(n);
   const CkptLayout cl = ckpt_layout(n, 2 * D, nsteps, every);
-  hipLaunchKernelGGL(adjoint_wave_kernel<D>, dim3((unsigned)blocks), dim3(kAwLanes * kAwWaves), 0, stream, md,
-                     fin.f64, fin.comp, n, fin.ld, fin.beam_id_offset, (const char *)ckpt, cl, nsteps, dt, seed, every,
-                     cot, 1.0 / (double)n_traj, slots, partial);
-  return launch_adj_final(partial, blocks, out, stream);
+  double *recs = (double *)work;
+  double *ybuf = recs + chunk * (int64_t)every * (AwT<D>::RREC + 2);
+  double *gen = ybuf + chunk * AwT<D>::NF * kAwLanes;
+  double *bsc = gen + chunk * aw_gen_doubles<D>();
+  const double inv_ntraj = 1.0 / (double)n_traj;
+  for (int64_t b0 = 0; b0 < n; b0 += chunk) {
+    const int64_t nb = n - b0 < chunk ? n - b0 : chunk;
+    const unsigned blocks = (unsigned)((nb + kAwWaves - 1) / kAwWaves);
+    hipLaunchKernelGGL(aw_seed_kernel<D>, dim3(blocks), dim3(kAwLanes * kAwWaves), 0, stream, md, fin.f64, fin.comp,
+                       fin.ld, b0, nb, cot, inv_ntraj, ybuf, bsc);
+    for (int c = cl.n_ckpt - 1; c >= 0; --c) {
+      const int start = c * every, len = nsteps - start < every ? nsteps - start : every;
+      const char *base = (const char *)ckpt + (int64_t)c * cl.stride_bytes;
+      const double *cf = (const double *)base;
+      const int32_t *ci = (const int32_t *)(base + cl.rows * n * 8);
+      hipLaunchKernelGGL(aw_replay_kernel<D>, dim3(blocks), dim3(kAwLanes * kAwWaves), 0, stream, md, cf, ci, n, len,
+                         every, b0, nb, fin.beam_id_offset, seed, dt, recs, gen);
+      hipLaunchKernelGGL(aw_reverse_kernel<D>, dim3(blocks), dim3(kAwLanes * kAwWaves), 0, stream, md, cf, ci, n,
+                         len, every, c == 0 ? 1 : 0, b0, nb, fin.beam_id_offset, seed, dt, recs, ybuf, bsc, gen);
+    }
+  }
+  return launch_adj_final(bsc, n, out, stream);   // n = 0: zeros
 }
 
 bool adjoint_wave_supported(int d) { return d == 2 || d == 3 || d == 4 || d == 12; }
