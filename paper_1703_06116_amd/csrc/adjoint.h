@@ -139,6 +139,16 @@ __host__ __device__ inline double q1_pullback_rev(const DevModel &md, double q, 
 // next leg with rem (1 - theta) on the new component).
 enum LegKind : int { kLegAccept = 0, kLegPartial = 1, kLegEnd = 2, kLegNow = 3 };
 
+// Stage records of the reverse sweep of a d > 1 beam: what the
+// vector-Jacobian product of the right-hand side reads of a stage value (the
+// centre enters only through q1, p1 and the momentum component of P, the
+// Hessian only through dL/dH00 = 2 sum_a G_a0 Z_a,d): per RK4 stage
+// q1, p1, P_p1, then Re Zrp_a0, Im Zrp_a0, Re Zpp_0a, Im Zpp_0a for
+// a = 0 .. d-1 (one row of d values each); per interval the four stages'
+// records, the component and whether the interval has a hop (1.0) or not.
+__host__ __device__ constexpr int adj_stage_rec(int d) { return 3 + 4 * d; }
+__host__ __device__ constexpr int adj_interval_rec(int d) { return 4 * adj_stage_rec(d) + 2; }
+
 // Per-block partial sums of the reverse kernels: dA, dB, dC, dD, dp_mean, the
 // objective, two unused.
 constexpr int kAdjVals = 8;

@@ -21,18 +21,19 @@
 //
 // Per beam: the adjoint of its final contribution (c from an LDL-type
 // elimination of Z, with G = -Z^-1/2 + u u^T/(2 eps), u = Z^-1 P), then the
-// segments last to first.  Three kernels, one wavefront per beam over a chunk
-// of beams: the seed; per segment the replay from its checkpoint, which
-// writes each interval's stage records (what the vector-Jacobian products
-// read of a stage value: q1, p1, the momentum component of P and the column
-// d of Z) and whether the interval has a hop; and the reverse sweep, which
-// takes the intervals without a hop from their records alone (four stage
-// products per RK4 step) and the few with one out of line, through their
-// legs (adjoint.h): the trial step, the shortened step to the hop time and
-// the weight update, with the hop time t = (E - Lam)/(Lam' - Lam) carrying
-// the adjoint of the time left.  Splitting the phases gives each its own
-// register allocation.
+// segments last to first, over chunks of beams: the seed kernel (one
+// wavefront per beam); per segment the replay from its checkpoint by the
+// FP64 stepping kernel, which writes each interval's stage records (what the
+// vector-Jacobian products read of a stage value: q1, p1, the momentum
+// component of P and the column d of Z; adjoint.h) and whether the interval
+// has a hop; and the reverse kernel (one wavefront per beam), which takes the
+// intervals without a hop from their records alone (four stage products per
+// RK4 step) and the few with one out of line: their start found again from
+// the checkpoint, then swept through their legs (adjoint.h): the trial step,
+// the shortened step to the hop time and the weight update, with the hop time
+// t = (E - Lam)/(Lam' - Lam) carrying the adjoint of the time left.
 #include "adjoint.h"
+#include "dual.h"
 #include "wave.h"
 
 namespace shgb {
@@ -53,16 +54,16 @@ struct AwT {
   // momentum component of P (the centre enters through them only), and the
   // column d of Z: Zrp_a0 and Zpp_0a for a < d (the Hessian enters only
   // through dL/dH00).  One record per RK4 stage.
-  static constexpr int SR = 3 + 4 * D;
+  static constexpr int SR = adj_stage_rec(D);
   static constexpr int RREC = 4 * SR;                         // one RK4 step
   // full stage inputs 1..3 of a step with a hop (the step-size adjoint needs
   // the slopes), per lane, in the wave's workspace
   static constexpr int REC = 3 * NF * kAwLanes;
   // the seed's elimination of [Z | I | P], in LDS
   static constexpr int ELIM = M * (2 * M + 2) * 2;
-  // the wave's exchange buffer with the out-of-line hop intervals: two
-  // states, the hop scalars and the parameter adjoints
-  static constexpr int IO = 2 * NF * kAwLanes + 16;
+  // the exchange buffer with the out-of-line hop intervals: the adjoint
+  // state and the parameter adjoints
+  static constexpr int IO = NF * kAwLanes + 8;
 };
 
 // Doubles per beam of the buffers of an interval with a hop: its full stage
@@ -266,17 +267,61 @@ __device__ inline void aw_rk4(const DevModel &md, int l, const typename AwT<D>::
   }
 }
 
+// The two-level quantities at the four stages of a step and their Jacobian
+// in (q1, A, B, C, D): per stage 32 doubles, (s, s1, s2, s3, d21) then
+// J[o][k] at 5 + 5 o + k (o over the five quantities, k over the five
+// inputs), in the calling wave's part of an LDS array.
+constexpr int kQ1Tab = 32;
+
+template <int D>
+__device__ inline double *aw_q1tab() {
+  __shared__ double tab[kAwWaves][4 * kQ1Tab];
+  return tab[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
+}
+
+// Fill the table for the step whose stage records are rr: lane L < 20 takes
+// stage L / 5 and the forward derivative along input L % 5 (dual numbers,
+// the formulas of the stepping kernels); the values come with every lane.
+template <int D>
+__device__ inline void aw_q1_fill(const DevModel &md, int lane, const double *rr, double *tab) {
+  const int st = lane < 20 ? lane / 5 : 0, k = lane < 20 ? lane % 5 : 0;
+  const double q0 = rr[st * AwT<D>::SR];
+  QcleDu p;
+  p.A = Du(md.A, k == 1 ? 1.0 : 0.0);
+  p.B = Du(md.B, k == 2 ? 1.0 : 0.0);
+  p.C = Du(md.C, k == 3 ? 1.0 : 0.0);
+  p.D = Du(md.D, k == 4 ? 1.0 : 0.0);
+  p.inv_mass = md.inv_mass;
+  const Q1Du o = qcle_q1_du(p, Du(q0, k == 0 ? 1.0 : 0.0));
+  double *t = tab + st * kQ1Tab;
+  if (lane < 20) {
+    t[5 + k] = o.s.d;
+    t[10 + k] = o.s1.d;
+    t[15 + k] = o.s2.d;
+    t[20 + k] = o.s3.d;
+    t[25 + k] = o.d21.d;
+    if (k == 0) {
+      t[0] = o.s.v;
+      t[1] = o.s1.v;
+      t[2] = o.s2.v;
+      t[3] = o.s3.v;
+      t[4] = o.d21.v;
+    }
+  }
+  wave_lds_sync();
+}
+
 // Vector-Jacobian product of the right-hand side at the stage value whose
-// record is q: yb gets g^T d(rhs)/dy, th (replicated over the lanes) gets
-// g^T d(rhs)/d(A, B, C, D).
+// record is q and whose two-level table is t: yb gets g^T d(rhs)/dy, th
+// (replicated over the lanes) gets g^T d(rhs)/d(A, B, C, D).
 template <int D>
 __device__ inline void aw_vjp(const DevModel &md, int l, const typename AwT<D>::Cx &cx, const double *q,
-                              const typename AwT<D>::Y &g, typename AwT<D>::Y &yb, double th[4],
+                              const double *t, const typename AwT<D>::Y &g, typename AwT<D>::Y &yb, double th[4],
                               typename AwT<D>::Lds &s) {
   using C = typename AwT<D>::C;
   const int lane = cx.r;
-  const double q0 = q[0], p0 = q[1], Pp0 = q[2];
-  const Q1 k = qcle_q1(md, q0);
+  const double p0 = q[1], Pp0 = q[2];
+  const Q1 k = {t[0], t[1], t[2], t[3], t[4]};
   const double im = md.inv_mass, lam = md.lam;
   const double sg = comp_sigma(l), bc = comp_bcoef(l), H00 = sg * k.s2;
   // the Hessian part: the forward update of the exchanged adjoint, exchanged
@@ -357,7 +402,17 @@ __device__ inline void aw_vjp(const DevModel &md, int l, const typename AwT<D>::
   sb[2] = sg * Hb - bc * gi00;
   sb[3] = -sg * Pp0 * gi00;
   sb[4] = 2.0 * sgn * v * gL;
-  const double qb = q1_pullback_rev(md, q0, sb, th);
+  // the pullback to q1 and (A, B, C, D) through the stage's Jacobian
+  double qb = 0.0;
+#pragma unroll
+  for (int o = 0; o < 5; ++o) qb += sb[o] * t[5 + 5 * o];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double a = 0.0;
+#pragma unroll
+    for (int o = 0; o < 5; ++o) a += sb[o] * t[5 + 5 * o + 1 + j];
+    th[j] += a;
+  }
   yb.x[0] = Xb + (lane == 0 ? qb : 0.0);
   yb.p[0] = Pb;
 #pragma unroll
@@ -379,6 +434,8 @@ __device__ inline void aw_rk4_rev_fast(const DevModel &md, int l, const typename
   using C = typename AwT<D>::C;
   using Y = typename AwT<D>::Y;
   const double h6 = h * (1.0 / 6.0);
+  double *tab = aw_q1tab<D>();
+  aw_q1_fill<D>(md, cx.r, rr, tab);
   const Y ybo = yb;
   Y Yb;
   aw_zero<D>(Yb);
@@ -398,7 +455,7 @@ __device__ inline void aw_rk4_rev_fast(const DevModel &md, int l, const typename
     }
     g.S = ca * ybo.S + cb * Yb.S;
     g.Lam = ca * ybo.Lam + cb * Yb.Lam;
-    aw_vjp<D>(md, l, cx, rr + st * AwT<D>::SR, g, Yb, th, s);
+    aw_vjp<D>(md, l, cx, rr + st * AwT<D>::SR, tab + st * kQ1Tab, g, Yb, th, s);
     aw_axpy<D>(yb, 1.0, Yb);
   }
 }
@@ -414,13 +471,15 @@ __device__ inline void aw_rk4_rev(const DevModel &md, int l, const typename AwT<
   using Y = typename AwT<D>::Y;
   const int lane = cx.r;
   const double h6 = h * (1.0 / 6.0);
+  double *tab = aw_q1tab<D>();
+  aw_q1_fill<D>(md, lane, rr, tab);
   ybi = ybo;
   Y g, Yb, Ys;
   hb = 0.0;
   // stage 4 (input rec[2]), then 3, 2, 1; kb carries the adjoint of the previous stage's slope
   aw_zero<D>(g);
   aw_axpy<D>(g, h6, ybo);
-  aw_vjp<D>(md, l, cx, rr + 3 * AwT<D>::SR, g, Yb, th, s);
+  aw_vjp<D>(md, l, cx, rr + 3 * AwT<D>::SR, tab + 3 * kQ1Tab, g, Yb, th, s);
   aw_axpy<D>(ybi, 1.0, Yb);
   double kdot = 0.0;
   if (need_h) {
@@ -432,7 +491,7 @@ __device__ inline void aw_rk4_rev(const DevModel &md, int l, const typename AwT<
   aw_zero<D>(g);
   aw_axpy<D>(g, 2.0 * h6, ybo);
   aw_axpy<D>(g, h, Yb);
-  aw_vjp<D>(md, l, cx, rr + 2 * AwT<D>::SR, g, Yb, th, s);
+  aw_vjp<D>(md, l, cx, rr + 2 * AwT<D>::SR, tab + 2 * kQ1Tab, g, Yb, th, s);
   aw_axpy<D>(ybi, 1.0, Yb);
   if (need_h) {
     Y k2;
@@ -443,7 +502,7 @@ __device__ inline void aw_rk4_rev(const DevModel &md, int l, const typename AwT<
   aw_zero<D>(g);
   aw_axpy<D>(g, 2.0 * h6, ybo);
   aw_axpy<D>(g, 0.5 * h, Yb);
-  aw_vjp<D>(md, l, cx, rr + AwT<D>::SR, g, Yb, th, s);
+  aw_vjp<D>(md, l, cx, rr + AwT<D>::SR, tab + kQ1Tab, g, Yb, th, s);
   aw_axpy<D>(ybi, 1.0, Yb);
   if (need_h) {
     Y k1;
@@ -453,7 +512,7 @@ __device__ inline void aw_rk4_rev(const DevModel &md, int l, const typename AwT<
   aw_zero<D>(g);
   aw_axpy<D>(g, h6, ybo);
   aw_axpy<D>(g, 0.5 * h, Yb);
-  aw_vjp<D>(md, l, cx, rr, g, Yb, th, s);
+  aw_vjp<D>(md, l, cx, rr, tab, g, Yb, th, s);
   aw_axpy<D>(ybi, 1.0, Yb);
   if (need_h) {
     // ybo . (k1 + 2 k2 + 2 k3 + k4) / 6 = ybo . (out - y) / h with out recomputed
@@ -562,52 +621,10 @@ __device__ inline void aw_opaque(typename AwT<D>::Cx &cx) {
   for (int e = 0; e < AwT<D>::C::NG; ++e) asm volatile("" : "+v"(cx.a[e]), "+v"(cx.b[e]));
 }
 
-// The out-of-line parts (an interval with a hop: a few in a thousand)
-// exchange their state with the calling loop through the beam's buffer io:
-// a state at io, a second one at io + NF 64, the hop scalars at io + 2 NF 64
-// and the parameter adjoints at io + 2 NF 64 + 8, so that the loop's
-// registers are not tied to memory.
-template <int D>
-__device__ inline void aw_put_h(const HopScalars &h, double *q, int lane) {
-  if (lane == 0) {
-    q[0] = h.logw;
-    q[1] = h.phre;
-    q[2] = h.phim;
-    q[3] = h.Lam;
-    q[4] = h.E;
-    q[5] = (double)h.comp;
-    q[6] = (double)h.nhop;
-  }
-}
-
-__device__ inline void aw_get_h(HopScalars &h, const double *q) {
-  h.logw = q[0];
-  h.phre = q[1];
-  h.phim = q[2];
-  h.Lam = q[3];
-  h.E = q[4];
-  h.comp = (int)q[5];
-  h.nhop = (uint32_t)q[6];
-}
-
-// An interval with a hop, forwards, from the state and hop scalars in io
-// (replaced by the interval's end).
-template <int D>
-__device__ __attribute__((noinline)) void aw_interval_hop(const DevModel &md, double *io, uint64_t gid,
-                                                          uint64_t seed, double dt) {
-  constexpr int NF = AwT<D>::NF;
-  const typename AwT<D>::Cx cx = aw_ctx<D>(threadIdx.x & 63);
-  typename AwT<D>::Y y;
-  HopScalars h;
-  aw_get<D>(y, io, cx.r);
-  aw_get_h(h, io + 2 * NF * kAwLanes);
-  double rem;
-  aw_legs_general<D>(md, cx, y, h, gid, seed, dt, -1, rem, aw_lds<D>());
-  aw_put<D>(y, io, cx.r);
-  aw_put_h<D>(h, io + 2 * NF * kAwLanes, cx.r);
-  aw_mem_sync();
-}
-
+// The out-of-line part (an interval with a hop: a few in a thousand)
+// exchanges its state with the calling loop through the beam's buffer io:
+// the adjoint state at io and the parameter adjoints at io + NF 64, so that
+// the loop's registers are not tied to memory.
 // Reverse sweep of one interval starting at (ys, hs); yb: adjoint of its end
 // on entry, of its start on return.
 template <int D>
@@ -723,8 +740,8 @@ __device__ inline void aw_load(const typename AwT<D>::Cx &cx, const double *f, c
 
 // Reverse sweep of interval i of a segment that has a hop: its start is
 // found again by running the segment from its checkpoint (cf, ci; the beam's
-// column b), the adjoint of its end is at io + NF 64 (replaced by that of its
-// start), the parameter adjoints it adds go to io + 2 NF 64 + 8; rec and rr
+// column b), the adjoint of its end is at io (replaced by that of its
+// start), the parameter adjoints it adds go to io + NF 64; rec and rr
 // hold the stage values of one step.
 template <int D>
 __device__ __attribute__((noinline)) void aw_interval_rev_hop(const DevModel &md, const double *cf, const int32_t *ci,
@@ -750,12 +767,12 @@ __device__ __attribute__((noinline)) void aw_interval_rev_hop(const DevModel &md
       aw_legs_general<D>(md, cx, ys, hs, gid, seed, dt, -1, rem, s);
     }
   }
-  aw_get<D>(yb, io + NF * kAwLanes, cx.r);
+  aw_get<D>(yb, io, cx.r);
   double th[4] = {0.0, 0.0, 0.0, 0.0};
   aw_interval_rev_general<D>(md, cx, ys, hs, gid, seed, dt, yb, logwb, th, s, rec, rr);
-  aw_put<D>(yb, io + NF * kAwLanes, cx.r);
+  aw_put<D>(yb, io, cx.r);
   if (cx.r == 0)
-    for (int k = 0; k < 4; ++k) io[2 * NF * kAwLanes + 8 + k] = th[k];
+    for (int k = 0; k < 4; ++k) io[NF * kAwLanes + k] = th[k];
   aw_mem_sync();
 }
 
@@ -907,50 +924,17 @@ aw_seed_kernel(DevModel md, const double *__restrict__ fin, const int32_t *__res
   }
 }
 
-// Replay of segment [start, start + len) from its checkpoint: each interval's
-// trial-step stage records, its component and whether it has a hop.
-template <int D>
-__global__ void __launch_bounds__(kAwLanes * kAwWaves)
-aw_replay_kernel(DevModel md, const double *__restrict__ cf, const int32_t *__restrict__ ci, int64_t n, int len,
-                 int every, int64_t b0, int64_t nb, uint64_t gid0, uint64_t seed, double dt, double *__restrict__ recs,
-                 double *__restrict__ gen) {
-  using Y = typename AwT<D>::Y;
-  constexpr int M = 2 * D, NF = AwT<D>::NF, RS = AwT<D>::RREC + 2;
-  const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t w = (int64_t)blockIdx.x * kAwWaves + wid;
+// The checkpoint of the chunk's beams [b0, b0 + nb) (rows of n) into a
+// state of rows of ld = chunk, for the replay.
+__global__ void __launch_bounds__(256) aw_ckpt_load_kernel(const double *__restrict__ cf, const int32_t *__restrict__ ci,
+                                                           int64_t n, int64_t rows, int64_t b0, int64_t nb, int64_t ld,
+                                                           double *__restrict__ f64, int32_t *__restrict__ comp,
+                                                           uint32_t *__restrict__ nhop) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= nb) return;
-  typename AwT<D>::Lds &s = aw_lds<D>();
-  typename AwT<D>::Cx cx = aw_ctx<D>(lane);
-  pg_fill_const<D, kAwLanes, double>(lane, md.bath_k, s);
-  const int64_t b = b0 + w;
-  const uint64_t gid = gid0 + (uint64_t)b;
-  const int64_t tro = (int64_t)(2 * M + M * (M + 1));
-  double *rw = recs + w * (int64_t)every * RS;
-  double *io = gen + w * aw_gen_doubles<D>() + AwT<D>::REC + AwT<D>::RREC;
-  Y ys;
-  aw_load<D>(cx, cf, cf + tro * n, n, b, ys);
-  HopScalars hs = aw_ckpt_h(cf, ci, tro, n, b);
-  for (int i = 0; i < len; ++i) {
-    aw_opaque<D>(cx);
-    double *r = rw + (int64_t)i * RS;
-    Y yt;
-    aw_rk4<D>(md, hs.comp, cx, ys, dt, yt, s, nullptr, r);
-    const bool hop = yt.Lam >= hs.E;
-    if (lane == 0) {
-      r[AwT<D>::RREC] = (double)hs.comp;
-      r[AwT<D>::RREC + 1] = hop ? 1.0 : 0.0;
-    }
-    if (!hop) {
-      ys = yt;
-    } else {
-      aw_put<D>(ys, io, lane);
-      aw_put_h<D>(hs, io + 2 * NF * kAwLanes, lane);
-      aw_mem_sync();
-      aw_interval_hop<D>(md, io, gid, seed, dt);
-      aw_get<D>(ys, io, lane);
-      aw_get_h(hs, io + 2 * NF * kAwLanes);
-    }
-  }
+  for (int64_t f = 0; f < rows; ++f) f64[f * ld + w] = cf[f * n + b0 + w];
+  comp[w] = ci[b0 + w];
+  nhop[w] = (uint32_t)ci[n + b0 + w];
 }
 
 // Reverse sweep of the segment from its records; the adjoint state in ybuf
@@ -963,7 +947,7 @@ aw_reverse_kernel(DevModel md, const double *__restrict__ cf, const int32_t *__r
                   const double *__restrict__ recs, double *__restrict__ ybuf, double *__restrict__ bsc,
                   double *__restrict__ gen) {
   using Y = typename AwT<D>::Y;
-  constexpr int NF = AwT<D>::NF, RS = AwT<D>::RREC + 2;
+  constexpr int NF = AwT<D>::NF, RS = adj_interval_rec(D);
   const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t w = (int64_t)blockIdx.x * kAwWaves + wid;
   if (w >= nb) return;
@@ -986,12 +970,12 @@ aw_reverse_kernel(DevModel md, const double *__restrict__ cf, const int32_t *__r
     if (r[AwT<D>::RREC + 1] == 0.0) {
       aw_rk4_rev_fast<D>(md, (int)r[AwT<D>::RREC], cx, r, dt, yb, th, s);
     } else {
-      aw_put<D>(yb, io + NF * kAwLanes, lane);
+      aw_put<D>(yb, io, lane);
       aw_mem_sync();
       aw_interval_rev_hop<D>(md, cf, ci, n, b, i, io, gid, seed, dt, logwb, g, g + AwT<D>::REC);
-      aw_get<D>(yb, io + NF * kAwLanes, lane);
+      aw_get<D>(yb, io, lane);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) th[k] += io[2 * NF * kAwLanes + 8 + k];
+      for (int k = 0; k < 4; ++k) th[k] += io[NF * kAwLanes + k];
     }
   }
   aw_put<D>(yb, ybuf + w * NF * kAwLanes, lane);
@@ -1014,15 +998,22 @@ int64_t aw_chunk(int64_t n) {
   return n < kAwChunk ? (n < 1 ? 1 : n) : kAwChunk;
 }
 
+// Workspace (doubles): the records of one segment for the chunk, the
+// chunk's adjoint states, its buffers for intervals with a hop, its replay
+// state (shgb_nfields rows, then comp and nhop), and one row of kAdjVals per
+// beam.
 template <int D>
 int64_t aw_workspace_bytes(int64_t n, int every) {
   const int64_t c = aw_chunk<D>(n);
-  const int64_t dbl = c * ((int64_t)every * (AwT<D>::RREC + 2) + AwT<D>::NF * kAwLanes + aw_gen_doubles<D>()) +
+  const int64_t dbl = c * ((int64_t)every * adj_interval_rec(D) + AwT<D>::NF * kAwLanes + aw_gen_doubles<D>() +
+                           shgb_nfields(2 * D) + 1) +
                       (n < 1 ? 1 : n) * kAdjVals;
   return dbl * 8;
 }
 
 hipError_t launch_adj_final(const double *, int64_t, double *, hipStream_t);
+hipError_t launch_step_wave_record(const DevModel &, const shgb_state &, int, double, uint64_t, double *, int,
+                                   hipStream_t);
 
 template <int D>
 hipError_t launch_aw(const DevModel &md, const shgb_state &fin, const void *ckpt, int nsteps, double dt, uint64_t seed,
@@ -1031,22 +1022,37 @@ hipError_t launch_aw(const DevModel &md, const shgb_state &fin, const void *ckpt
   const int64_t chunk = aw_chunk<D>(n);
   const CkptLayout cl = ckpt_layout(n, 2 * D, nsteps, every);
   double *recs = (double *)work;
-  double *ybuf = recs + chunk * (int64_t)every * (AwT<D>::RREC + 2);
+  double *ybuf = recs + chunk * (int64_t)every * adj_interval_rec(D);
   double *gen = ybuf + chunk * AwT<D>::NF * kAwLanes;
-  double *bsc = gen + chunk * aw_gen_doubles<D>();
+  double *rf = gen + chunk * aw_gen_doubles<D>();
+  int32_t *rcomp = (int32_t *)(rf + chunk * (int64_t)shgb_nfields(2 * D));
+  uint32_t *rnhop = (uint32_t *)(rcomp + chunk);
+  double *bsc = rf + chunk * ((int64_t)shgb_nfields(2 * D) + 1);
   const double inv_ntraj = 1.0 / (double)n_traj;
   for (int64_t b0 = 0; b0 < n; b0 += chunk) {
     const int64_t nb = n - b0 < chunk ? n - b0 : chunk;
     const unsigned blocks = (unsigned)((nb + kAwWaves - 1) / kAwWaves);
     hipLaunchKernelGGL(aw_seed_kernel<D>, dim3(blocks), dim3(kAwLanes * kAwWaves), 0, stream, md, fin.f64, fin.comp,
                        fin.ld, b0, nb, cot, inv_ntraj, ybuf, bsc);
+    shgb_state rs{};
+    rs.f64 = rf;
+    rs.comp = rcomp;
+    rs.nhop = rnhop;
+    rs.n_beams = nb;
+    rs.ld = chunk;
+    rs.beam_id_offset = fin.beam_id_offset + (uint64_t)b0;
+    rs.m = 2 * D;
+    rs.precision = SHGB_FP64;
+    rs.f32 = nullptr;
     for (int c = cl.n_ckpt - 1; c >= 0; --c) {
       const int start = c * every, len = nsteps - start < every ? nsteps - start : every;
       const char *base = (const char *)ckpt + (int64_t)c * cl.stride_bytes;
       const double *cf = (const double *)base;
       const int32_t *ci = (const int32_t *)(base + cl.rows * n * 8);
-      hipLaunchKernelGGL(aw_replay_kernel<D>, dim3(blocks), dim3(kAwLanes * kAwWaves), 0, stream, md, cf, ci, n, len,
-                         every, b0, nb, fin.beam_id_offset, seed, dt, recs, gen);
+      hipLaunchKernelGGL(aw_ckpt_load_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, stream, cf, ci, n,
+                         cl.rows, b0, nb, chunk, rf, rcomp, rnhop);
+      const hipError_t e = launch_step_wave_record(md, rs, len, dt, seed, recs, every, stream);
+      if (e != hipSuccess) return e;
       hipLaunchKernelGGL(aw_reverse_kernel<D>, dim3(blocks), dim3(kAwLanes * kAwWaves), 0, stream, md, cf, ci, n,
                          len, every, c == 0 ? 1 : 0, b0, nb, fin.beam_id_offset, seed, dt, recs, ybuf, bsc, gen);
     }

@@ -30,6 +30,7 @@
 // area too), each step's increment is formed in FP32 and added to an FP64
 // copy of the state held in registers for the whole call; S and Lam are
 // FP64 as in the FP64 path.
+#include "adjoint.h"
 #include "batch.h"
 #include "wave.h"
 
@@ -102,24 +103,51 @@ __device__ inline void pg_stage(const DevModel &md, const QcleF &mf, int l, cons
   fold(acc.Lam, unused, y0.Lam, dL);
 }
 
-// One classical RK4 step of the group's beam on its component, into `out`;
-// `s` is clobbered.
+// The stage record of stage values y at q (when q is given): the values
+// the reverse sweep's vector-Jacobian products read, in the layout of
+// adj_stage_rec (adjoint.h): X_1 from lane 0, X_d+1 and P_d+1 from lane d,
+// and from lane a < d the slots ba and pp of its first group, (0, a).
 template <int D, int LPB>
+__device__ inline void pg_record(const PgCtx<D, LPB, double> &cx, const PgY<D, LPB, double> &y, double *q) {
+  static_assert(2 * D <= LPB, "the record's owners are the first 2d lanes, first slots");
+  if (!q) return;
+  const int r = cx.r;
+  if (r == 0) q[0] = y.x[0];
+  if (r == D) {
+    q[1] = y.x[0];
+    q[2] = y.p[0];
+  }
+  if (r < D) {
+    q[3 + r] = y.g[0].v[kBaR];
+    q[3 + D + r] = y.g[0].v[kBaI];
+    q[3 + 2 * D + r] = y.g[0].v[kPpR];
+    q[3 + 3 * D + r] = y.g[0].v[kPpI];
+  }
+}
+
+// One classical RK4 step of the group's beam on its component, into `out`;
+// `s` is clobbered.  REC: the four stage records go to rec when it is given.
+template <int D, int LPB, bool REC = false>
 __device__ inline void pg_rk4(const DevModel &md, const QcleF &mf, const HopCtx &hc, const PgCtx<D, LPB, double> &cx,
                               const PgY<D, LPB, double> &y, double h, PgY<D, LPB, double> &out,
-                              PgLds<D, double> &s) {
+                              PgLds<D, double> &s, double *rec = nullptr) {
+  constexpr int SR = adj_stage_rec(D);
   PgY<D, LPB, double> ys = y;
   const double h6 = h * (1.0 / 6.0);
   const int l = hc.h.comp;
+  if constexpr (REC) pg_record(cx, ys, rec);
   pg_publish(cx, ys, s);
   pg_stage<D, LPB, 0>(md, mf, l, cx, y, ys, out, 0.5 * h, h6, s);
   wave_lds_sync();
+  if constexpr (REC) pg_record(cx, ys, rec ? rec + SR : rec);
   pg_publish(cx, ys, s);
   pg_stage<D, LPB, 1>(md, mf, l, cx, y, ys, out, 0.5 * h, h6, s);
   wave_lds_sync();
+  if constexpr (REC) pg_record(cx, ys, rec ? rec + 2 * SR : rec);
   pg_publish(cx, ys, s);
   pg_stage<D, LPB, 2>(md, mf, l, cx, y, ys, out, h, h6, s);
   wave_lds_sync();
+  if constexpr (REC) pg_record(cx, ys, rec ? rec + 3 * SR : rec);
   pg_publish(cx, ys, s);
   pg_stage<D, LPB, 3>(md, mf, l, cx, y, ys, out, 0.0, h6, s);
   wave_lds_sync();
@@ -210,31 +238,40 @@ __device__ inline void pg_add_inc(PgY<D, LPB, double> &y, const PgY<D, LPB, floa
 // interpolated hop time, the hop (at the state reached), and the rest of
 // the interval.  MIXED selects the
 // mixed-precision step.
-template <int D, int LPB, bool MIXED>
+template <int D, int LPB, bool MIXED, bool REC = false>
 __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const PgCtx<D, LPB, double> &cx,
                                    const PgCtx<D, LPB, float> &cxf, int base, PgY<D, LPB, double> &y, HopCtx &hc,
-                                   double dt, Counters &cnt, void *lds) {
+                                   double dt, Counters &cnt, void *lds, double *rec = nullptr) {
   const double tie_rel = MIXED ? kTieRelMixed : kTieRel;
   double rem = dt, hstep = dt, theta = 1.0;
   bool partial = false;
   int hops = 0;
   using YN = typename std::conditional<MIXED, PgY<D, LPB, float>, PgY<D, LPB, double>>::type;
   YN yn;  // FP64: the trial result; mixed: the trial increment
-  auto trial = [&](double hh) {
+  auto trial = [&](double hh, double *rq) {
     if constexpr (MIXED) pg_rk4_m(md, mf, hc, cnt, cxf, y, hh, yn, *(PgLds<D, float> *)lds);
-    else pg_rk4(md, mf, hc, cx, y, hh, yn, *(PgLds<D, double> *)lds);
+    else pg_rk4<D, LPB, REC>(md, mf, hc, cx, y, hh, yn, *(PgLds<D, double> *)lds, rq);
   };
+  // REC: the first trial step's stage records, then the interval's component
+  // and whether it has a hop (the trial step is not its whole result)
+  const int comp0 = hc.h.comp;
   auto accept = [&]() {
     if constexpr (MIXED) pg_add_inc(y, yn);
     else y = yn;
   };
   for (;;) {
-    trial(hstep);
+    trial(hstep, (REC && hops == 0 && !partial) ? rec : nullptr);
     const double E = hc.h.E;
     if (!partial) {
       const bool capped = hops >= SHGB_HOP_CAP;
       const double lam_n = MIXED ? y.Lam + yn.Lam : yn.Lam;
       if (!capped && fabs(lam_n - E) <= tie_rel * E) cnt.thr_ties++;
+      if constexpr (REC) {
+        if (hops == 0 && cx.r == 0 && rec) {
+          rec[4 * adj_stage_rec(D)] = (double)comp0;
+          rec[4 * adj_stage_rec(D) + 1] = (capped || !(lam_n >= E)) ? 0.0 : 1.0;
+        }
+      }
       if (capped || !(lam_n >= E)) {
         if (capped) cnt.cap++;
         accept();
@@ -285,11 +322,12 @@ constexpr int kLanesPerBeamD12 = 32;
 // per wave).  TS: element type of the stored trajectory rows (double: FP64
 // path, float: mixed path); the register copy of the state is FP64 in both.
 // The group's replicated counts are added to cnt by its lane 0 only.
-template <int D, int LPB, typename TS, int WPB>
+template <int D, int LPB, typename TS, int WPB, bool REC = false>
 __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double *__restrict__ sc,
                                  int32_t *__restrict__ comp, uint32_t *__restrict__ nhop, int64_t n, int64_t ld,
                                  uint64_t gid0, int nsteps, double dt, uint64_t seed, int64_t tile,
-                                 PgLds<D, TS> *lds, Counters &cnt_out) {
+                                 PgLds<D, TS> *lds, Counters &cnt_out, double *__restrict__ recs = nullptr,
+                                 int every = 0) {
   using C = PG<D, LPB>;
   constexpr int M = C::M;
   constexpr bool MIXED = sizeof(TS) == sizeof(float);
@@ -349,7 +387,8 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
     hc.seed = seed;
     pg_fill_const<D, LPB>(r, md.bath_k, lds[slot]);
     for (int st = 0; st < nsteps; ++st)
-      pg_interval<D, LPB, MIXED>(md, mf, cx, cxf, base, y, hc, dt, cnt, (void *)&lds[slot]);
+      pg_interval<D, LPB, MIXED, REC>(md, mf, cx, cxf, base, y, hc, dt, cnt, (void *)&lds[slot],
+                                      REC ? recs + ((int64_t)b * every + st) * adj_interval_rec(D) : nullptr);
     // (every hop is completed where it starts, so none is pending here)
     // finiteness of the values this lane owns (slots without a pair group
     // or coordinate hold no state)
@@ -439,6 +478,45 @@ step_wave_batched(const BatchItem *__restrict__ items, int n_items, int64_t tota
     }
   }
   flush_counters(cnt, diag);
+}
+
+// The FP64 stepping kernel that also writes, for every interval, the stage
+// records of its trial step, its component and whether it has a hop (the
+// replay of a segment for the reverse sweep; records of beam b, interval i at
+// recs + (b every + i) adj_interval_rec(d)).
+template <int D, int LPB>
+__global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(1)))
+step_wave_rec_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
+                     uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps, double dt,
+                     uint64_t seed, double *__restrict__ recs, int every) {
+  __shared__ PgLds<D, double> lds[kWavesPerBlock * PG<D, LPB>::G];
+  Counters cnt;
+  wave_tile<D, LPB, double, kWavesPerBlock, true>(md, tr, sc, comp, nhop, n, ld, gid0, nsteps, dt, seed, blockIdx.x,
+                                                  lds, cnt, recs, every);
+}
+
+template <int D, int LPB>
+static void launch_pg_rec(const DevModel &md, const shgb_state &st, int nsteps, double dt, uint64_t seed,
+                          double *recs, int every, hipStream_t stream) {
+  constexpr int beams_per_block = kWavesPerBlock * PG<D, LPB>::G;
+  const int64_t blocks = (st.n_beams + beams_per_block - 1) / beams_per_block;
+  hipLaunchKernelGGL((step_wave_rec_kernel<D, LPB>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, stream,
+                     md, st.f64, scalar_block(st), st.comp, st.nhop, st.n_beams, st.ld, st.beam_id_offset, nsteps,
+                     dt, seed, recs, every);
+}
+
+hipError_t launch_step_wave_record(const DevModel &md, const shgb_state &st, int nsteps, double dt, uint64_t seed,
+                                   double *recs, int every, hipStream_t stream) {
+  if (st.n_beams == 0 || nsteps == 0) return hipSuccess;
+  if (mixed(st) || nsteps > every) return hipErrorInvalidValue;
+  switch (md.d) {
+    case 2: launch_pg_rec<2, 8>(md, st, nsteps, dt, seed, recs, every, stream); break;
+    case 3: launch_pg_rec<3, 8>(md, st, nsteps, dt, seed, recs, every, stream); break;
+    case 4: launch_pg_rec<4, 8>(md, st, nsteps, dt, seed, recs, every, stream); break;
+    case 12: launch_pg_rec<12, kLanesPerBeamD12>(md, st, nsteps, dt, seed, recs, every, stream); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 bool step_wave_supported(int d) { return d == 2 || d == 3 || d == 4 || d == 12; }
