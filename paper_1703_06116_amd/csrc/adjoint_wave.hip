@@ -940,8 +940,13 @@ __global__ void __launch_bounds__(256) aw_ckpt_load_kernel(const double *__restr
 // Reverse sweep of the segment from its records; the adjoint state in ybuf
 // and the beam's row of bsc are read and written back.  After the first
 // segment (start 0) the adjoint of the initial p1 goes to the row.
+// Two wavefronts per SIMD: the register file is halved (a few values of the
+// interval loop go to scratch, mostly around the out-of-line call) and the
+// latencies of the exchange area and of the FP64 chains are hidden by the
+// second wavefront (1.29 s against 1.56 s for the d = 12 gradient workload;
+// at three wavefronts the spills cost more than the occupancy gains).
 template <int D>
-__global__ void __launch_bounds__(kAwLanes * kAwWaves)
+__global__ void __launch_bounds__(kAwLanes * kAwWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
 aw_reverse_kernel(DevModel md, const double *__restrict__ cf, const int32_t *__restrict__ ci, int64_t n, int len,
                   int every, int first, int64_t b0, int64_t nb, uint64_t gid0, uint64_t seed, double dt,
                   const double *__restrict__ recs, double *__restrict__ ybuf, double *__restrict__ bsc,
