@@ -62,12 +62,14 @@ FLOPS_PER_BEAM_STEP_M24 = 4 * 3616 + 13 * 650
 # per beam-point evaluation of the m = 24 field: the exponent as a contraction over
 # F = 325 features for Re and Im (4 F = 1300, the matrix-core work)
 FLOPS_PER_EVAL_M24 = 4 * 325
-# FP64 operations per beam-interval of the m = 24 reverse sweep: the segment's forward
-# replay (one RK4 step) and the swept step's stages recomputed (one RK4 step), four
-# vector-Jacobian products of the right-hand side (each as costly as the right-hand side,
-# 3616, plus 190 for the pullback of the two-level quantities) and the reverse Runge-Kutta
-# combinations (13 per state double)
-FLOPS_PER_BEAM_STEP_ADJ_M24 = 2 * FLOPS_PER_BEAM_STEP_M24 + 4 * (3616 + 190) + 13 * 650
+# FP64 operations per beam-interval of the m = 24 reverse sweep: the segment's replay
+# (one RK4 step, 22914, by the stepping kernel that writes the stage records) and the
+# reverse kernel: four vector-Jacobian products of the right-hand side (each as costly as
+# the right-hand side without its two-level quantities, 3616 - 87, plus 62 for the
+# cotangents of those quantities and their pullback through the 5 x 5 Jacobian), the
+# Jacobian itself once per step (five directional derivatives, 2 x 87 each) and the
+# reverse Runge-Kutta combinations (4 per state double and stage)
+FLOPS_PER_BEAM_STEP_ADJ_M24 = FLOPS_PER_BEAM_STEP_M24 + 4 * (3616 - 87 + 62) + 5 * 2 * 87 + 16 * 650
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector and FP64 matrix: 256 CU x 64 lanes x 2 flop x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector
 PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
@@ -597,10 +599,15 @@ def run_grad(name, steps, warmup, with_tangent):
         "upper_population": float(p[0, 0] / N),
         "objective_from_reverse_sweep": float(g[5]),
         "d_upper_population": {n: float(g[j]) for j, n in enumerate(("A", "B", "C", "D", "p_mean"))},
-        "roofline": {"bound": "alu", "kernel": f"adjoint_wave_kernel<{c['d']}>" if m > 2 else "adjoint_m2_kernel",
+        "roofline": {"bound": "alu",
+                     "kernel": (f"reverse sweep: step_wave_rec_kernel<{c['d']}, 32> replay + aw_reverse_kernel<{c['d']}>"
+                                if m > 2 else "adjoint_m2_kernel"),
                      "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / PEAK_FP64_TFLOPS, "flops_per_unit": FLOPS_PER_BEAM_STEP_ADJ_M24,
-                     "units_per_launch": N * nsteps, "traffic": None},
+                     "units_per_launch": N * nsteps, "traffic": None,
+                     "note": "time of the whole reverse-sweep call (seed, per segment the replay and the reverse "
+                             "kernel): a lower bound on the reverse kernel's rate; the split per kernel is in "
+                             "profiles/adjoint_wave_qcle12d_grad.md"},
     }
     if with_tangent:
         out = torch.zeros((5, 4, 4), dtype=torch.float64, device=dev)

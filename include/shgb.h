@@ -330,7 +330,10 @@ int shgb_population_tangent(const shgb_model *model, const shgb_state *st, int32
  * its checkpoint and sweeps it backwards.  cot: device double[SHGB_NCOMP * 2];
  * out: device double[6] = dL/dA, dL/dB, dL/dC, dL/dD, dL/dp_mean, L.
  * QCLE, FP64 state, d in {1, 2, 3, 4, 12} (the workspace query returns -1
- * for other m).  Errors: EINVAL, EWORKSPACE, EUNSUPPORTED. */
+ * for other m).  For d > 1 the beams are taken in chunks of at most 8192;
+ * the workspace holds one segment's stage records for a chunk (8 (4 (3 + 4d)
+ * + 2) bytes per beam and interval), the chunk's adjoint states and a copy
+ * of its checkpoint.  Errors: EINVAL, EWORKSPACE, EUNSUPPORTED. */
 int64_t shgb_checkpoint_bytes(int64_t n_beams, int32_t m, int32_t nsteps, int32_t every);
 int shgb_step_checkpointed(const shgb_model *model, const shgb_state *st, int32_t nsteps, double dt, uint64_t seed,
                            int32_t every, void *ckpt, int64_t ckpt_bytes, uint64_t *diag, void *stream);
