@@ -79,8 +79,9 @@ PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
 # kernel it was taken on; remove it when that kernel changes.
 STEP_TRAFFIC = {
     "qcle1d_1e6": ((66680.1 * 2.0 + 133300.8 * 1.0) * 1024, "step_m2_kernel, profiles/step_m2_qcle1d_1e6.md"),
-    "qcle12d_2p18": ((2773065.8 * 2.0 + 4688936.7 * 1.0) * 1024,
-                     "step_wave_kernel<12, 32, double>, profiles/step_wave_qcle12d_2p18.md"),
+    "qcle12d_2p18": ((1829896.6 * 2.0 + 4549004.8 * 1.0) * 1024,
+                     "step_wave_kernel<12, 32, double> with line-sharing tiles on one XCD, "
+                     "profiles/step_wave_qcle12d_2p18.md"),
 }
 # Fraction of the direct sum's VALU instructions that the culled m = 2 field kernel executes
 # on the bench grid (SQ_INSTS_VALU 1.29e9 culled against 4.01e9 direct,

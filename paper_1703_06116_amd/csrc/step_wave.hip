@@ -445,6 +445,29 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
   }
 }
 
+// The tile of workgroup b when K consecutive tiles share the 128-byte lines
+// of the state rows (d = 12: a tile of 8 beams covers half a line of FP64
+// rows, a quarter of FP32 rows): consecutive workgroups are dispatched to the
+// 8 XCDs in turn, so tiles Ki .. Ki + K-1 go to workgroups b, b + 8, ...,
+// which run on one XCD and share its L2, and each line is fetched once.
+// Groups of 8K workgroups are permuted; a last partial group keeps its order.
+template <int K>
+__device__ inline int64_t xcd_line_tile(int64_t b, int64_t nblocks) {
+  if constexpr (K <= 1) {
+    return b;
+  } else {
+    const int64_t q = b / (8 * K), r = b % (8 * K);
+    if ((q + 1) * (8 * K) > nblocks) return b;
+    return 8 * K * q + K * (r % 8) + r / 8;
+  }
+}
+
+template <int D, int LPB, typename TS>
+constexpr int tiles_per_line() {
+  constexpr int bytes = kWavesPerBlock * PG<D, LPB>::G * (int)sizeof(TS);
+  return bytes >= 128 ? 1 : 128 / bytes;
+}
+
 template <int D, int LPB, typename TS>
 __global__ void __launch_bounds__(64 * kWavesPerBlock)
 __attribute__((amdgpu_waves_per_eu(sizeof(TS) == sizeof(float) ? 2 : 1)))
@@ -453,7 +476,8 @@ step_wave_kernel(DevModel md, TS *__restrict__ tr, double *__restrict__ sc, int3
                  uint64_t seed, uint64_t *diag) {
   __shared__ PgLds<D, TS> lds[kWavesPerBlock * PG<D, LPB>::G];
   Counters cnt;
-  wave_tile<D, LPB, TS, kWavesPerBlock>(md, tr, sc, comp, nhop, n, ld, gid0, nsteps, dt, seed, blockIdx.x, lds, cnt);
+  wave_tile<D, LPB, TS, kWavesPerBlock>(md, tr, sc, comp, nhop, n, ld, gid0, nsteps, dt, seed,
+                                        xcd_line_tile<tiles_per_line<D, LPB, TS>()>(blockIdx.x, gridDim.x), lds, cnt);
   flush_counters(cnt, diag);
 }
 
@@ -491,7 +515,8 @@ step_wave_rec_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ 
                      uint64_t seed, double *__restrict__ recs, int every) {
   __shared__ PgLds<D, double> lds[kWavesPerBlock * PG<D, LPB>::G];
   Counters cnt;
-  wave_tile<D, LPB, double, kWavesPerBlock, true>(md, tr, sc, comp, nhop, n, ld, gid0, nsteps, dt, seed, blockIdx.x,
+  wave_tile<D, LPB, double, kWavesPerBlock, true>(md, tr, sc, comp, nhop, n, ld, gid0, nsteps, dt, seed,
+                                                  xcd_line_tile<tiles_per_line<D, LPB, double>()>(blockIdx.x, gridDim.x),
                                                   lds, cnt, recs, every);
 }
 
