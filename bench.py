@@ -646,6 +646,8 @@ def main():
         import multiprocessing as mp
         with mp.get_context("fork").Pool(host_cores()) as pool:   # before the GPU is touched
             cpu = cpu_baselines([head] + extra, pool)
+            pool.close()
+            pool.join()   # every worker has exited before the GPU part starts
 
     import torch
     torch.cuda.set_device(0)
