@@ -330,7 +330,7 @@ int shgb_population_tangent(const shgb_model *model, const shgb_state *st, int32
  * its checkpoint and sweeps it backwards.  cot: device double[SHGB_NCOMP * 2];
  * out: device double[6] = dL/dA, dL/dB, dL/dC, dL/dD, dL/dp_mean, L.
  * QCLE, FP64 state, d in {1, 2, 3, 4, 12} (the workspace query returns -1
- * for other m).  For d > 1 the beams are taken in chunks of at most 8192;
+ * for other m).  For d > 1 the beams are taken in chunks of at most 65536;
  * the workspace holds one segment's stage records for a chunk (8 (4 (3 + 4d)
  * + 2) bytes per beam and interval), the chunk's adjoint states and a copy
  * of its checkpoint.  Errors: EINVAL, EWORKSPACE, EUNSUPPORTED. */

@@ -47,10 +47,11 @@ def tangent_gradient(cfg, cot):
     return (d * w[None]).sum((1, 2)) / cfg["n_beams"]
 
 
-# d > 1 sweeps beams in chunks of 8192: 8192 + 37 beams take a full chunk and a ragged one
+# d > 1 sweeps beams in chunks of 65536: 65536 + 37 beams take a full chunk and a ragged one
 @pytest.mark.parametrize("d,n,nsteps,every", [(1, 2 * 256 + 37, 600, 100), (1, 300, 257, 37), (1, 64, 250, 400),
                                               (2, 2 * 128 + 5, 500, 100), (12, 2 * 64 + 3, 450, 100),
-                                              (12, 37, 330, 64), (2, 8192 + 37, 160, 64), (12, 8192 + 37, 160, 64)])
+                                              (12, 37, 330, 64), (2, 65536 + 37, 120, 48),
+                                              (12, 65536 + 37, 120, 48)])
 def test_adjoint_equals_tangent(gpu, d, n, nsteps, every):
     cfg = crossing_cfg(n, nsteps, d=d)
     rng = np.random.default_rng(7)
