@@ -144,6 +144,35 @@ __device__ inline double aw_wave_sum(double x) {
   return x;
 }
 
+// A DPP move of a double within 16-lane rows (CTRL: a DPP control code).
+template <int CTRL>
+__device__ inline double aw_dpp(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Lane `src`'s value, read into scalar registers (src uniform).
+__device__ inline double aw_lane(double x, int src) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// The sum over lanes 0..31 (the lanes that can hold the summed values:
+// 2d <= 32), returned to every lane: within each 16-lane row by DPP
+// (exchanges with lane ^ 1, lane ^ 2, then rotations by 4 and 8), then the
+// two rows' sums read out of lanes 0 and 16.  No LDS traffic.
+__device__ inline double aw_sum32(double x) {
+  x += aw_dpp<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+  x += aw_dpp<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+  x += aw_dpp<0x124>(x);   // row_ror 4
+  x += aw_dpp<0x128>(x);   // row_ror 8
+  return aw_lane(x, 0) + aw_lane(x, 16);
+}
+
 // Pairing of two adjoint-shaped values over the whole beam: each pair-group
 // slot counted as often as its entry appears in the symmetric matrix
 // (off-diagonal entries twice), S and Lam once.
@@ -373,13 +402,14 @@ __device__ inline void aw_vjp(const DevModel &md, int l, const typename AwT<D>::
     hb = g.g[0].v[kRrR] * q[3 + lane] + g.g[0].v[kRrI] * q[3 + D + lane] + g.g[0].v[kAbR] * q[3 + 2 * D + lane] +
          g.g[0].v[kAbI] * q[3 + 3 * D + lane];
   wave_lds_sync();
-  double Hb = 2.0 * aw_wave_sum(hb);
-  const double gi00 = __shfl(g.g[0].v[kRrI], 0, 64);   // Im G_00: group (0, 0) is lane 0's first
+  static_assert(2 * D <= 32, "the centre's sums cover lanes 0..31");
+  double Hb = 2.0 * aw_sum32(hb);
+  const double gi00 = aw_lane(g.g[0].v[kRrI], 0);   // Im G_00: group (0, 0) is lane 0's first
   // coordinates: lane c owns X_c and P_c (c < 2D)
   const double gx = g.x[0], gp = g.p[0];
-  const double gXp0 = __shfl(gx, D, 64), gPr0 = __shfl(gp, 0, 64);
-  const double sumX = aw_wave_sum(lane > D && lane < 2 * D ? gx : 0.0);   // sum_{k>0} g of X_{p_k}
-  const double sumP = aw_wave_sum(lane > 0 && lane < D ? gp : 0.0);       // sum_{k>0} g of P_{r_k}
+  const double gXp0 = aw_lane(gx, D), gPr0 = aw_lane(gp, 0);
+  const double sumX = aw_sum32(lane > D && lane < 2 * D ? gx : 0.0);   // sum_{k>0} g of X_{p_k}
+  const double sumP = aw_sum32(lane > 0 && lane < D ? gp : 0.0);       // sum_{k>0} g of P_{r_k}
   const int partner = lane < D ? lane + D : (lane < 2 * D ? lane - D : lane);
   const double gxo = __shfl(gx, partner, 64), gpo = __shfl(gp, partner, 64);
   const double v = p0 * im, vk = v * k.d21;
