@@ -340,6 +340,30 @@ __device__ inline void aw_q1_fill(const DevModel &md, int lane, const double *rr
   wave_lds_sync();
 }
 
+// The exchange sums of an adjoint (as pg_sums), each over four partial sums
+// so that the dependent adds after the reads are shorter.
+template <int D>
+__device__ inline void aw_sums(const typename AwT<D>::Cx &cx, typename AwT<D>::Lds &s) {
+  constexpr int W = AwT<D>::Lds::W;
+  static_assert(2 * D + 1 <= kAwLanes, "one exchange sum per lane");
+  const int t = cx.r < 2 * D + 1 ? cx.r : 2 * D;
+  const bool row = t < D, col = !row && t < 2 * D;
+  const int u = row ? t : (col ? t - D : 0);
+  const double *br = row ? &s.rp[u][0].re : (col ? &s.pp[0][u].re : &s.x[0]);
+  const double *bi = row ? &s.rp[u][0].im : (col ? &s.pp[0][u].im : &s.p[D]);
+  const int stride = row ? 2 : (col ? 2 * W : 1);
+  double *orr = row ? &s.rho[u].re : (col ? &s.chi[u].re : &s.sx);
+  double *oi = row ? &s.rho[u].im : (col ? &s.chi[u].im : &s.sp);
+  double sr[4] = {0.0, 0.0, 0.0, 0.0}, si[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 1; k < D; ++k) {
+    sr[k & 3] += br[k * stride];
+    si[k & 3] += bi[k * stride];
+  }
+  *orr = (sr[0] + sr[1]) + (sr[2] + sr[3]);
+  *oi = (si[0] + si[1]) + (si[2] + si[3]);
+}
+
 // Vector-Jacobian product of the right-hand side at the stage value whose
 // record is q and whose two-level table is t: yb gets g^T d(rhs)/dy, th
 // (replicated over the lanes) gets g^T d(rhs)/d(A, B, C, D).
@@ -368,7 +392,7 @@ __device__ inline void aw_vjp(const DevModel &md, int l, const typename AwT<D>::
     }
   }
   wave_lds_sync();
-  pg_sums(cx, s);
+  aw_sums<D>(cx, s);
   wave_lds_sync();
   StageCoef<double> c0;
   c0.k = Q1T<double>{k.s, k.s1, k.s2, k.s3, k.d21};
