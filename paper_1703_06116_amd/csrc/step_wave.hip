@@ -1,6 +1,7 @@
 // Beam stepping for the d-dimensional QCLE (phase space m = 2d > 2): a group
-// of LPB lanes per beam (64/LPB beams per wavefront), all intervals in
-// registers.
+// of LPB lanes per beam (64/LPB beams per wavefront), all intervals on chip
+// (in registers; for FP64 d = 12 two pair-group slots of the interval's
+// starting state in LDS).
 //
 // Model (Sec. 3.3 with a harmonic bath): E_l(r) = Vb(r) + sigma_l s(q1),
 // Vb = sum_{k>=1} (M w_k^2 q_k^2 / 2 + lam q1 q_k), so H = Hess E_l is an
@@ -61,46 +62,237 @@ __device__ inline StageCoef<T> stage_coef(const DevModel &md, const QcleF &mf, i
   return c;
 }
 
-// One Runge-Kutta stage ST of the FP64 path.  The stage values ys have been
-// published to s; the derivative of each owned value is formed and folded
-// at once into the accumulator and the next stage:
-//   stage 0: acc = k;            ys = y0 + c k
-//   stage 1, 2: acc += 2 k;      ys = y0 + c k
-//   stage 3: acc = y0 + h6 (acc + k)   (the step's result)
-// The stage has no branches: every slot is evaluated (a slot without a pair
-// group reads group (0, 0) and gets a zero derivative), so that the pair
-// groups, which do not depend on the two-level quantities unless a or b is
-// 0, can be scheduled together with their evaluation.
-template <int D, int LPB, int ST>
+// 32-bit LDS addresses.  A workgroup's exchange areas lie below 64 KiB, so
+// two addresses share a word.  Complex entries move as one 16-byte vector.
+template <typename X>
+using Lds3 = __attribute__((address_space(3))) X;
+typedef double Dbl2 __attribute__((ext_vector_type(2)));
+template <typename X>
+__device__ inline uint32_t lds_addr(const X *p) {
+  return (uint32_t)(uintptr_t)(const Lds3<X> *)p;
+}
+__device__ inline double lds_get_d(uint32_t a) { return *(const Lds3<double> *)(size_t)a; }
+__device__ inline Cx2<double> lds_get_c(uint32_t a) {
+  const Dbl2 v = *(const Lds3<Dbl2> *)(size_t)a;
+  return Cx2<double>{v.x, v.y};
+}
+__device__ inline void lds_put_c(uint32_t a, double re, double im) {
+  Dbl2 v;
+  v.x = re;
+  v.y = im;
+  *(Lds3<Dbl2> *)(size_t)a = v;
+}
+
+// The LDS addresses of the operands of a lane's pair-group slots (FP64
+// stage loop), formed once per call.  Each stage takes them through an
+// empty asm statement, so that the compiler does not hoist what it derives
+// from them out of the stage loop (the derived addresses would not fit in
+// the registers of two wavefronts per SIMD).
+template <int D, int LPB>
+struct PgAddr {
+  static constexpr int NG = PG<D, LPB>::NG;
+  uint32_t wr[NG];  // Zrp_ab | Zrp_ba << 16 (the Zpp entries at a fixed distance)
+  uint32_t xt[NG];  // the cross operands of (Zrp H)_ab and (Zrp H)_ba: xo | to << 16
+  uint32_t uw[NG];  // the cross operands of (H Zpp)_ab and (H Zpp)_ba: uo | wo << 16
+  uint32_t hh[NG];  // hk[a] | hk[b] << 16
+  uint32_t home;    // the lane's first pair of home values (see TileLds)
+};
+
+// Values of the interval's starting state kept in LDS instead of registers:
+// the first HS pair-group slots of an FP64 d = 12 beam (16 values a lane),
+// so that the stage loop of two wavefronts per SIMD fits in the register
+// file.  Per wavefront, value v of lane l sits at pair v / 2, lane l:
+// home + (v / 2) kHomePair + (v % 2) 8 bytes (16-byte lane stride, no bank
+// conflicts).
+template <int D, typename TS>
+constexpr int home_slots() {
+  return (D == 12 && sizeof(TS) == sizeof(double)) ? 2 : 0;
+}
+constexpr uint32_t kHomePair = 64 * 16;
+__device__ inline double home_get(uint32_t home, int v) { return lds_get_d(home + (v / 2) * kHomePair + (v % 2) * 8); }
+__device__ inline void home_put2(uint32_t home, int v, double a, double b) {
+  lds_put_c(home + (v / 2) * kHomePair, a, b);
+}
+
+// A workgroup's LDS: the exchange areas (first, so that their addresses fit
+// in 16 bits) and the home values of its wavefronts.
+template <int D, int LPB, typename TS, int WPB>
+struct TileLds {
+  static constexpr int HS = home_slots<D, TS>();
+  PgLds<D, TS> ex[WPB * PG<D, LPB>::G];
+  Dbl2 home[WPB][HS > 0 ? HS * kGrpN / 2 : 1][64];
+};
+
+template <int D, int LPB>
+__device__ inline PgAddr<D, LPB> pg_addr(const PgCtx<D, LPB, double> &cx, const PgLds<D, double> &s) {
+  PgAddr<D, LPB> ad;
+#pragma unroll
+  for (int e = 0; e < PG<D, LPB>::NG; ++e) {
+    const int a = cx.a[e] >= 0 ? cx.a[e] : 0, b = cx.a[e] >= 0 ? cx.b[e] : 0;
+    const uint32_t xo = lds_addr(b > 0 ? &s.rp[a][0] : &s.rho[a]), to = lds_addr(a > 0 ? &s.rp[b][0] : &s.rho[b]);
+    const uint32_t uo = lds_addr(a > 0 ? &s.pp[0][b] : &s.chi[b]), wo = lds_addr(b > 0 ? &s.pp[0][a] : &s.chi[a]);
+    ad.wr[e] = lds_addr(&s.rp[a][b]) | lds_addr(&s.rp[b][a]) << 16;
+    ad.xt[e] = xo | to << 16;
+    ad.uw[e] = uo | wo << 16;
+    ad.hh[e] = lds_addr(&s.hk[a]) | lds_addr(&s.hk[b]) << 16;
+  }
+  return ad;
+}
+
+template <int D, int LPB>
+__device__ inline void pg_ctx_opaque(PgCtx<D, LPB, double> &cx) {
+#pragma unroll
+  for (int e = 0; e < PG<D, LPB>::NG; ++e) {
+    asm volatile("" : "+v"(cx.a[e]));
+    asm volatile("" : "+v"(cx.b[e]));
+  }
+  asm volatile("" : "+v"(cx.r));
+}
+
+template <int D, int LPB>
+__device__ inline void pg_addr_opaque(PgAddr<D, LPB> &ad) {
+#pragma unroll
+  for (int e = 0; e < PG<D, LPB>::NG; ++e) {
+    asm volatile("" : "+v"(ad.wr[e]));
+    asm volatile("" : "+v"(ad.xt[e]));
+    asm volatile("" : "+v"(ad.uw[e]));
+    asm volatile("" : "+v"(ad.hh[e]));
+  }
+  asm volatile("" : "+v"(ad.home));
+}
+
+// Publish the stage values (FP64 stage loop): pg_publish with the slots'
+// addresses taken from ad.
+template <int D, int LPB>
+__device__ inline void pg_publish_ad(const PgCtx<D, LPB, double> &cx, const PgAddr<D, LPB> &ad,
+                                     const PgY<D, LPB, double> &y, PgLds<D, double> &s) {
+  constexpr uint32_t kPp = (uint32_t)(D * (D + 1) * sizeof(Cx2<double>));   // Zpp after Zrp
+  static_assert(sizeof(s.rp) == kPp, "Zpp directly after Zrp");
+#pragma unroll
+  for (int e = 0; e < PG<D, LPB>::NG; ++e) {
+    if ((e + 1) * LPB <= PG<D, LPB>::NGRP || cx.a[e] >= 0) {
+      const double *v = y.g[e].v;
+      const uint32_t ab = ad.wr[e] & 0xffffu, ba = ad.wr[e] >> 16;
+      lds_put_c(ab, v[kAbR], v[kAbI]);
+      lds_put_c(ba, v[kBaR], v[kBaI]);   // a == b: the same entry, written twice with one value
+      lds_put_c(ab + kPp, v[kPpR], v[kPpI]);
+      lds_put_c(ba + kPp, v[kPpR], v[kPpI]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PG<D, LPB>::NXP; ++j) {
+    const int c = cx.r + LPB * j;
+    if (c < 2 * D) { s.x[c] = y.x[j]; s.p[c] = y.p[j]; }
+  }
+  wave_lds_sync();
+  pg_sums(cx, s);
+  wave_lds_sync();
+}
+
+// One Runge-Kutta stage of the FP64 path.  The stage values ys have been
+// published to s; the derivative k of each owned value is formed and folded
+// at once into the accumulator (zero before stage 0) and the next stage:
+//   acc += w k (w = 1, 2, 2, 1),  ys = y0 + c k (c = h/2, h/2, h; 0 in the
+//   last stage, whose ys is not used)
+// and the step's result is y0 + h/6 acc (pg_finish).  Every slot is
+// evaluated: a slot without a pair group reads the operands of group
+// (0, 0) and folds with weights 0, so its values stay 0.  The folds are
+// explicit fused multiply-adds, so that every form of the step rounds alike.
+// The pair-group derivatives are those of grp_deriv, with operands read
+// from the addresses in ad.
+template <int D, int LPB, int HS>
 __device__ inline void pg_stage(const DevModel &md, const QcleF &mf, int l, const PgCtx<D, LPB, double> &cx,
-                                const PgY<D, LPB, double> &y0, PgY<D, LPB, double> &ys, PgY<D, LPB, double> &acc,
-                                double c, double h6, const PgLds<D, double> &s) {
+                                const PgAddr<D, LPB> &ad, const PgY<D, LPB, double> &y0,
+                                PgY<D, LPB, double> &ys, PgY<D, LPB, double> &acc, double w, double c,
+                                const PgLds<D, double> &s) {
   using C = PG<D, LPB>;
   const StageCoef<double> sc = stage_coef<D, double>(md, mf, l, s);
-  auto fold = [&](double &a, double &yv, double y0v, double d) {
-    if constexpr (ST == 0) a = d;
-    else if constexpr (ST < 3) a = a + 2.0 * d;
-    else a = y0v + h6 * (a + d);
-    if constexpr (ST < 3) yv = y0v + c * d;
-  };
+  const double lam = sc.lam, im = sc.im;
+  // The slots one after another: each slot's LDS reads wait (through an
+  // empty asm statement) for the previous slot's last result, the first
+  // slot's for the two-level quantities, so that the reads of all slots are
+  // not issued ahead together (their operands would not fit in the
+  // registers of two wavefronts per SIMD).
+  double dep0 = sc.H00, dep1 = sc.B00, dep2 = sc.H00;
 #pragma unroll
   for (int e = 0; e < C::NG; ++e) {
-    const bool live = (e + 1) * LPB <= C::NGRP || cx.a[e] >= 0;
+    const bool full = (e + 1) * LPB <= C::NGRP, live = full || cx.a[e] >= 0;
+    const bool a0 = cx.a[e] <= 0, b0 = !live || cx.b[e] == 0;    // index 0 (a dead slot: group (0, 0))
+    const double we = live ? w : 0.0, ce = live ? c : 0.0;
+    const double *v = ys.g[e].v;
+    uint32_t hh = ad.hh[e], xt = ad.xt[e], uw = ad.uw[e], home = ad.home;
+    asm volatile("" : "+v"(hh), "+v"(xt), "+v"(uw), "+v"(home) : "v"(dep0), "v"(dep1), "v"(dep2));
+    const double hka = lds_get_d(hh & 0xffffu), hkb = lds_get_d(hh >> 16);   // read unconditionally
+    const double Ha = a0 ? sc.H00 : hka, Hb = b0 ? sc.H00 : hkb;
+    const Cx2<double> xo = lds_get_c(xt & 0xffffu), to = lds_get_c(xt >> 16);
+    const Cx2<double> uo = lds_get_c(uw & 0xffffu), wo = lds_get_c(uw >> 16);
     double d[kGrpN];
-    grp_deriv<D, double>(live ? cx.a[e] : 0, live ? cx.b[e] : 0, sc, ys.g[e].v, s, d);
+    // Zrr_ab' = (Zrp H)_ab + (Zrp H)_ba (+ i B at (0, 0))
+    double xr = v[kAbR] * Hb, xi = v[kAbI] * Hb;
+    xr += lam * xo.re;
+    xi += lam * xo.im;
+    double tr = v[kBaR] * Ha, ti = v[kBaI] * Ha;
+    tr += lam * to.re;
+    ti += lam * to.im;
+    d[kRrR] = xr + tr;
+    d[kRrI] = (xi + ti) + ((a0 && b0) ? sc.B00 : 0.0);
+    // Zrp_ab' = (H Zpp)_ab - Zrr_ab / M,  Zrp_ba' = (H Zpp)_ba - Zrr_ba / M
+    double ur = Ha * v[kPpR], ui = Ha * v[kPpI];
+    ur += lam * uo.re;
+    ui += lam * uo.im;
+    double wr = Hb * v[kPpR], wi = Hb * v[kPpI];
+    wr += lam * wo.re;
+    wi += lam * wo.im;
+    d[kAbR] = ur - v[kRrR] * im;
+    d[kAbI] = ui - v[kRrI] * im;
+    d[kBaR] = wr - v[kRrR] * im;
+    d[kBaI] = wi - v[kRrI] * im;
+    // Zpp_ab' = -(Zrp_ba + Zrp_ab) / M
+    d[kPpR] = -(v[kBaR] + v[kAbR]) * im;
+    d[kPpI] = -(v[kBaI] + v[kAbI]) * im;
 #pragma unroll
-    for (int j = 0; j < kGrpN; ++j) fold(acc.g[e].v[j], ys.g[e].v[j], y0.g[e].v[j], live ? d[j] : 0.0);
+    for (int j = 0; j < kGrpN; ++j) {
+      acc.g[e].v[j] = fma(we, d[j], acc.g[e].v[j]);
+      ys.g[e].v[j] = fma(ce, d[j], e < HS ? home_get(home, e * kGrpN + j) : y0.g[e].v[j]);
+    }
+    // the slot's results are complete before the next slot's reads
+#pragma unroll
+    for (int j = 0; j < kGrpN; ++j) asm volatile("" : "+v"(acc.g[e].v[j]), "+v"(ys.g[e].v[j]));
+    dep0 = ys.g[e].v[kRrR];
+    dep1 = ys.g[e].v[kAbR];
+    dep2 = ys.g[e].v[kBaR];
   }
 #pragma unroll
   for (int j = 0; j < C::NXP; ++j) {
     double dx, dp;
     xp_deriv<D, double>(cx.r + LPB * j, sc, s, dx, dp);
-    fold(acc.x[j], ys.x[j], y0.x[j], dx);
-    fold(acc.p[j], ys.p[j], y0.p[j], dp);
+    acc.x[j] = fma(w, dx, acc.x[j]);
+    ys.x[j] = fma(c, dx, y0.x[j]);
+    acc.p[j] = fma(w, dp, acc.p[j]);
+    ys.p[j] = fma(c, dp, y0.p[j]);
   }
-  double dS = sc.bc * sc.k.s, dL = 2.0 * fabs(s.x[D] * sc.im * sc.k.d21), unused = 0.0;
-  fold(acc.S, unused, y0.S, dS);
-  fold(acc.Lam, unused, y0.Lam, dL);
+  const double dS = sc.bc * sc.k.s, dL = 2.0 * fabs(s.x[D] * sc.im * sc.k.d21);
+  acc.S = fma(w, dS, acc.S);
+  acc.Lam = fma(w, dL, acc.Lam);
+}
+
+// The step's result from the accumulated slopes: out = y0 + h6 out (the
+// first HS slots of y0 at home).
+template <int D, int LPB, int HS>
+__device__ inline void pg_finish(const PgY<D, LPB, double> &y0, uint32_t home, double h6,
+                                 PgY<D, LPB, double> &out) {
+#pragma unroll
+  for (int e = 0; e < PG<D, LPB>::NG; ++e)
+#pragma unroll
+    for (int j = 0; j < kGrpN; ++j)
+      out.g[e].v[j] = fma(h6, out.g[e].v[j], e < HS ? home_get(home, e * kGrpN + j) : y0.g[e].v[j]);
+#pragma unroll
+  for (int j = 0; j < PG<D, LPB>::NXP; ++j) {
+    out.x[j] = fma(h6, out.x[j], y0.x[j]);
+    out.p[j] = fma(h6, out.p[j], y0.p[j]);
+  }
+  out.S = fma(h6, out.S, y0.S);
+  out.Lam = fma(h6, out.Lam, y0.Lam);
 }
 
 // The stage record of stage values y at q (when q is given): the values
@@ -125,32 +317,45 @@ __device__ inline void pg_record(const PgCtx<D, LPB, double> &cx, const PgY<D, L
   }
 }
 
+template <int D, int LPB>
+__device__ inline void pg_zero(PgY<D, LPB, double> &y) {
+#pragma unroll
+  for (int e = 0; e < PG<D, LPB>::NG; ++e)
+#pragma unroll
+    for (int j = 0; j < kGrpN; ++j) y.g[e].v[j] = 0.0;
+#pragma unroll
+  for (int j = 0; j < PG<D, LPB>::NXP; ++j) y.x[j] = y.p[j] = 0.0;
+  y.S = y.Lam = 0.0;
+}
+
 // One classical RK4 step of the group's beam on its component, into `out`;
-// `s` is clobbered.  REC: the four stage records go to rec when it is given.
-template <int D, int LPB, bool REC = false>
-__device__ inline void pg_rk4(const DevModel &md, const QcleF &mf, const HopCtx &hc, const PgCtx<D, LPB, double> &cx,
-                              const PgY<D, LPB, double> &y, double h, PgY<D, LPB, double> &out,
-                              PgLds<D, double> &s, double *rec = nullptr) {
+// `s` is clobbered.  The four stages run as a loop: one copy of the stage
+// code, whose live set (not that of four interleaved stages) decides the
+// registers, so that two wavefronts fit on a SIMD.  REC: the stage records
+// go to rec when it is given.
+template <int D, int LPB, int HS, bool REC = false>
+__device__ inline void pg_rk4(const DevModel &md, const QcleF &mf, const HopCtx &hc, PgCtx<D, LPB, double> &cx,
+                              PgAddr<D, LPB> &ad, const PgY<D, LPB, double> &y, double h,
+                              PgY<D, LPB, double> &out, PgLds<D, double> &s, double *rec = nullptr) {
   constexpr int SR = adj_stage_rec(D);
   PgY<D, LPB, double> ys = y;
-  const double h6 = h * (1.0 / 6.0);
+#pragma unroll
+  for (int e = 0; e < HS; ++e)
+#pragma unroll
+    for (int j = 0; j < kGrpN; ++j) ys.g[e].v[j] = home_get(ad.home, e * kGrpN + j);
   const int l = hc.h.comp;
-  if constexpr (REC) pg_record(cx, ys, rec);
-  pg_publish(cx, ys, s);
-  pg_stage<D, LPB, 0>(md, mf, l, cx, y, ys, out, 0.5 * h, h6, s);
-  wave_lds_sync();
-  if constexpr (REC) pg_record(cx, ys, rec ? rec + SR : rec);
-  pg_publish(cx, ys, s);
-  pg_stage<D, LPB, 1>(md, mf, l, cx, y, ys, out, 0.5 * h, h6, s);
-  wave_lds_sync();
-  if constexpr (REC) pg_record(cx, ys, rec ? rec + 2 * SR : rec);
-  pg_publish(cx, ys, s);
-  pg_stage<D, LPB, 2>(md, mf, l, cx, y, ys, out, h, h6, s);
-  wave_lds_sync();
-  if constexpr (REC) pg_record(cx, ys, rec ? rec + 3 * SR : rec);
-  pg_publish(cx, ys, s);
-  pg_stage<D, LPB, 3>(md, mf, l, cx, y, ys, out, 0.0, h6, s);
-  wave_lds_sync();
+  pg_zero(out);
+#pragma unroll 1
+  for (int st = 0; st < 4; ++st) {
+    if constexpr (REC) pg_record(cx, ys, rec ? rec + st * SR : rec);
+    pg_ctx_opaque(cx);
+    pg_addr_opaque(ad);
+    pg_publish_ad(cx, ad, ys, s);
+    pg_stage<D, LPB, HS>(md, mf, l, cx, ad, y, ys, out, (st == 0 || st == 3) ? 1.0 : 2.0,
+                         st == 3 ? 0.0 : (st == 2 ? h : 0.5 * h), s);
+    wave_lds_sync();
+  }
+  pg_finish<D, LPB, HS>(y, ad.home, h * (1.0 / 6.0), out);
 }
 
 // Mixed precision: one stage with FP32 stage values and accumulator; stage 3
@@ -238,9 +443,9 @@ __device__ inline void pg_add_inc(PgY<D, LPB, double> &y, const PgY<D, LPB, floa
 // interpolated hop time, the hop (at the state reached), and the rest of
 // the interval.  MIXED selects the
 // mixed-precision step.
-template <int D, int LPB, bool MIXED, bool REC = false>
-__device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const PgCtx<D, LPB, double> &cx,
-                                   const PgCtx<D, LPB, float> &cxf, int base, PgY<D, LPB, double> &y, HopCtx &hc,
+template <int D, int LPB, bool MIXED, int HS, bool REC = false>
+__device__ inline void pg_interval(const DevModel &md, const QcleF &mf, PgCtx<D, LPB, double> &cx,
+                                   const PgCtx<D, LPB, float> &cxf, PgAddr<D, LPB> &ad, int base, PgY<D, LPB, double> &y, HopCtx &hc,
                                    double dt, Counters &cnt, void *lds, double *rec = nullptr) {
   const double tie_rel = MIXED ? kTieRelMixed : kTieRel;
   double rem = dt, hstep = dt, theta = 1.0;
@@ -250,14 +455,21 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const Pg
   YN yn;  // FP64: the trial result; mixed: the trial increment
   auto trial = [&](double hh, double *rq) {
     if constexpr (MIXED) pg_rk4_m(md, mf, hc, cnt, cxf, y, hh, yn, *(PgLds<D, float> *)lds);
-    else pg_rk4<D, LPB, REC>(md, mf, hc, cx, y, hh, yn, *(PgLds<D, double> *)lds, rq);
+    else pg_rk4<D, LPB, HS, REC>(md, mf, hc, cx, ad, y, hh, yn, *(PgLds<D, double> *)lds, rq);
   };
   // REC: the first trial step's stage records, then the interval's component
   // and whether it has a hop (the trial step is not its whole result)
   const int comp0 = hc.h.comp;
   auto accept = [&]() {
-    if constexpr (MIXED) pg_add_inc(y, yn);
-    else y = yn;
+    if constexpr (MIXED) {
+      pg_add_inc(y, yn);
+    } else {
+      y = yn;
+#pragma unroll
+      for (int e = 0; e < HS; ++e)
+#pragma unroll
+        for (int j = 0; j < kGrpN; j += 2) home_put2(ad.home, e * kGrpN + j, yn.g[e].v[j], yn.g[e].v[j + 1]);
+    }
   };
   for (;;) {
     trial(hstep, (REC && hops == 0 && !partial) ? rec : nullptr);
@@ -299,7 +511,7 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const Pg
     } else {
       const double q1 = __shfl(y.x[0], base, 64), p1 = __shfl(y.x[D / LPB], base + D % LPB, 64);
       const Q1 k = qcle_q1(md, q1);
-      hop_choose(p1 * md.inv_mass * k.d21, hc.h, hc.gid, hc.seed, cnt, kTieRel);
+      hop_choose_call(p1 * md.inv_mass * k.d21, hc.h, hc.gid, hc.seed, cnt, kTieRel);
     }
     hc.pending = false;
     ++hops;
@@ -310,12 +522,12 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, const Pg
 }
 
 constexpr int kWavesPerBlock = 4;
-// Lanes per d = 12 beam: 32, two beams per wavefront.  FP64 stage values
-// fill the register file of one wave per SIMD; their stage has no branches,
-// so the scheduler overlaps the pair groups with the two-level quantities
-// (with 16 lanes per beam that schedule spills).  FP32 stage values keep two
-// waves per SIMD; there the branch-free stage spills, so the mixed stage
-// keeps its branches.
+// Lanes per d = 12 beam: 32, two beams per wavefront, two wavefronts per
+// SIMD for both precisions.  The FP64 stage runs as a loop over the four
+// stages with the slots in sequence and two slots of the interval's state
+// in LDS (TileLds), which keeps it within 256 registers without spills; at
+// 16 lanes per beam the three copies of the state alone need 276.  The FP32
+// stage keeps its branches (branch-free, it spills at two waves per SIMD).
 constexpr int kLanesPerBeamD12 = 32;
 
 // All nsteps intervals of the beams of one tile (WPB waves, 64/LPB beams
@@ -326,8 +538,10 @@ template <int D, int LPB, typename TS, int WPB, bool REC = false>
 __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double *__restrict__ sc,
                                  int32_t *__restrict__ comp, uint32_t *__restrict__ nhop, int64_t n, int64_t ld,
                                  uint64_t gid0, int nsteps, double dt, uint64_t seed, int64_t tile,
-                                 PgLds<D, TS> *lds, Counters &cnt_out, double *__restrict__ recs = nullptr,
+                                 TileLds<D, LPB, TS, WPB> &tl, Counters &cnt_out, double *__restrict__ recs = nullptr,
                                  int every = 0) {
+  constexpr int HS = TileLds<D, LPB, TS, WPB>::HS;
+  PgLds<D, TS> *lds = tl.ex;
   using C = PG<D, LPB>;
   constexpr int M = C::M;
   constexpr bool MIXED = sizeof(TS) == sizeof(float);
@@ -386,10 +600,23 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
     hc.gid = gid0 + (uint64_t)b;
     hc.seed = seed;
     pg_fill_const<D, LPB>(r, md.bath_k, lds[slot]);
+    PgAddr<D, LPB> ad{};
+    if constexpr (!MIXED) {
+      ad = pg_addr(cx, lds[slot]);
+      ad.home = lds_addr(&tl.home[wid][0][lane]);
+#pragma unroll
+      for (int e = 0; e < HS; ++e)
+#pragma unroll
+        for (int j = 0; j < kGrpN; j += 2) home_put2(ad.home, e * kGrpN + j, y.g[e].v[j], y.g[e].v[j + 1]);
+    }
     for (int st = 0; st < nsteps; ++st)
-      pg_interval<D, LPB, MIXED, REC>(md, mf, cx, cxf, base, y, hc, dt, cnt, (void *)&lds[slot],
+      pg_interval<D, LPB, MIXED, HS, REC>(md, mf, cx, cxf, ad, base, y, hc, dt, cnt, (void *)&lds[slot],
                                       REC ? recs + ((int64_t)b * every + st) * adj_interval_rec(D) : nullptr);
     // (every hop is completed where it starts, so none is pending here)
+#pragma unroll
+    for (int e = 0; e < HS; ++e)
+#pragma unroll
+      for (int j = 0; j < kGrpN; ++j) y.g[e].v[j] = home_get(ad.home, e * kGrpN + j);
     // finiteness of the values this lane owns (slots without a pair group
     // or coordinate hold no state)
     double chk = y.S + y.Lam + h.logw;
@@ -469,26 +696,26 @@ constexpr int tiles_per_line() {
 }
 
 template <int D, int LPB, typename TS>
-__global__ void __launch_bounds__(64 * kWavesPerBlock)
-__attribute__((amdgpu_waves_per_eu(sizeof(TS) == sizeof(float) ? 2 : 1)))
+__global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(2)))
 step_wave_kernel(DevModel md, TS *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
                  uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps, double dt,
                  uint64_t seed, uint64_t *diag) {
-  __shared__ PgLds<D, TS> lds[kWavesPerBlock * PG<D, LPB>::G];
+  __shared__ TileLds<D, LPB, TS, kWavesPerBlock> tl;
+  static_assert(sizeof(tl.ex) <= 65536, "16-bit LDS addresses (PgAddr)");
   Counters cnt;
   wave_tile<D, LPB, TS, kWavesPerBlock>(md, tr, sc, comp, nhop, n, ld, gid0, nsteps, dt, seed,
-                                        xcd_line_tile<tiles_per_line<D, LPB, TS>()>(blockIdx.x, gridDim.x), lds, cnt);
+                                        xcd_line_tile<tiles_per_line<D, LPB, TS>()>(blockIdx.x, gridDim.x), tl, cnt);
   flush_counters(cnt, diag);
 }
 
 // Persistent form for a batch: each workgroup takes tiles from the queue
 // until none is left; the tile decides the instance (model and state).
 template <int D, int LPB, typename TS, int WPB>
-__global__ void __launch_bounds__(64 * WPB)
-__attribute__((amdgpu_waves_per_eu(sizeof(TS) == sizeof(float) ? 2 : 1)))
+__global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(2)))
 step_wave_batched(const BatchItem *__restrict__ items, int n_items, int64_t total_tiles, int grab, int nsteps,
                   double dt, unsigned long long *queue, uint64_t *diag) {
-  __shared__ PgLds<D, TS> lds[WPB * PG<D, LPB>::G];
+  __shared__ TileLds<D, LPB, TS, WPB> tl;
+  static_assert(sizeof(tl.ex) <= 65536, "16-bit LDS addresses (PgAddr)");
   Counters cnt;
   for (;;) {
     const int64_t t0 = batch_grab(queue, grab);
@@ -497,7 +724,7 @@ step_wave_batched(const BatchItem *__restrict__ items, int n_items, int64_t tota
     for (int64_t t = t0; t < t1; ++t) {
       const BatchItem &it = items[batch_find(items, n_items, t)];
       wave_tile<D, LPB, TS, WPB>(it.md, (TS *)it.tr, it.sc, it.comp, it.nhop, it.n, it.ld, it.gid0, nsteps, dt,
-                                 it.seed, t - it.tile0, lds, cnt);
+                                 it.seed, t - it.tile0, tl, cnt);
       __syncthreads();
     }
   }
@@ -509,15 +736,16 @@ step_wave_batched(const BatchItem *__restrict__ items, int n_items, int64_t tota
 // replay of a segment for the reverse sweep; records of beam b, interval i at
 // recs + (b every + i) adj_interval_rec(d)).
 template <int D, int LPB>
-__global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(1)))
+__global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(2)))
 step_wave_rec_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
                      uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps, double dt,
                      uint64_t seed, double *__restrict__ recs, int every) {
-  __shared__ PgLds<D, double> lds[kWavesPerBlock * PG<D, LPB>::G];
+  __shared__ TileLds<D, LPB, double, kWavesPerBlock> tl;
+  static_assert(sizeof(tl.ex) <= 65536, "16-bit LDS addresses (PgAddr)");
   Counters cnt;
   wave_tile<D, LPB, double, kWavesPerBlock, true>(md, tr, sc, comp, nhop, n, ld, gid0, nsteps, dt, seed,
                                                   xcd_line_tile<tiles_per_line<D, LPB, double>()>(blockIdx.x, gridDim.x),
-                                                  lds, cnt, recs, every);
+                                                  tl, cnt, recs, every);
 }
 
 template <int D, int LPB>
