@@ -95,6 +95,7 @@ struct PgAddr {
   uint32_t xt[NG];  // the cross operands of (Zrp H)_ab and (Zrp H)_ba: xo | to << 16
   uint32_t uw[NG];  // the cross operands of (H Zpp)_ab and (H Zpp)_ba: uo | wo << 16
   uint32_t hh[NG];  // hk[a] | hk[b] << 16
+  uint32_t sum;     // the lane's sum task: its row's entry 0 | the output << 16
   uint32_t home;    // the lane's first pair of home values (see TileLds)
 };
 
@@ -136,6 +137,17 @@ __device__ inline PgAddr<D, LPB> pg_addr(const PgCtx<D, LPB, double> &cx, const 
     ad.uw[e] = uo | wo << 16;
     ad.hh[e] = lds_addr(&s.hk[a]) | lds_addr(&s.hk[b]) << 16;
   }
+  // Sum task t = min(r, 2d): the row sums over k > 0 of Zrp (rho_t), of Zpp
+  // (chi_{t-d}: Zpp is symmetric and stored in both triangles, so its row
+  // sums are its column sums, term by term) and of the coordinate pairs
+  // (sx, sp).  Every task reads a row of complex entries 16 bytes apart.
+  const int t = cx.r < 2 * D ? cx.r : 2 * D;
+  const Cx2<double> *row = t < D ? &s.rp[t][0] : (t < 2 * D ? &s.pp[t - D][0] : &s.xq[0]);
+  const uint32_t out = t < D ? lds_addr(&s.rho[t]) : (t < 2 * D ? lds_addr(&s.chi[t - D]) : lds_addr(&s.sx));
+  using S = PgLds<D, double>;
+  static_assert(offsetof(S, sp) == offsetof(S, sx) + sizeof(double) && offsetof(S, sx) % 16 == 0,
+                "sx and sp as one complex entry");
+  ad.sum = lds_addr(row) | out << 16;
   return ad;
 }
 
@@ -158,6 +170,7 @@ __device__ inline void pg_addr_opaque(PgAddr<D, LPB> &ad) {
     asm volatile("" : "+v"(ad.uw[e]));
     asm volatile("" : "+v"(ad.hh[e]));
   }
+  asm volatile("" : "+v"(ad.sum));
   asm volatile("" : "+v"(ad.home));
 }
 
@@ -182,10 +195,29 @@ __device__ inline void pg_publish_ad(const PgCtx<D, LPB, double> &cx, const PgAd
 #pragma unroll
   for (int j = 0; j < PG<D, LPB>::NXP; ++j) {
     const int c = cx.r + LPB * j;
-    if (c < 2 * D) { s.x[c] = y.x[j]; s.p[c] = y.p[j]; }
+    if (c < 2 * D) {
+      s.x[c] = y.x[j];
+      s.p[c] = y.p[j];
+      if (c < D) s.xq[c].re = y.x[j];      // X_c (entry 0 is not summed)
+      else s.xq[c - D].im = y.p[j];        // P_c, c = d + k
+    }
   }
   wave_lds_sync();
-  pg_sums(cx, s);
+  if constexpr (2 * D + 1 <= LPB) {
+    // the lane's sum task (lanes past the last task repeat it: the same
+    // values to the same place), in the order of pg_sum_task
+    const uint32_t row = ad.sum & 0xffffu;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int k = 1; k < D; ++k) {
+      const Cx2<double> v = lds_get_c(row + 16 * k);
+      sr += v.re;
+      si += v.im;
+    }
+    lds_put_c(ad.sum >> 16, sr, si);
+  } else {
+    pg_sums(cx, s);   // more tasks than lanes: round robin
+  }
   wave_lds_sync();
 }
 

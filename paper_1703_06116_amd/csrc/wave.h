@@ -51,6 +51,7 @@ struct PgLds {
   T x[2 * D], p[2 * D];
   T sx, sp;
   T hk[D];           // H_kk = M w_k^2 for k > 0 (hk[0] is not used)
+  Cx2<T> xq[D];      // (X_k, P_d+k) side by side, k > 0: the coordinate sums as a row (FP64 stage loop)
 };
 
 // Fill the constant part of the exchange area (before the first publish,
