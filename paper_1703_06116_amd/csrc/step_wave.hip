@@ -110,7 +110,8 @@ constexpr int home_slots() {
   return (D == 12 && sizeof(TS) == sizeof(double)) ? 2 : 0;
 }
 constexpr uint32_t kHomePair = 64 * 16;
-__device__ inline double home_get(uint32_t home, int v) { return lds_get_d(home + (v / 2) * kHomePair + (v % 2) * 8); }
+// values v and v + 1 (v even) as one 16-byte access
+__device__ inline Cx2<double> home_get2(uint32_t home, int v) { return lds_get_c(home + (v / 2) * kHomePair); }
 __device__ inline void home_put2(uint32_t home, int v, double a, double b) {
   lds_put_c(home + (v / 2) * kHomePair, a, b);
 }
@@ -227,8 +228,9 @@ __device__ inline void pg_publish_ad(const PgCtx<D, LPB, double> &cx, const PgAd
 //   acc += w k (w = 1, 2, 2, 1),  ys = y0 + c k (c = h/2, h/2, h; 0 in the
 //   last stage, whose ys is not used)
 // and the step's result is y0 + h/6 acc (pg_finish).  Every slot is
-// evaluated: a slot without a pair group reads the operands of group
-// (0, 0) and folds with weights 0, so its values stay 0.  The folds are
+// evaluated: a slot without a pair group computes with the operands of
+// group (0, 0) values that nothing reads (they are not published, checked
+// or stored).  The folds are
 // explicit fused multiply-adds, so that every form of the step rounds alike.
 // The pair-group derivatives are those of grp_deriv, with operands read
 // from the addresses in ad.
@@ -248,9 +250,10 @@ __device__ inline void pg_stage(const DevModel &md, const QcleF &mf, int l, cons
   double dep0 = sc.H00, dep1 = sc.B00, dep2 = sc.H00;
 #pragma unroll
   for (int e = 0; e < C::NG; ++e) {
-    const bool full = (e + 1) * LPB <= C::NGRP, live = full || cx.a[e] >= 0;
-    const bool a0 = cx.a[e] <= 0, b0 = !live || cx.b[e] == 0;    // index 0 (a dead slot: group (0, 0))
-    const double we = live ? w : 0.0, ce = live ? c : 0.0;
+    // index 0 occurs in the first slot only (groups (0, b) come first); a
+    // slot without a group reads the operands of group (0, 0)
+    const bool can0 = e * LPB < D;
+    const bool a0 = can0 && cx.a[e] <= 0, b0 = can0 && cx.b[e] <= 0;
     const double *v = ys.g[e].v;
     uint32_t hh = ad.hh[e], xt = ad.xt[e], uw = ad.uw[e], home = ad.home;
     asm volatile("" : "+v"(hh), "+v"(xt), "+v"(uw), "+v"(home) : "v"(dep0), "v"(dep1), "v"(dep2));
@@ -283,9 +286,12 @@ __device__ inline void pg_stage(const DevModel &md, const QcleF &mf, int l, cons
     d[kPpR] = -(v[kBaR] + v[kAbR]) * im;
     d[kPpI] = -(v[kBaI] + v[kAbI]) * im;
 #pragma unroll
-    for (int j = 0; j < kGrpN; ++j) {
-      acc.g[e].v[j] = fma(we, d[j], acc.g[e].v[j]);
-      ys.g[e].v[j] = fma(ce, d[j], e < HS ? home_get(home, e * kGrpN + j) : y0.g[e].v[j]);
+    for (int j = 0; j < kGrpN; j += 2) {
+      const Cx2<double> h2 = e < HS ? home_get2(home, e * kGrpN + j) : Cx2<double>{y0.g[e].v[j], y0.g[e].v[j + 1]};
+      acc.g[e].v[j] = fma(w, d[j], acc.g[e].v[j]);
+      ys.g[e].v[j] = fma(c, d[j], h2.re);
+      acc.g[e].v[j + 1] = fma(w, d[j + 1], acc.g[e].v[j + 1]);
+      ys.g[e].v[j + 1] = fma(c, d[j + 1], h2.im);
     }
     // the slot's results are complete before the next slot's reads
 #pragma unroll
@@ -316,8 +322,11 @@ __device__ inline void pg_finish(const PgY<D, LPB, double> &y0, uint32_t home, d
 #pragma unroll
   for (int e = 0; e < PG<D, LPB>::NG; ++e)
 #pragma unroll
-    for (int j = 0; j < kGrpN; ++j)
-      out.g[e].v[j] = fma(h6, out.g[e].v[j], e < HS ? home_get(home, e * kGrpN + j) : y0.g[e].v[j]);
+    for (int j = 0; j < kGrpN; j += 2) {
+      const Cx2<double> h2 = e < HS ? home_get2(home, e * kGrpN + j) : Cx2<double>{y0.g[e].v[j], y0.g[e].v[j + 1]};
+      out.g[e].v[j] = fma(h6, out.g[e].v[j], h2.re);
+      out.g[e].v[j + 1] = fma(h6, out.g[e].v[j + 1], h2.im);
+    }
 #pragma unroll
   for (int j = 0; j < PG<D, LPB>::NXP; ++j) {
     out.x[j] = fma(h6, out.x[j], y0.x[j]);
@@ -374,7 +383,11 @@ __device__ inline void pg_rk4(const DevModel &md, const QcleF &mf, const HopCtx 
 #pragma unroll
   for (int e = 0; e < HS; ++e)
 #pragma unroll
-    for (int j = 0; j < kGrpN; ++j) ys.g[e].v[j] = home_get(ad.home, e * kGrpN + j);
+    for (int j = 0; j < kGrpN; j += 2) {
+      const Cx2<double> h2 = home_get2(ad.home, e * kGrpN + j);
+      ys.g[e].v[j] = h2.re;
+      ys.g[e].v[j + 1] = h2.im;
+    }
   const int l = hc.h.comp;
   pg_zero(out);
 #pragma unroll 1
@@ -648,7 +661,11 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
 #pragma unroll
     for (int e = 0; e < HS; ++e)
 #pragma unroll
-      for (int j = 0; j < kGrpN; ++j) y.g[e].v[j] = home_get(ad.home, e * kGrpN + j);
+      for (int j = 0; j < kGrpN; j += 2) {
+        const Cx2<double> h2 = home_get2(ad.home, e * kGrpN + j);
+        y.g[e].v[j] = h2.re;
+        y.g[e].v[j + 1] = h2.im;
+      }
     // finiteness of the values this lane owns (slots without a pair group
     // or coordinate hold no state)
     double chk = y.S + y.Lam + h.logw;
