@@ -403,25 +403,19 @@ __device__ inline void pg_rk4(const DevModel &md, const QcleF &mf, const HopCtx 
   pg_finish<D, LPB, HS>(y, ad.home, h * (1.0 / 6.0), out);
 }
 
-// Mixed precision: one stage with FP32 stage values and accumulator; stage 3
-// leaves the step's increment h/6 (k1 + 2k2 + 2k3 + k4) in acc (FP32 for the
-// trajectory values, FP64 for S and Lam).
+// Mixed precision: one stage with FP32 stage values and accumulator (zero
+// before stage 0): acc += w k (w = 1, 2, 2, 1), ys = y0 + c k formed in FP64
+// and rounded (c = h/2, h/2, h; 0 in the last stage); S and Lam accumulate
+// in FP64.  pg_rk4_m turns acc into the step's increment h/6 acc.
 template <int D, int LPB>
 __device__ inline void pg_stage_m(const DevModel &md, const QcleF &mf, HopCtx &hc, Counters &cnt,
                                   const PgCtx<D, LPB, float> &cx, const PgY<D, LPB, double> &y0,
-                                  PgY<D, LPB, float> &ys, PgY<D, LPB, float> &acc, int stage, double c, float h6,
-                                  double h6d, const PgLds<D, float> &s) {
+                                  PgY<D, LPB, float> &ys, PgY<D, LPB, float> &acc, float w, double c,
+                                  const PgLds<D, float> &s) {
   const StageCoef<float> sc = stage_coef<D, float>(md, mf, hc.h.comp, s);
   auto fold = [&](float &a, float &yv, double y0v, float d) {
-    if (stage == 0) a = d;
-    else if (stage < 3) a = a + 2.0f * d;
-    else a = h6 * (a + d);
-    if (stage < 3) yv = (float)(y0v + c * (double)d);
-  };
-  auto fold64 = [&](double &a, double d) {
-    if (stage == 0) a = d;
-    else if (stage < 3) a = a + 2.0 * d;
-    else a = h6d * (a + d);
+    a = fmaf(w, d, a);
+    yv = (float)fma(c, (double)d, y0v);
   };
 #pragma unroll
   for (int e = 0; e < PG<D, LPB>::NG; ++e) {
@@ -439,8 +433,8 @@ __device__ inline void pg_stage_m(const DevModel &md, const QcleF &mf, HopCtx &h
     fold(acc.x[j], ys.x[j], y0.x[j], dx);
     fold(acc.p[j], ys.p[j], y0.p[j], dp);
   }
-  fold64(acc.S, (double)(sc.bc * sc.k.s));
-  fold64(acc.Lam, (double)(2.0f * fabsf(s.x[D] * sc.im * sc.k.d21)));
+  acc.S = fma((double)w, (double)(sc.bc * sc.k.s), acc.S);
+  acc.Lam = fma((double)w, (double)(2.0f * fabsf(s.x[D] * sc.im * sc.k.d21)), acc.Lam);
 }
 
 template <int D, int LPB>
@@ -451,21 +445,38 @@ __device__ inline void pg_rk4_m(const DevModel &md, const QcleF &mf, HopCtx &hc,
 #pragma unroll
   for (int e = 0; e < PG<D, LPB>::NG; ++e)
 #pragma unroll
-    for (int j = 0; j < kGrpN; ++j) ys.g[e].v[j] = (float)y.g[e].v[j];
+    for (int j = 0; j < kGrpN; ++j) {
+      ys.g[e].v[j] = (float)y.g[e].v[j];
+      inc.g[e].v[j] = 0.0f;
+    }
 #pragma unroll
   for (int j = 0; j < PG<D, LPB>::NXP; ++j) {
     ys.x[j] = (float)y.x[j];
     ys.p[j] = (float)y.p[j];
+    inc.x[j] = inc.p[j] = 0.0f;
   }
-  const double h6d = h * (1.0 / 6.0);
-  const float h6 = (float)h6d;
-  const double cs[3] = {0.5 * h, 0.5 * h, h};
+  inc.S = inc.Lam = 0.0;
 #pragma unroll 1
   for (int st = 0; st < 4; ++st) {
     pg_publish(cx, ys, s);
-    pg_stage_m(md, mf, hc, cnt, cx, y, ys, inc, st, st < 3 ? cs[st] : 0.0, h6, h6d, s);
+    pg_stage_m(md, mf, hc, cnt, cx, y, ys, inc, (st == 0 || st == 3) ? 1.0f : 2.0f,
+               st == 3 ? 0.0 : (st == 2 ? h : 0.5 * h), s);
     wave_lds_sync();
   }
+  // the increment h/6 acc
+  const double h6d = h * (1.0 / 6.0);
+  const float h6 = (float)h6d;
+#pragma unroll
+  for (int e = 0; e < PG<D, LPB>::NG; ++e)
+#pragma unroll
+    for (int j = 0; j < kGrpN; ++j) inc.g[e].v[j] = h6 * inc.g[e].v[j];
+#pragma unroll
+  for (int j = 0; j < PG<D, LPB>::NXP; ++j) {
+    inc.x[j] = h6 * inc.x[j];
+    inc.p[j] = h6 * inc.p[j];
+  }
+  inc.S = h6d * inc.S;
+  inc.Lam = h6d * inc.Lam;
 }
 
 template <int D, int LPB>
