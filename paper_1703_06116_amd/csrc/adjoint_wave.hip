@@ -340,28 +340,26 @@ __device__ inline void aw_q1_fill(const DevModel &md, int lane, const double *rr
   wave_lds_sync();
 }
 
-// The exchange sums of an adjoint (as pg_sums), each over four partial sums
-// so that the dependent adds after the reads are shorter.
+// The exchange sums of an adjoint that the vector-Jacobian product reads:
+// the row sums over k > 0 of Zrp (rho) and of Zpp (chi: the exchanged Zpp is
+// written to both triangles, so its row sums are its column sums, term by
+// term), one row of 16-byte entries per lane (lanes past the last task
+// repeat it), each over four partial sums so that the dependent adds after
+// the reads are shorter.  The coordinate sums are not read.
 template <int D>
 __device__ inline void aw_sums(const typename AwT<D>::Cx &cx, typename AwT<D>::Lds &s) {
-  constexpr int W = AwT<D>::Lds::W;
-  static_assert(2 * D + 1 <= kAwLanes, "one exchange sum per lane");
-  const int t = cx.r < 2 * D + 1 ? cx.r : 2 * D;
-  const bool row = t < D, col = !row && t < 2 * D;
-  const int u = row ? t : (col ? t - D : 0);
-  const double *br = row ? &s.rp[u][0].re : (col ? &s.pp[0][u].re : &s.x[0]);
-  const double *bi = row ? &s.rp[u][0].im : (col ? &s.pp[0][u].im : &s.p[D]);
-  const int stride = row ? 2 : (col ? 2 * W : 1);
-  double *orr = row ? &s.rho[u].re : (col ? &s.chi[u].re : &s.sx);
-  double *oi = row ? &s.rho[u].im : (col ? &s.chi[u].im : &s.sp);
+  static_assert(2 * D <= kAwLanes, "one exchange sum per lane");
+  const int t = cx.r < 2 * D ? cx.r : 2 * D - 1;
+  const Cx2<double> *row = t < D ? &s.rp[t][0] : &s.pp[t - D][0];
+  Cx2<double> *out = t < D ? &s.rho[t] : &s.chi[t - D];
   double sr[4] = {0.0, 0.0, 0.0, 0.0}, si[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 1; k < D; ++k) {
-    sr[k & 3] += br[k * stride];
-    si[k & 3] += bi[k * stride];
+    const Cx2<double> v = row[k];
+    sr[k & 3] += v.re;
+    si[k & 3] += v.im;
   }
-  *orr = (sr[0] + sr[1]) + (sr[2] + sr[3]);
-  *oi = (si[0] + si[1]) + (si[2] + si[3]);
+  *out = Cx2<double>{(sr[0] + sr[1]) + (sr[2] + sr[3]), (si[0] + si[1]) + (si[2] + si[3])};
 }
 
 // Vector-Jacobian product of the right-hand side at the stage value whose
@@ -404,7 +402,7 @@ __device__ inline void aw_vjp(const DevModel &md, int l, const typename AwT<D>::
   c0.B00 = 0.0;
 #pragma unroll
   for (int e = 0; e < C::NG; ++e) {
-    const bool live = cx.a[e] >= 0;
+    const bool live = (e + 1) * kAwLanes <= C::NGRP || cx.a[e] >= 0;   // slots every lane fills need no test
     const double *v = g.g[e].v;
     const double gs[kGrpN] = {v[kPpR], v[kPpI], v[kBaR], v[kBaI], v[kAbR], v[kAbI], v[kRrR], v[kRrI]};
     double d[kGrpN];
