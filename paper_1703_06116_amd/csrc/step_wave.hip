@@ -557,7 +557,10 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, PgCtx<D,
       partial = false;
     }
     // the hop at once, from the coupling (p1/M) d21(q1) at the state reached (in
-    // the stage precision); the draw and the choice out of line (fewer spills)
+    // the stage precision); the draw and the choice out of line: inline they
+    // spill (mixed: inside the interval loop; FP64: across it, and the FP64
+    // launch is 3 % slower), while the call saves a few live registers in
+    // scratch memory at each hop
     hop_start(hc, y.Lam);
     if constexpr (MIXED) {
       const float q1 = (float)__shfl(y.x[0], base, 64),
