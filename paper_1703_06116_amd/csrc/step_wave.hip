@@ -116,13 +116,23 @@ __device__ inline void home_put2(uint32_t home, int v, double a, double b) {
   lds_put_c(home + (v / 2) * kHomePair, a, b);
 }
 
+// A beam's rarely changed scalars in the FP64 stepping loop (log weight,
+// unit phase, event counts), in LDS rather than in registers.
+struct HopLds {
+  double logw, phre, phim;
+  uint32_t cnt[6];   // hops, threshold ties, destination ties, cap, zero rate (non-finite: unused)
+};
+
 // A workgroup's LDS: the exchange areas (first, so that their addresses fit
-// in 16 bits) and the home values of its wavefronts.
+// in 16 bits, and at their own stride, which sets how the two beams of a
+// wavefront fall on the LDS banks), the home values of its wavefronts and
+// the beams' hop scalars.
 template <int D, int LPB, typename TS, int WPB>
 struct TileLds {
   static constexpr int HS = home_slots<D, TS>();
   PgLds<D, TS> ex[WPB * PG<D, LPB>::G];
   Dbl2 home[WPB][HS > 0 ? HS * kGrpN / 2 : 1][64];
+  HopLds hop[WPB * PG<D, LPB>::G];
 };
 
 template <int D, int LPB>
@@ -502,7 +512,7 @@ __device__ inline void pg_add_inc(PgY<D, LPB, double> &y, const PgY<D, LPB, floa
 template <int D, int LPB, bool MIXED, int HS, bool REC = false>
 __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, PgCtx<D, LPB, double> &cx,
                                    const PgCtx<D, LPB, float> &cxf, PgAddr<D, LPB> &ad, int base, PgY<D, LPB, double> &y, HopCtx &hc,
-                                   double dt, Counters &cnt, void *lds, double *rec = nullptr) {
+                                   double dt, Counters &cnt, void *lds, HopLds &hl, double *rec = nullptr) {
   const double tie_rel = MIXED ? kTieRelMixed : kTieRel;
   double rem = dt, hstep = dt, theta = 1.0;
   bool partial = false;
@@ -533,7 +543,10 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, PgCtx<D,
     if (!partial) {
       const bool capped = hops >= SHGB_HOP_CAP;
       const double lam_n = MIXED ? y.Lam + yn.Lam : yn.Lam;
-      if (!capped && fabs(lam_n - E) <= tie_rel * E) cnt.thr_ties++;
+      if (!capped && fabs(lam_n - E) <= tie_rel * E) {
+        if constexpr (MIXED) cnt.thr_ties++;
+        else hl.cnt[1]++;   // every lane of the beam writes the same count
+      }
       if constexpr (REC) {
         if (hops == 0 && cx.r == 0 && rec) {
           rec[4 * adj_stage_rec(D)] = (double)comp0;
@@ -541,7 +554,10 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, PgCtx<D,
         }
       }
       if (capped || !(lam_n >= E)) {
-        if (capped) cnt.cap++;
+        if (capped) {
+          if constexpr (MIXED) cnt.cap++;
+          else hl.cnt[3]++;
+        }
         accept();
         break;
       }
@@ -557,20 +573,37 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, PgCtx<D,
       partial = false;
     }
     // the hop at once, from the coupling (p1/M) d21(q1) at the state reached (in
-    // the stage precision); the draw and the choice out of line: inline they
-    // spill (mixed: inside the interval loop; FP64: across it, and the FP64
-    // launch is 3 % slower), while the call saves a few live registers in
-    // scratch memory at each hop
-    hop_start(hc, y.Lam);
+    // the stage precision).  Mixed: the draw and the choice out of line (inline
+    // they spill inside the interval loop).  FP64: inline, with the beam's log
+    // weight, phase and counts in LDS (HopLds; every lane of the beam
+    // computes and writes the same values), so that nothing is held in
+    // registers across the interval loop for the hop and no call saves
+    // registers in scratch memory.
     if constexpr (MIXED) {
+      hop_start(hc, y.Lam);
       const float q1 = (float)__shfl(y.x[0], base, 64),
                   p1 = (float)__shfl(y.x[D / LPB], base + D % LPB, 64);
       const Q1f k = qcle_q1f(mf, q1);
       hop_choose_call((double)(p1 * mf.inv_mass * k.d21), hc.h, hc.gid, hc.seed, cnt, kTieRelMixed);
     } else {
+      HopScalars hh = hc.h;
+      hh.logw = hl.logw + y.Lam;   // the weight update of hop_start
+      hh.phre = hl.phre;
+      hh.phim = hl.phim;
+      hop_start(hc, y.Lam);
       const double q1 = __shfl(y.x[0], base, 64), p1 = __shfl(y.x[D / LPB], base + D % LPB, 64);
       const Q1 k = qcle_q1(md, q1);
-      hop_choose_call(p1 * md.inv_mass * k.d21, hc.h, hc.gid, hc.seed, cnt, kTieRel);
+      Counters c1;
+      hop_choose(p1 * md.inv_mass * k.d21, hh, hc.gid, hc.seed, c1, kTieRel);
+      hl.logw = hh.logw;
+      hl.phre = hh.phre;
+      hl.phim = hh.phim;
+      hl.cnt[0] += c1.hops;
+      hl.cnt[2] += c1.dest_ties;
+      hl.cnt[4] += c1.zero_rate;
+      hc.h.comp = hh.comp;
+      hc.h.nhop = hh.nhop;
+      hc.h.E = hh.E;
     }
     hc.pending = false;
     ++hops;
@@ -659,6 +692,16 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
     hc.gid = gid0 + (uint64_t)b;
     hc.seed = seed;
     pg_fill_const<D, LPB>(r, md.bath_k, lds[slot]);
+    HopLds &hl = tl.hop[slot];
+    if constexpr (!MIXED) {
+      // the beam's rarely changed scalars (every lane writes the same values;
+      // only the beam's lanes read them, after the first publish's barrier)
+      hl.logw = h.logw;
+      hl.phre = h.phre;
+      hl.phim = h.phim;
+#pragma unroll
+      for (int t = 0; t < 6; ++t) hl.cnt[t] = 0u;
+    }
     PgAddr<D, LPB> ad{};
     if constexpr (!MIXED) {
       ad = pg_addr(cx, lds[slot]);
@@ -669,9 +712,13 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
         for (int j = 0; j < kGrpN; j += 2) home_put2(ad.home, e * kGrpN + j, y.g[e].v[j], y.g[e].v[j + 1]);
     }
     for (int st = 0; st < nsteps; ++st)
-      pg_interval<D, LPB, MIXED, HS, REC>(md, mf, cx, cxf, ad, base, y, hc, dt, cnt, (void *)&lds[slot],
+      pg_interval<D, LPB, MIXED, HS, REC>(md, mf, cx, cxf, ad, base, y, hc, dt, cnt, (void *)&lds[slot], hl,
                                       REC ? recs + ((int64_t)b * every + st) * adj_interval_rec(D) : nullptr);
     // (every hop is completed where it starts, so none is pending here)
+    // the beam index through an empty asm statement: the stores' addresses
+    // are formed here, not kept from the loads before the interval loop
+    int64_t bw = b;
+    asm volatile("" : "+v"(bw));
 #pragma unroll
     for (int e = 0; e < HS; ++e)
 #pragma unroll
@@ -682,6 +729,16 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
       }
     // finiteness of the values this lane owns (slots without a pair group
     // or coordinate hold no state)
+    if constexpr (!MIXED) {
+      h.logw = hl.logw;
+      h.phre = hl.phre;
+      h.phim = hl.phim;
+      cnt.hops = hl.cnt[0];
+      cnt.thr_ties = hl.cnt[1];
+      cnt.dest_ties = hl.cnt[2];
+      cnt.cap = hl.cnt[3];
+      cnt.zero_rate = hl.cnt[4];
+    }
     double chk = y.S + y.Lam + h.logw;
 #pragma unroll
     for (int j = 0; j < C::NXP; ++j)
@@ -704,26 +761,26 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
                                 L.Zre(tba), L.Zim(tba), L.Zre(tpp), L.Zim(tpp)};
 #pragma unroll
         for (int j = 0; j < kGrpN; ++j)
-          if (a != bb || (j != kBaR && j != kBaI)) tr[row[j] * ld + b] = (TS)y.g[e].v[j];
+          if (a != bb || (j != kBaR && j != kBaI)) tr[row[j] * ld + bw] = (TS)y.g[e].v[j];
       }
     }
 #pragma unroll
     for (int j = 0; j < C::NXP; ++j) {
       const int c = r + LPB * j;
       if (c < M) {
-        tr[L.X(c) * ld + b] = (TS)y.x[j];
-        tr[L.P(c) * ld + b] = (TS)y.p[j];
+        tr[L.X(c) * ld + bw] = (TS)y.x[j];
+        tr[L.P(c) * ld + bw] = (TS)y.p[j];
       }
     }
     if (r == 0) {
-      sc[kRowS * ld + b] = y.S;
-      sc[kRowLam * ld + b] = y.Lam;
-      sc[kRowLogw * ld + b] = h.logw;
-      sc[kRowPhre * ld + b] = h.phre;
-      sc[kRowPhim * ld + b] = h.phim;
-      sc[kRowE * ld + b] = h.E;
-      comp[b] = h.comp;
-      nhop[b] = h.nhop;
+      sc[kRowS * ld + bw] = y.S;
+      sc[kRowLam * ld + bw] = y.Lam;
+      sc[kRowLogw * ld + bw] = h.logw;
+      sc[kRowPhre * ld + bw] = h.phre;
+      sc[kRowPhim * ld + bw] = h.phim;
+      sc[kRowE * ld + bw] = h.E;
+      comp[bw] = h.comp;
+      nhop[bw] = h.nhop;
       if (bad) cnt.nonfinite++;
       cnt_out.hops += cnt.hops;
       cnt_out.thr_ties += cnt.thr_ties;
