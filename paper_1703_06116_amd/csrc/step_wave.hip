@@ -414,18 +414,18 @@ __device__ inline void pg_rk4(const DevModel &md, const QcleF &mf, const HopCtx 
 }
 
 // Mixed precision: one stage with FP32 stage values and accumulator (zero
-// before stage 0): acc += w k (w = 1, 2, 2, 1), ys = y0 + c k formed in FP64
-// and rounded (c = h/2, h/2, h; 0 in the last stage); S and Lam accumulate
-// in FP64.  pg_rk4_m turns acc into the step's increment h/6 acc.
+// before stage 0): acc += w k (w = 1, 2, 2, 1), ys = y0 + c k in FP32 from
+// y0 rounded to FP32 (c = h/2, h/2, h; 0 in the last stage); S and Lam
+// accumulate in FP64.  pg_rk4_m turns acc into the step's increment h/6 acc.
 template <int D, int LPB>
 __device__ inline void pg_stage_m(const DevModel &md, const QcleF &mf, HopCtx &hc, Counters &cnt,
                                   const PgCtx<D, LPB, float> &cx, const PgY<D, LPB, double> &y0,
-                                  PgY<D, LPB, float> &ys, PgY<D, LPB, float> &acc, float w, double c,
+                                  PgY<D, LPB, float> &ys, PgY<D, LPB, float> &acc, float w, float c,
                                   const PgLds<D, float> &s) {
   const StageCoef<float> sc = stage_coef<D, float>(md, mf, hc.h.comp, s);
   auto fold = [&](float &a, float &yv, double y0v, float d) {
     a = fmaf(w, d, a);
-    yv = (float)fma(c, (double)d, y0v);
+    yv = fmaf(c, d, (float)y0v);
   };
 #pragma unroll
   for (int e = 0; e < PG<D, LPB>::NG; ++e) {
@@ -470,7 +470,7 @@ __device__ inline void pg_rk4_m(const DevModel &md, const QcleF &mf, HopCtx &hc,
   for (int st = 0; st < 4; ++st) {
     pg_publish(cx, ys, s);
     pg_stage_m(md, mf, hc, cnt, cx, y, ys, inc, (st == 0 || st == 3) ? 1.0f : 2.0f,
-               st == 3 ? 0.0 : (st == 2 ? h : 0.5 * h), s);
+               (float)(st == 3 ? 0.0 : (st == 2 ? h : 0.5 * h)), s);
     wave_lds_sync();
   }
   // the increment h/6 acc
