@@ -447,6 +447,38 @@ __device__ inline void pg_stage_m(const DevModel &md, const QcleF &mf, HopCtx &h
   acc.Lam = fma((double)w, (double)(2.0f * fabsf(s.x[D] * sc.im * sc.k.d21)), acc.Lam);
 }
 
+// Publish FP32 stage values (mixed path): pg_publish with the exchange sums
+// as rows of 8-byte complex entries (Zpp's column sums are its row sums;
+// the coordinate sums read the pairs (X_k, P_d+k)), one task per lane.
+template <int D, int LPB>
+__device__ inline void pg_publish_f(const PgCtx<D, LPB, float> &cx, const PgY<D, LPB, float> &y, PgLds<D, float> &s) {
+  pg_write(cx, y, s);
+#pragma unroll
+  for (int j = 0; j < PG<D, LPB>::NXP; ++j) {
+    const int c = cx.r + LPB * j;
+    if (c < D) s.xq[c].re = y.x[j];
+    else if (c < 2 * D) s.xq[c - D].im = y.p[j];
+  }
+  wave_lds_sync();
+  if constexpr (2 * D + 1 <= LPB) {
+    const int t = cx.r < 2 * D ? cx.r : 2 * D;
+    const Cx2<float> *row = t < D ? &s.rp[t][0] : (t < 2 * D ? &s.pp[t - D][0] : &s.xq[0]);
+    float sr = 0.0f, si = 0.0f;
+#pragma unroll
+    for (int k = 1; k < D; ++k) {
+      const Cx2<float> v = row[k];
+      sr += v.re;
+      si += v.im;
+    }
+    if (t < D) s.rho[t] = Cx2<float>{sr, si};
+    else if (t < 2 * D) s.chi[t - D] = Cx2<float>{sr, si};
+    else { s.sx = sr; s.sp = si; }
+  } else {
+    pg_sums(cx, s);
+  }
+  wave_lds_sync();
+}
+
 template <int D, int LPB>
 __device__ inline void pg_rk4_m(const DevModel &md, const QcleF &mf, HopCtx &hc, Counters &cnt,
                                 const PgCtx<D, LPB, float> &cx, const PgY<D, LPB, double> &y, double h,
@@ -468,7 +500,7 @@ __device__ inline void pg_rk4_m(const DevModel &md, const QcleF &mf, HopCtx &hc,
   inc.S = inc.Lam = 0.0;
 #pragma unroll 1
   for (int st = 0; st < 4; ++st) {
-    pg_publish(cx, ys, s);
+    pg_publish_f(cx, ys, s);
     pg_stage_m(md, mf, hc, cnt, cx, y, ys, inc, (st == 0 || st == 3) ? 1.0f : 2.0f,
                (float)(st == 3 ? 0.0 : (st == 2 ? h : 0.5 * h)), s);
     wave_lds_sync();
