@@ -406,6 +406,10 @@ __device__ inline void pg_rk4(const DevModel &md, const QcleF &mf, const HopCtx 
     pg_ctx_opaque(cx);
     pg_addr_opaque(ad);
     pg_publish_ad(cx, ad, ys, s);
+    // the publish and its sums scheduled apart from the stage's arithmetic
+    // (3 % on the d = 12 launch; left to itself the scheduler interleaves
+    // them in a slower order)
+    __builtin_amdgcn_sched_barrier(0);
     pg_stage<D, LPB, HS>(md, mf, l, cx, ad, y, ys, out, (st == 0 || st == 3) ? 1.0 : 2.0,
                          st == 3 ? 0.0 : (st == 2 ? h : 0.5 * h), s);
     wave_lds_sync();
