@@ -79,7 +79,7 @@ PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
 # kernel it was taken on; remove it when that kernel changes.
 STEP_TRAFFIC = {
     "qcle1d_1e6": ((66680.1 * 2.0 + 133300.8 * 1.0) * 1024, "step_m2_kernel, profiles/step_m2_qcle1d_1e6.md"),
-    "qcle12d_2p18": ((672056.8 * 2.0 + 2052431.0 * 1.0) * 1024,
+    "qcle12d_2p18": ((672056.3 * 2.0 + 2064897.0 * 1.0) * 1024,
                      "step_wave_kernel<12, 32, double> (two wavefronts per SIMD, no scratch), "
                      "profiles/step_wave_qcle12d_2p18.md"),
 }
