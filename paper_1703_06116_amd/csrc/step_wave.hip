@@ -22,9 +22,10 @@
 // local operand of its four derivatives; only Zrp_a0, Zpp_0b and the sums
 // rho, chi come from other lanes, through the beam's slice of LDS.  Lane
 // r of the group owns X_c and P_c for c = r, r + LPB, ... below m; the
-// scalars (S, Lam, weights, the threshold and the component) are replicated
-// over the group, so the hop logic (Sec. 2.4 steps 3-5) is uniform within a
-// group.
+// scalars (S, Lam, the weight, the threshold and the component) are
+// replicated over the group, so the hop logic (Sec. 2.4 steps 3-5) is
+// uniform within a group (an FP64 beam's log weight, phase and event counts
+// sit in LDS, written alike by its lanes).
 //
 // Precision: an FP64 state is integrated in FP64 throughout.  For a mixed
 // state the stage values and the right-hand side are FP32 (the exchange
