@@ -677,15 +677,24 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int grp = lane / LPB, r = lane % LPB, base = grp * LPB;
   const int slot = wid * C::G + grp;
-  const int64_t b = tile * (WPB * C::G) + slot;
+  constexpr int NB = WPB * C::G;  // beams of the tile
+  // A tile narrower than a 128-byte line of a trajectory row writes its rows
+  // through LDS after the last interval, all of the tile's beams of a row at
+  // once: written by each beam on its own, the line's pieces leave the L2 at
+  // different times and are written to HBM more than once.
+  constexpr bool kStageOut = NB * (int)sizeof(TS) < 128;
+  constexpr int kTrajRows = 2 * M + M * (M + 1);
+  static_assert(!kStageOut || kTrajRows * NB * sizeof(TS) <= sizeof(TileLds<D, LPB, TS, WPB>),
+                "the tile's trajectory rows fit in its LDS");
+  const int64_t b = tile * NB + slot;
+  const Layout L(M, ld);
   Counters cnt;
+  PgCtx<D, LPB, double> cx;
+  PgY<D, LPB, double> y;
   if (b < n) {  // uniform across the beam's lanes
-    const Layout L(M, ld);
     const QcleF mf = qcle_f32(md);
-    PgCtx<D, LPB, double> cx;
     PgCtx<D, LPB, float> cxf;
     cx.r = cxf.r = r;
-    PgY<D, LPB, double> y;
 #pragma unroll
     for (int e = 0; e < C::NG; ++e) {
       const int gi = r + LPB * e;
@@ -788,25 +797,27 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
     int bad = !isfinite(chk);
 #pragma unroll
     for (int off = 1; off < LPB; off <<= 1) bad |= __shfl_xor(bad, off, 64);
+    if constexpr (!kStageOut) {
 #pragma unroll
-    for (int e = 0; e < C::NG; ++e) {
-      const int a = cx.a[e], bb = cx.b[e];
-      if (a >= 0) {
-        const int trr = Layout::tri(M, a, bb), tab = Layout::tri(M, a, D + bb), tba = Layout::tri(M, bb, D + a),
-                  tpp = Layout::tri(M, D + a, D + bb);
-        const int row[kGrpN] = {L.Zre(trr), L.Zim(trr), L.Zre(tab), L.Zim(tab),
-                                L.Zre(tba), L.Zim(tba), L.Zre(tpp), L.Zim(tpp)};
+      for (int e = 0; e < C::NG; ++e) {
+        const int a = cx.a[e], bb = cx.b[e];
+        if (a >= 0) {
+          const int trr = Layout::tri(M, a, bb), tab = Layout::tri(M, a, D + bb), tba = Layout::tri(M, bb, D + a),
+                    tpp = Layout::tri(M, D + a, D + bb);
+          const int row[kGrpN] = {L.Zre(trr), L.Zim(trr), L.Zre(tab), L.Zim(tab),
+                                  L.Zre(tba), L.Zim(tba), L.Zre(tpp), L.Zim(tpp)};
 #pragma unroll
-        for (int j = 0; j < kGrpN; ++j)
-          if (a != bb || (j != kBaR && j != kBaI)) tr[row[j] * ld + bw] = (TS)y.g[e].v[j];
+          for (int j = 0; j < kGrpN; ++j)
+            if (a != bb || (j != kBaR && j != kBaI)) tr[row[j] * ld + bw] = (TS)y.g[e].v[j];
+        }
       }
-    }
 #pragma unroll
-    for (int j = 0; j < C::NXP; ++j) {
-      const int c = r + LPB * j;
-      if (c < M) {
-        tr[L.X(c) * ld + bw] = (TS)y.x[j];
-        tr[L.P(c) * ld + bw] = (TS)y.p[j];
+      for (int j = 0; j < C::NXP; ++j) {
+        const int c = r + LPB * j;
+        if (c < M) {
+          tr[L.X(c) * ld + bw] = (TS)y.x[j];
+          tr[L.P(c) * ld + bw] = (TS)y.p[j];
+        }
       }
     }
     if (r == 0) {
@@ -825,6 +836,41 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
       cnt_out.cap += cnt.cap;
       cnt_out.zero_rate += cnt.zero_rate;
       cnt_out.nonfinite += cnt.nonfinite;
+    }
+  }
+  if constexpr (kStageOut) {
+    // rows [kTrajRows][NB] over the whole tile area, once every wave of the
+    // tile is past its last interval
+    TS *stg = reinterpret_cast<TS *>(&tl);
+    __syncthreads();
+    if (b < n) {
+#pragma unroll
+      for (int e = 0; e < C::NG; ++e) {
+        const int a = cx.a[e], bb = cx.b[e];
+        if (a >= 0) {
+          const int trr = Layout::tri(M, a, bb), tab = Layout::tri(M, a, D + bb), tba = Layout::tri(M, bb, D + a),
+                    tpp = Layout::tri(M, D + a, D + bb);
+          const int row[kGrpN] = {L.Zre(trr), L.Zim(trr), L.Zre(tab), L.Zim(tab),
+                                  L.Zre(tba), L.Zim(tba), L.Zre(tpp), L.Zim(tpp)};
+#pragma unroll
+          for (int j = 0; j < kGrpN; ++j)
+            if (a != bb || (j != kBaR && j != kBaI)) stg[row[j] * NB + slot] = (TS)y.g[e].v[j];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < C::NXP; ++j) {
+        const int c = r + LPB * j;
+        if (c < M) {
+          stg[L.X(c) * NB + slot] = (TS)y.x[j];
+          stg[L.P(c) * NB + slot] = (TS)y.p[j];
+        }
+      }
+    }
+    __syncthreads();
+    const int64_t b0 = tile * NB;
+    for (int i = threadIdx.x; i < kTrajRows * NB; i += 64 * WPB) {
+      const int row = i / NB, s = i % NB;
+      if (b0 + s < n) tr[row * ld + b0 + s] = stg[i];
     }
   }
 }
