@@ -586,6 +586,48 @@ def run_grad(name, steps, warmup, with_tangent):
     torch.cuda.synchronize()
     ms_fwd = (time.perf_counter() - t0) * 1e3 / steps
     p = pops.cpu().numpy()
+    kept = None
+    if m > 2:
+        # the same gradient with every interval's stage records kept from the forward run (memory
+        # instead of the reverse sweep's replay of each segment)
+        del adj_work
+        recs = torch.empty(shgb.record_bytes(N, m, nsteps, every) // 8, dtype=torch.float64, device=dev)
+        kwork = torch.empty(max(shgb.population_adjoint_recorded_workspace(N, m, every), 8), dtype=torch.uint8,
+                            device=dev)
+        grad_k = torch.empty(6, dtype=torch.float64, device=dev)
+
+        def kept_step(evs=None):
+            def mark(i):
+                if evs is not None:
+                    evs[i].record()
+            mark(0)
+            shgb.init_beams(mdl, spec, st, seed)
+            shgb.step_recorded(mdl, st, nsteps, dt, seed, every=every, ckpt=ckpt, recs=recs)
+            shgb.populations(mdl, st, out=pops, work=pop_work)
+            mark(1)
+            shgb.population_adjoint_recorded(mdl, st, ckpt, recs, nsteps, dt, seed, cot, N, every=every, out=grad_k,
+                                             work=kwork)
+            mark(2)
+
+        for _ in range(warmup):
+            kept_step()
+        torch.cuda.synchronize()
+        evk = [[_timer() for _ in range(3)] for _ in range(steps)]
+        t0 = time.perf_counter()
+        for k in range(steps):
+            kept_step(evk[k])
+        torch.cuda.synchronize()
+        ms_kept = (time.perf_counter() - t0) * 1e3 / steps
+        gk = grad_k.cpu().numpy()
+        kept = {"ms_per_step": ms_kept, "gradient_over_forward": ms_kept / ms_fwd,
+                "kernel_ms": {"forward_with_records": float(np.mean([e[0].elapsed_time(e[1]) for e in evk])),
+                              "reverse_sweep": float(np.mean([e[1].elapsed_time(e[2]) for e in evk]))},
+                "record_bytes": int(recs.numel() * 8),
+                "max_rel_diff_vs_replay": float(np.abs(gk[:5] - g[:5]).max() / max(np.abs(g[:5]).max(), 1e-300)),
+                "note": "shgb_step_recorded + shgb_population_adjoint_recorded: the forward run keeps every "
+                        "interval's stage records in HBM and the reverse sweep reads them instead of running each "
+                        "segment again"}
+        del recs
     tflops = FLOPS_PER_BEAM_STEP_ADJ_M24 * N * nsteps / (adj_ms / 1e3) / 1e12
     line = {
         "value": N * nsteps / (ms_grad / 1e3), "unit": "beam-steps/s", "ms_per_step": ms_grad,
@@ -597,6 +639,8 @@ def run_grad(name, steps, warmup, with_tangent):
         "kernel_ms": {"forward_with_checkpoints": fwd_ckpt_ms, "reverse_sweep": adj_ms},
         "forward_fp64_ms_per_step": ms_fwd,
         "gradient_over_forward": ms_grad / ms_fwd,
+        "gradient_over_forward_kept_records": kept["gradient_over_forward"] if kept else None,
+        "kept_records": kept,
         "upper_population": float(p[0, 0] / N),
         "objective_from_reverse_sweep": float(g[5]),
         "d_upper_population": {n: float(g[j]) for j, n in enumerate(("A", "B", "C", "D", "p_mean"))},

@@ -342,6 +342,36 @@ int shgb_population_adjoint(const shgb_model *model, const shgb_state *st, const
                             uint64_t seed, int32_t every, const double *cot, int64_t n_traj, double *out, void *work,
                             int64_t work_bytes, void *stream);
 
+/* ---- the same derivative with the forward run's stage records kept ------
+ * Memory instead of recomputation (d in {2, 3, 4, 12}, FP64): the reverse
+ * sweep above runs every segment forward a second time to get the stage
+ * records its vector-Jacobian products read (Sec. 2.3 eq:shgb_odes through
+ * the RK4 stages of Sec. 2.4 step 3).  shgb_step_recorded advances the
+ * ensemble as shgb_step_checkpointed does (the same checkpoints, the same
+ * final state, hops and diag counts) and also writes those records of every
+ * interval into recs: device memory of shgb_record_bytes, 8 (4 (3 + 4d) + 2)
+ * bytes per beam and interval rounded up to whole segments of `every`
+ * (1648 bytes per beam and interval at d = 12: 108 GB for 65536 beams and
+ * 1000 intervals).  Segment c, beam b, interval i of the segment at
+ * recs + ((c n_beams + b) every + i) (4 (3 + 4d) + 2) doubles.
+ * shgb_population_adjoint_recorded then gives what shgb_population_adjoint
+ * gives for the same stepped state and checkpoints, without the replays; its
+ * workspace (shgb_population_adjoint_recorded_workspace) holds no records.
+ * The caller owns ckpt, recs and work; the two calls must see the same
+ * nsteps, dt, seed and every, and recs unchanged between them.
+ * shgb_record_bytes and the workspace query return -1 for m = 2 and other d.
+ * Errors: EINVAL, EWORKSPACE (ckpt or recs too small), EUNSUPPORTED (m = 2,
+ * other d, mixed state, other models). */
+int64_t shgb_record_bytes(int64_t n_beams, int32_t m, int32_t nsteps, int32_t every);
+int shgb_step_recorded(const shgb_model *model, const shgb_state *st, int32_t nsteps, double dt, uint64_t seed,
+                       int32_t every, void *ckpt, int64_t ckpt_bytes, double *recs, int64_t recs_bytes,
+                       uint64_t *diag, void *stream);
+int64_t shgb_population_adjoint_recorded_workspace(int64_t n_beams, int32_t m, int32_t every);
+int shgb_population_adjoint_recorded(const shgb_model *model, const shgb_state *st, const void *ckpt,
+                                     const double *recs, int32_t nsteps, double dt, uint64_t seed, int32_t every,
+                                     const double *cot, int64_t n_traj, double *out, void *work, int64_t work_bytes,
+                                     void *stream);
+
 /* ---- batches: many instances in one persistent launch ------------------
  * A batch is n_inst independent QCLE instances (model, state, seed) of one
  * dimension d and one precision; models may differ in every parameter and

@@ -1060,31 +1060,36 @@ int64_t aw_chunk(int64_t n) {
   return n < kAwChunk ? (n < 1 ? 1 : n) : kAwChunk;
 }
 
-// Workspace (doubles): the records of one segment for the chunk, the
-// chunk's adjoint states, its buffers for intervals with a hop, its replay
-// state (shgb_nfields rows, then comp and nhop), and one row of kAdjVals per
-// beam.
+// Workspace (doubles): the records of one segment for the chunk (none when
+// the forward run kept its records), the chunk's adjoint states, its buffers
+// for intervals with a hop, its replay state (shgb_nfields rows, then comp
+// and nhop), and one row of kAdjVals per beam.
 template <int D>
-int64_t aw_workspace_bytes(int64_t n, int every) {
+int64_t aw_workspace_bytes(int64_t n, int every, bool recorded) {
   const int64_t c = aw_chunk<D>(n);
-  const int64_t dbl = c * ((int64_t)every * adj_interval_rec(D) + AwT<D>::NF * kAwLanes + aw_gen_doubles<D>() +
-                           shgb_nfields(2 * D) + 1) +
+  const int64_t seg = recorded ? 0 : (int64_t)every * adj_interval_rec(D);
+  const int64_t dbl = c * (seg + AwT<D>::NF * kAwLanes + aw_gen_doubles<D>() + shgb_nfields(2 * D) + 1) +
                       (n < 1 ? 1 : n) * kAdjVals;
   return dbl * 8;
 }
 
 hipError_t launch_adj_final(const double *, int64_t, double *, hipStream_t);
 hipError_t launch_step_wave_record(const DevModel &, const shgb_state &, int, double, uint64_t, double *, int,
-                                   hipStream_t);
+                                   uint64_t *, hipStream_t);
 
+// kept: the forward run's records of every segment (segment c, beam b,
+// interval i at kept + ((c n + b) every + i) adj_interval_rec(d)), or null
+// for the replay of each segment from its checkpoint.
 template <int D>
-hipError_t launch_aw(const DevModel &md, const shgb_state &fin, const void *ckpt, int nsteps, double dt, uint64_t seed,
-                     int every, const double *cot, int64_t n_traj, double *out, void *work, hipStream_t stream) {
+hipError_t launch_aw(const DevModel &md, const shgb_state &fin, const void *ckpt, const double *kept, int nsteps,
+                     double dt, uint64_t seed, int every, const double *cot, int64_t n_traj, double *out, void *work,
+                     hipStream_t stream) {
   const int64_t n = fin.n_beams;
   const int64_t chunk = aw_chunk<D>(n);
   const CkptLayout cl = ckpt_layout(n, 2 * D, nsteps, every);
+  const int64_t seg = (int64_t)every * adj_interval_rec(D);   // doubles per beam and segment
   double *recs = (double *)work;
-  double *ybuf = recs + chunk * (int64_t)every * adj_interval_rec(D);
+  double *ybuf = recs + (kept ? 0 : chunk * seg);
   double *gen = ybuf + chunk * AwT<D>::NF * kAwLanes;
   double *rf = gen + chunk * aw_gen_doubles<D>();
   int32_t *rcomp = (int32_t *)(rf + chunk * (int64_t)shgb_nfields(2 * D));
@@ -1111,12 +1116,17 @@ hipError_t launch_aw(const DevModel &md, const shgb_state &fin, const void *ckpt
       const char *base = (const char *)ckpt + (int64_t)c * cl.stride_bytes;
       const double *cf = (const double *)base;
       const int32_t *ci = (const int32_t *)(base + cl.rows * n * 8);
-      hipLaunchKernelGGL(aw_ckpt_load_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, stream, cf, ci, n,
-                         cl.rows, b0, nb, chunk, rf, rcomp, rnhop);
-      const hipError_t e = launch_step_wave_record(md, rs, len, dt, seed, recs, every, stream);
-      if (e != hipSuccess) return e;
+      const double *rr = recs;
+      if (kept) {
+        rr = kept + ((int64_t)c * n + b0) * seg;
+      } else {
+        hipLaunchKernelGGL(aw_ckpt_load_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, stream, cf, ci, n,
+                           cl.rows, b0, nb, chunk, rf, rcomp, rnhop);
+        const hipError_t e = launch_step_wave_record(md, rs, len, dt, seed, recs, every, nullptr, stream);
+        if (e != hipSuccess) return e;
+      }
       hipLaunchKernelGGL(aw_reverse_kernel<D>, dim3(blocks), dim3(kAwLanes * kAwWaves), 0, stream, md, cf, ci, n,
-                         len, every, c == 0 ? 1 : 0, b0, nb, fin.beam_id_offset, seed, dt, recs, ybuf, bsc, gen);
+                         len, every, c == 0 ? 1 : 0, b0, nb, fin.beam_id_offset, seed, dt, rr, ybuf, bsc, gen);
     }
   }
   return launch_adj_final(bsc, n, out, stream);   // n = 0: zeros
@@ -1124,24 +1134,24 @@ hipError_t launch_aw(const DevModel &md, const shgb_state &fin, const void *ckpt
 
 bool adjoint_wave_supported(int d) { return d == 2 || d == 3 || d == 4 || d == 12; }
 
-int64_t adj_wave_workspace_bytes(int64_t n, int m, int every) {
+int64_t adj_wave_workspace_bytes(int64_t n, int m, int every, bool recorded) {
   switch (m / 2) {
-    case 2: return aw_workspace_bytes<2>(n, every);
-    case 3: return aw_workspace_bytes<3>(n, every);
-    case 4: return aw_workspace_bytes<4>(n, every);
-    case 12: return aw_workspace_bytes<12>(n, every);
+    case 2: return aw_workspace_bytes<2>(n, every, recorded);
+    case 3: return aw_workspace_bytes<3>(n, every, recorded);
+    case 4: return aw_workspace_bytes<4>(n, every, recorded);
+    case 12: return aw_workspace_bytes<12>(n, every, recorded);
     default: return -1;
   }
 }
 
-hipError_t launch_adjoint_wave(const DevModel &md, const shgb_state &fin, const void *ckpt, int nsteps, double dt,
-                               uint64_t seed, int every, const double *cot, int64_t n_traj, double *out, void *work,
-                               hipStream_t stream) {
+hipError_t launch_adjoint_wave(const DevModel &md, const shgb_state &fin, const void *ckpt, const double *kept,
+                               int nsteps, double dt, uint64_t seed, int every, const double *cot, int64_t n_traj,
+                               double *out, void *work, hipStream_t stream) {
   switch (md.d) {
-    case 2: return launch_aw<2>(md, fin, ckpt, nsteps, dt, seed, every, cot, n_traj, out, work, stream);
-    case 3: return launch_aw<3>(md, fin, ckpt, nsteps, dt, seed, every, cot, n_traj, out, work, stream);
-    case 4: return launch_aw<4>(md, fin, ckpt, nsteps, dt, seed, every, cot, n_traj, out, work, stream);
-    case 12: return launch_aw<12>(md, fin, ckpt, nsteps, dt, seed, every, cot, n_traj, out, work, stream);
+    case 2: return launch_aw<2>(md, fin, ckpt, kept, nsteps, dt, seed, every, cot, n_traj, out, work, stream);
+    case 3: return launch_aw<3>(md, fin, ckpt, kept, nsteps, dt, seed, every, cot, n_traj, out, work, stream);
+    case 4: return launch_aw<4>(md, fin, ckpt, kept, nsteps, dt, seed, every, cot, n_traj, out, work, stream);
+    case 12: return launch_aw<12>(md, fin, ckpt, kept, nsteps, dt, seed, every, cot, n_traj, out, work, stream);
     default: return hipErrorInvalidValue;
   }
 }

@@ -44,13 +44,13 @@ hipError_t launch_tangent_wave(const DevModel &, const shgb_state &, int, double
 hipError_t launch_tangent_m2(const DevModel &, const shgb_state &, int, double, uint64_t, uint32_t, double *, void *,
                              uint64_t *, hipStream_t);
 int m2_tile_beams(int wpb);
-hipError_t launch_step_checkpointed(const DevModel &, const shgb_state &, int, double, uint64_t, int, void *, uint64_t *,
-                                    hipStream_t);
+hipError_t launch_step_checkpointed(const DevModel &, const shgb_state &, int, double, uint64_t, int, void *, double *,
+                                    uint64_t *, hipStream_t);
 int64_t adj_m2_workspace_bytes(int64_t, int);
-int64_t adj_wave_workspace_bytes(int64_t, int, int);
+int64_t adj_wave_workspace_bytes(int64_t, int, int, bool);
 bool adjoint_wave_supported(int d);
-hipError_t launch_adjoint_wave(const DevModel &, const shgb_state &, const void *, int, double, uint64_t, int,
-                               const double *, int64_t, double *, void *, hipStream_t);
+hipError_t launch_adjoint_wave(const DevModel &, const shgb_state &, const void *, const double *, int, double,
+                               uint64_t, int, const double *, int64_t, double *, void *, hipStream_t);
 hipError_t launch_adjoint_m2(const DevModel &, const shgb_state &, const void *, int, double, uint64_t, int,
                              const double *, int64_t, double *, void *, hipStream_t);
 hipError_t launch_step_wave_batched(int d, bool mixed_state, int wpb, const BatchItem *items, int n_items,
@@ -399,13 +399,62 @@ int shgb_step_checkpointed(const shgb_model *model, const shgb_state *st, int32_
   if (!adjoint_supported(md, st)) return SHGB_EUNSUPPORTED;
   const int64_t need = shgb_checkpoint_bytes(st->n_beams, st->m, nsteps, every);
   if (need > 0 && (!ckpt || ckpt_bytes < need)) return SHGB_EWORKSPACE;
-  return hip_status(launch_step_checkpointed(md, *st, nsteps, dt, seed, every, ckpt, diag, (hipStream_t)stream));
+  return hip_status(
+      launch_step_checkpointed(md, *st, nsteps, dt, seed, every, ckpt, nullptr, diag, (hipStream_t)stream));
 }
 
 int64_t shgb_population_adjoint_workspace(int64_t n_beams, int32_t m, int32_t every) {
   if (n_beams < 0 || m < 2 || m > 2 * SHGB_MAX_D || (m & 1) || every < 1) return -1;
   if (m != 2 && !adjoint_wave_supported(m / 2)) return -1;
-  return m == 2 ? adj_m2_workspace_bytes(n_beams, every) : adj_wave_workspace_bytes(n_beams, m, every);
+  return m == 2 ? adj_m2_workspace_bytes(n_beams, every) : adj_wave_workspace_bytes(n_beams, m, every, false);
+}
+
+int64_t shgb_record_bytes(int64_t n_beams, int32_t m, int32_t nsteps, int32_t every) {
+  if (n_beams < 0 || m < 4 || m > 2 * SHGB_MAX_D || (m & 1) || nsteps < 0 || every < 1) return -1;
+  if (!adjoint_wave_supported(m / 2)) return -1;
+  const int64_t n_seg = ((int64_t)nsteps + every - 1) / every;
+  return n_seg * n_beams * (int64_t)every * adj_interval_rec(m / 2) * 8;
+}
+
+int shgb_step_recorded(const shgb_model *model, const shgb_state *st, int32_t nsteps, double dt, uint64_t seed,
+                       int32_t every, void *ckpt, int64_t ckpt_bytes, double *recs, int64_t recs_bytes,
+                       uint64_t *diag, void *stream) {
+  DevModel md;
+  int rc = to_dev_model(model, md);
+  if (rc) return rc;
+  if ((rc = check_state(st, md))) return rc;
+  if (nsteps < 0 || !finite_pos(dt) || every < 1) return SHGB_EINVAL;
+  if (!adjoint_supported(md, st) || st->m == 2) return SHGB_EUNSUPPORTED;
+  const int64_t need = shgb_checkpoint_bytes(st->n_beams, st->m, nsteps, every);
+  if (need > 0 && (!ckpt || ckpt_bytes < need)) return SHGB_EWORKSPACE;
+  const int64_t rneed = shgb_record_bytes(st->n_beams, st->m, nsteps, every);
+  if (rneed > 0 && (!recs || recs_bytes < rneed)) return SHGB_EWORKSPACE;
+  if (rneed == 0) recs = nullptr;   // nothing to record: the plain kernels
+  return hip_status(launch_step_checkpointed(md, *st, nsteps, dt, seed, every, ckpt, recs, diag, (hipStream_t)stream));
+}
+
+int64_t shgb_population_adjoint_recorded_workspace(int64_t n_beams, int32_t m, int32_t every) {
+  if (n_beams < 0 || m < 4 || m > 2 * SHGB_MAX_D || (m & 1) || every < 1) return -1;
+  if (!adjoint_wave_supported(m / 2)) return -1;
+  return adj_wave_workspace_bytes(n_beams, m, every, true);
+}
+
+int shgb_population_adjoint_recorded(const shgb_model *model, const shgb_state *st, const void *ckpt,
+                                     const double *recs, int32_t nsteps, double dt, uint64_t seed, int32_t every,
+                                     const double *cot, int64_t n_traj, double *out, void *work, int64_t work_bytes,
+                                     void *stream) {
+  DevModel md;
+  int rc = to_dev_model(model, md);
+  if (rc) return rc;
+  if ((rc = check_state(st, md))) return rc;
+  if (nsteps < 0 || !finite_pos(dt) || every < 1 || n_traj < 1 || !cot || !out) return SHGB_EINVAL;
+  if (!adjoint_supported(md, st) || st->m == 2) return SHGB_EUNSUPPORTED;
+  if (shgb_checkpoint_bytes(st->n_beams, st->m, nsteps, every) > 0 && !ckpt) return SHGB_EINVAL;
+  if (shgb_record_bytes(st->n_beams, st->m, nsteps, every) > 0 && !recs) return SHGB_EINVAL;
+  if (!work || work_bytes < shgb_population_adjoint_recorded_workspace(st->n_beams, st->m, every))
+    return SHGB_EWORKSPACE;
+  return hip_status(launch_adjoint_wave(md, *st, ckpt, recs, nsteps, dt, seed, every, cot, n_traj, out, work,
+                                        (hipStream_t)stream));
 }
 
 int shgb_population_adjoint(const shgb_model *model, const shgb_state *st, const void *ckpt, int32_t nsteps, double dt,
@@ -422,7 +471,7 @@ int shgb_population_adjoint(const shgb_model *model, const shgb_state *st, const
   if (st->m == 2)
     return hip_status(launch_adjoint_m2(md, *st, ckpt, nsteps, dt, seed, every, cot, n_traj, out, work,
                                         (hipStream_t)stream));
-  return hip_status(launch_adjoint_wave(md, *st, ckpt, nsteps, dt, seed, every, cot, n_traj, out, work,
+  return hip_status(launch_adjoint_wave(md, *st, ckpt, nullptr, nsteps, dt, seed, every, cot, n_traj, out, work,
                                         (hipStream_t)stream));
 }
 

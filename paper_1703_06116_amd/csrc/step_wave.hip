@@ -936,40 +936,42 @@ step_wave_batched(const BatchItem *__restrict__ items, int n_items, int64_t tota
 
 // The FP64 stepping kernel that also writes, for every interval, the stage
 // records of its trial step, its component and whether it has a hop (the
-// replay of a segment for the reverse sweep; records of beam b, interval i at
-// recs + (b every + i) adj_interval_rec(d)).
+// forward run that keeps its records, or the replay of a segment for the
+// reverse sweep; records of beam b, interval i at
+// recs + (b every + i) adj_interval_rec(d)).  diag may be null.
 template <int D, int LPB>
 __global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(2)))
 step_wave_rec_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
                      uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps, double dt,
-                     uint64_t seed, double *__restrict__ recs, int every) {
+                     uint64_t seed, double *__restrict__ recs, int every, uint64_t *diag) {
   __shared__ TileLds<D, LPB, double, kWavesPerBlock> tl;
   static_assert(sizeof(tl.ex) <= 65536, "16-bit LDS addresses (PgAddr)");
   Counters cnt;
   wave_tile<D, LPB, double, kWavesPerBlock, true>(md, tr, sc, comp, nhop, n, ld, gid0, nsteps, dt, seed,
                                                   xcd_line_tile<tiles_per_line<D, LPB, double>()>(blockIdx.x, gridDim.x),
                                                   tl, cnt, recs, every);
+  flush_counters(cnt, diag);
 }
 
 template <int D, int LPB>
 static void launch_pg_rec(const DevModel &md, const shgb_state &st, int nsteps, double dt, uint64_t seed,
-                          double *recs, int every, hipStream_t stream) {
+                          double *recs, int every, uint64_t *diag, hipStream_t stream) {
   constexpr int beams_per_block = kWavesPerBlock * PG<D, LPB>::G;
   const int64_t blocks = (st.n_beams + beams_per_block - 1) / beams_per_block;
   hipLaunchKernelGGL((step_wave_rec_kernel<D, LPB>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, stream,
                      md, st.f64, scalar_block(st), st.comp, st.nhop, st.n_beams, st.ld, st.beam_id_offset, nsteps,
-                     dt, seed, recs, every);
+                     dt, seed, recs, every, diag);
 }
 
 hipError_t launch_step_wave_record(const DevModel &md, const shgb_state &st, int nsteps, double dt, uint64_t seed,
-                                   double *recs, int every, hipStream_t stream) {
+                                   double *recs, int every, uint64_t *diag, hipStream_t stream) {
   if (st.n_beams == 0 || nsteps == 0) return hipSuccess;
   if (mixed(st) || nsteps > every) return hipErrorInvalidValue;
   switch (md.d) {
-    case 2: launch_pg_rec<2, 8>(md, st, nsteps, dt, seed, recs, every, stream); break;
-    case 3: launch_pg_rec<3, 8>(md, st, nsteps, dt, seed, recs, every, stream); break;
-    case 4: launch_pg_rec<4, 8>(md, st, nsteps, dt, seed, recs, every, stream); break;
-    case 12: launch_pg_rec<12, kLanesPerBeamD12>(md, st, nsteps, dt, seed, recs, every, stream); break;
+    case 2: launch_pg_rec<2, 8>(md, st, nsteps, dt, seed, recs, every, diag, stream); break;
+    case 3: launch_pg_rec<3, 8>(md, st, nsteps, dt, seed, recs, every, diag, stream); break;
+    case 4: launch_pg_rec<4, 8>(md, st, nsteps, dt, seed, recs, every, diag, stream); break;
+    case 12: launch_pg_rec<12, kLanesPerBeamD12>(md, st, nsteps, dt, seed, recs, every, diag, stream); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -114,6 +114,11 @@ def _load():
         "shgb_step_checkpointed": (I32, [P(Model), P(StateDesc), I32, D, U64, I32, V, I64, V, V]),
         "shgb_population_adjoint_workspace": (I64, [I64, I32, I32]),
         "shgb_population_adjoint": (I32, [P(Model), P(StateDesc), V, I32, D, U64, I32, V, I64, V, V, I64, V]),
+        "shgb_record_bytes": (I64, [I64, I32, I32, I32]),
+        "shgb_step_recorded": (I32, [P(Model), P(StateDesc), I32, D, U64, I32, V, I64, V, I64, V, V]),
+        "shgb_population_adjoint_recorded_workspace": (I64, [I64, I32, I32]),
+        "shgb_population_adjoint_recorded": (I32, [P(Model), P(StateDesc), V, V, I32, D, U64, I32, V, I64, V, V, I64,
+                                                   V]),
         "shgb_batch_table_bytes": (I64, [I32]),
         "shgb_batch_prepare": (I32, [P(Model), P(StateDesc), P(U64), I32, P(BatchConfig), V, I64, P(BatchDesc)]),
         "shgb_step_batched": (I32, [P(BatchDesc), I32, D, V, I64, V, V]),
@@ -139,7 +144,8 @@ EXPORTED = ("shgb_init_beams", "shgb_step_ensemble", "shgb_step_ensemble_scheme"
             "shgb_strerror", "shgb_version", "shgb_abi_sizes", "shgb_batch_table_bytes", "shgb_batch_prepare",
             "shgb_step_batched", "shgb_population_tangent_workspace", "shgb_population_tangent",
             "shgb_checkpoint_bytes", "shgb_step_checkpointed", "shgb_population_adjoint_workspace",
-            "shgb_population_adjoint")
+            "shgb_population_adjoint", "shgb_record_bytes", "shgb_step_recorded",
+            "shgb_population_adjoint_recorded_workspace", "shgb_population_adjoint_recorded")
 
 
 def _check(fn, rc):
@@ -403,6 +409,49 @@ def population_adjoint(model, state, ckpt, nsteps, dt, seed, cot, n_traj, every=
     _check("shgb_population_adjoint", _lib.shgb_population_adjoint(
         ctypes.byref(model), ctypes.byref(d), _ptr(ckpt), nsteps, float(dt), seed, every, _ptr(cot), int(n_traj),
         _ptr(out), _ptr(work), work.numel(), _stream(stream)))
+    return out
+
+
+def record_bytes(n, m, nsteps, every):
+    return int(_lib.shgb_record_bytes(n, m, nsteps, every))
+
+
+def step_recorded(model, state, nsteps, dt, seed, every=100, ckpt=None, recs=None, diag=None, stream=None):
+    """step_checkpointed that also keeps every interval's stage records (d > 1) in recs (a float64
+    device tensor of record_bytes / 8 elements, allocated here if not given); returns (ckpt, recs)."""
+    dev = state.f64.device
+    nb = checkpoint_bytes(state.n, state.m, nsteps, every)
+    if ckpt is None:
+        ckpt = torch.empty(max(nb, 8), dtype=torch.uint8, device=dev)
+    rb = record_bytes(state.n, state.m, nsteps, every)
+    if recs is None:
+        recs = torch.empty(max(rb, 8) // 8, dtype=torch.float64, device=dev)
+    assert recs.dtype == torch.float64 and recs.is_contiguous()
+    d = state.desc()
+    _check("shgb_step_recorded", _lib.shgb_step_recorded(ctypes.byref(model), ctypes.byref(d), nsteps, float(dt),
+                                                         seed, every, _ptr(ckpt), ckpt.numel(), _ptr(recs),
+                                                         recs.numel() * 8, _ptr(diag), _stream(stream)))
+    return ckpt, recs
+
+
+def population_adjoint_recorded_workspace(n, m, every):
+    return int(_lib.shgb_population_adjoint_recorded_workspace(n, m, every))
+
+
+def population_adjoint_recorded(model, state, ckpt, recs, nsteps, dt, seed, cot, n_traj, every=100, out=None,
+                                work=None, stream=None):
+    """population_adjoint from the records step_recorded kept (no replay of the segments)."""
+    dev = state.f64.device
+    assert cot.dtype == torch.float64 and cot.is_contiguous() and cot.numel() >= 2 * SHGB_NCOMP
+    if out is None:
+        out = torch.empty(6, dtype=torch.float64, device=dev)
+    nb = population_adjoint_recorded_workspace(state.n, state.m, every)
+    if work is None:
+        work = torch.empty(max(nb, 8), dtype=torch.uint8, device=dev)
+    d = state.desc()
+    _check("shgb_population_adjoint_recorded", _lib.shgb_population_adjoint_recorded(
+        ctypes.byref(model), ctypes.byref(d), _ptr(ckpt), _ptr(recs), nsteps, float(dt), seed, every, _ptr(cot),
+        int(n_traj), _ptr(out), _ptr(work), work.numel(), _stream(stream)))
     return out
 
 

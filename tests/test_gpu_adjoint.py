@@ -100,3 +100,70 @@ def test_adjoint_edge_cases(gpu):
     mx = gpu.State(5, 2, precision="mixed")
     with pytest.raises(gpu.ShgbError):
         gpu.step_checkpointed(mdl, mx, 10, 0.5, 1)
+
+
+# The forward run that keeps its stage records: the same checkpoints, final
+# state and event counts as the checkpointed run, and, from those records,
+# bitwise the reverse sweep that runs each segment again (both sweeps read
+# records written by the same recording kernel from the same states).
+@pytest.mark.parametrize("d,n,nsteps,every", [(2, 2 * 128 + 5, 300, 100), (3, 70, 200, 64),
+                                              (12, 2 * 64 + 3, 250, 100), (12, 37, 130, 64),
+                                              (12, 65536 + 37, 60, 48)])
+def test_kept_records_equal_replay(gpu, d, n, nsteps, every):
+    cfg = crossing_cfg(n, nsteps, d=d)
+    mdl = gpu_model(cfg)
+    m = 2 * d
+    st = gpu.State(n, m)
+    gpu.init_beams(mdl, gpu_spec(cfg), st, cfg["seed"])
+    ref = gpu.State(n, m)
+    gpu.init_beams(mdl, gpu_spec(cfg), ref, cfg["seed"])
+    dg, dref = gpu.new_diag(), gpu.new_diag()
+    # zeroed buffers: a checkpoint's rows are padded to 256 bytes, and padding is never written
+    nb = gpu.checkpoint_bytes(n, m, nsteps, every)
+    ckpt, recs = gpu.step_recorded(mdl, st, nsteps, cfg["dt"], cfg["seed"], every=every, diag=dg,
+                                   ckpt=torch.zeros(nb, dtype=torch.uint8, device="cuda"))
+    assert recs.numel() * 8 == gpu.record_bytes(n, m, nsteps, every)
+    ckref = gpu.step_checkpointed(mdl, ref, nsteps, cfg["dt"], cfg["seed"], every=every, diag=dref,
+                                  ckpt=torch.zeros(nb, dtype=torch.uint8, device="cuda"))
+    assert torch.equal(st.f64, ref.f64) and torch.equal(st.comp, ref.comp) and torch.equal(st.nhop, ref.nhop)
+    assert torch.equal(ckpt, ckref)
+    assert (dg.cpu().numpy() == dref.cpu().numpy()).all()
+    assert int(st.nhop.sum()) > 0
+    rng = np.random.default_rng(11)
+    for cot in ([1.0, 0, 0, 0, 0, 0, 0, 0], list(rng.normal(size=8))):
+        c = torch.tensor(cot, dtype=torch.float64, device="cuda")
+        a = gpu.population_adjoint(mdl, st, ckpt, nsteps, cfg["dt"], cfg["seed"], c, n, every=every)
+        b = gpu.population_adjoint_recorded(mdl, st, ckpt, recs, nsteps, cfg["dt"], cfg["seed"], c, n, every=every)
+        print(d, n, nsteps, every, "replay", a.cpu().numpy(), "kept", b.cpu().numpy())
+        assert torch.equal(a, b)
+    assert gpu.population_adjoint_recorded_workspace(n, m, every) < gpu.population_adjoint_workspace(n, m, every)
+
+
+def test_kept_records_edge_cases(gpu):
+    cfg = crossing_cfg(7, 10, d=12)
+    mdl = gpu_model(cfg)
+    cot = torch.ones(8, dtype=torch.float64, device="cuda")
+    # no intervals: no records; the gradient is zero and L the initial populations
+    st = gpu.State(7, 24)
+    gpu.init_beams(mdl, gpu_spec(cfg), st, cfg["seed"])
+    assert gpu.record_bytes(7, 24, 0, 100) == 0
+    ck, recs = gpu.step_recorded(mdl, st, 0, 0.5, cfg["seed"])
+    out = gpu.population_adjoint_recorded(mdl, st, ck, recs, 0, 0.5, cfg["seed"], cot, 7).cpu().numpy()
+    assert (out[:5] == 0).all() and abs(out[5] - 1.0) < 1e-12
+    # an empty ensemble
+    e = gpu.State(0, 24)
+    ck, recs = gpu.step_recorded(mdl, e, 10, 0.5, 1)
+    out = gpu.population_adjoint_recorded(mdl, e, ck, recs, 10, 0.5, 1, cot, 1).cpu().numpy()
+    assert (out == 0).all()
+    # records too small, and the one-dimensional model (its adjoint has no records to keep)
+    st = gpu.State(7, 24)
+    gpu.init_beams(mdl, gpu_spec(cfg), st, cfg["seed"])
+    small = torch.empty(gpu.record_bytes(7, 24, 10, 100) // 8 - 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu.ShgbError):
+        gpu.step_recorded(mdl, st, 10, 0.5, 1, recs=small)
+    c1 = crossing_cfg(5, 10)
+    s1 = gpu.State(5, 2)
+    gpu.init_beams(gpu_model(c1), gpu_spec(c1), s1, c1["seed"])
+    assert gpu.record_bytes(5, 2, 10, 100) == -1
+    with pytest.raises(gpu.ShgbError):
+        gpu.step_recorded(gpu_model(c1), s1, 10, 0.5, 1, recs=small)

@@ -236,3 +236,52 @@ def test_zero_work_calls_launch_nothing(binding):
     assert lib.shgb_step_ensemble(by(mdl), by(_desc(binding)), 0, 0.5, 1, nul, nul) == 0
     assert lib.shgb_hop(by(mdl), by(_desc(binding)), nul, 0, 1, nul, nul) == 0
     assert lib.shgb_philox(1, nul, nul, 0, nul) == 0
+
+
+def test_kept_record_sizes_and_validation(binding):
+    """Sizes of the kept stage records (8 (4 (3 + 4d) + 2) bytes per beam and interval, whole
+    segments) and the argument checks of the entry points that use them, before any device work."""
+    lib = binding._lib
+    by = ctypes.byref
+    nul = ctypes.c_void_p(0)
+    EINVAL, EUNS, EWS = -1, -2, -4
+    assert lib.shgb_record_bytes(10, 24, 250, 100) == 3 * 10 * 100 * (4 * (3 + 4 * 12) + 2) * 8
+    assert lib.shgb_record_bytes(10, 4, 100, 100) == 10 * 100 * (4 * (3 + 8) + 2) * 8
+    assert lib.shgb_record_bytes(10, 24, 0, 100) == 0
+    assert lib.shgb_record_bytes(10, 2, 100, 100) == -1       # the 1-D adjoint keeps no records
+    assert lib.shgb_record_bytes(10, 10, 100, 100) == -1      # d = 5: no adjoint
+    assert lib.shgb_record_bytes(10, 24, 100, 0) == -1
+    assert lib.shgb_population_adjoint_recorded_workspace(10, 2, 100) == -1
+    for n, every in ((1, 1), (65536 + 37, 48), (1000, 100)):
+        kept = lib.shgb_population_adjoint_recorded_workspace(n, 24, every)
+        replay = lib.shgb_population_adjoint_workspace(n, 24, every)
+        assert 0 < kept < replay
+        assert replay - kept == min(n, 65536) * every * (4 * (3 + 4 * 12) + 2) * 8
+    m12 = binding.make_model(12, mass=2000.0, eps=0.02, A=0.01, B=1.6, C=0.005, D=1.0, lam=1e-3,
+                             bath_omega=[0.01] * 11)
+    st = _desc(binding, n=16, m=24)
+    fake = ctypes.c_void_p(0x1000)
+    need_c = lib.shgb_checkpoint_bytes(16, 24, 10, 5)
+    need_r = lib.shgb_record_bytes(16, 24, 10, 5)
+    # records missing or too small; bad step parameters
+    assert lib.shgb_step_recorded(by(m12), by(st), 10, 0.5, 1, 5, fake, need_c, nul, 0, nul, nul) == EWS
+    assert lib.shgb_step_recorded(by(m12), by(st), 10, 0.5, 1, 5, fake, need_c, fake, need_r - 1, nul, nul) == EWS
+    assert lib.shgb_step_recorded(by(m12), by(st), 10, 0.5, 1, 5, fake, need_c - 1, fake, need_r, nul, nul) == EWS
+    assert lib.shgb_step_recorded(by(m12), by(st), 10, 0.0, 1, 5, fake, need_c, fake, need_r, nul, nul) == EINVAL
+    assert lib.shgb_step_recorded(by(m12), by(st), 10, 0.5, 1, 0, fake, need_c, fake, need_r, nul, nul) == EINVAL
+    # the 1-D model and a mixed state are not supported
+    m1 = _model(binding)
+    assert lib.shgb_step_recorded(by(m1), by(_desc(binding)), 10, 0.5, 1, 5, fake, 1 << 30, fake, 1 << 30, nul,
+                                  nul) == EUNS
+    mx = _desc(binding, n=16, m=24)
+    mx.precision = binding.PRECISION["mixed"]
+    mx.f32 = 0x1000
+    assert lib.shgb_step_recorded(by(m12), by(mx), 10, 0.5, 1, 5, fake, need_c, fake, need_r, nul, nul) == EUNS
+    # the reverse sweep from kept records: null records, small workspace, null cotangent
+    ws = lib.shgb_population_adjoint_recorded_workspace(16, 24, 5)
+    assert lib.shgb_population_adjoint_recorded(by(m12), by(st), fake, nul, 10, 0.5, 1, 5, fake, 16, fake, fake,
+                                                ws, nul) == EINVAL
+    assert lib.shgb_population_adjoint_recorded(by(m12), by(st), fake, fake, 10, 0.5, 1, 5, fake, 16, fake, fake,
+                                                ws - 1, nul) == EWS
+    assert lib.shgb_population_adjoint_recorded(by(m12), by(st), fake, fake, 10, 0.5, 1, 5, nul, 16, fake, fake,
+                                                ws, nul) == EINVAL
