@@ -997,6 +997,32 @@ __global__ void __launch_bounds__(256) aw_ckpt_load_kernel(const double *__restr
 // latencies of the exchange area and of the FP64 chains are hidden by the
 // second wavefront (1.29 s against 1.56 s for the d = 12 gradient workload;
 // at three wavefronts the spills cost more than the occupancy gains).
+// The records of one interval, copied into a per-wave LDS buffer by 16-byte
+// buffer loads with an LDS destination (lane l writes bytes [16 l, 16 l + 16)
+// of the wave's destination; gfx950), one interval ahead of their use, so
+// that the stage products read them from LDS and the copy's latency is spent
+// under the previous interval's work.  Two instructions cover the 2048
+// bytes of a buffer; reads past the records' end return zeros (the
+// descriptor's byte count), so nothing is read out of bounds.
+constexpr int kAwRecBuf = 256;   // doubles per buffer
+constexpr int kAwBufferFlags = 0x00020000;   // word 3 of a raw (untyped) buffer resource on gfx9
+
+template <int D>
+__device__ inline double *aw_recbuf(int k) {
+  static_assert(adj_interval_rec(D) <= kAwRecBuf, "one interval's records fit a buffer");
+  __shared__ double buf[kAwWaves][2][kAwRecBuf];
+  return buf[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)][k];
+}
+
+__device__ inline void aw_rec_fetch(const double *src, int64_t avail, double *dst, int lane) {
+  typedef __attribute__((address_space(3))) void *lds_ptr;
+  const int64_t bytes = avail * 8;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)src, 0, (int)(bytes < 0x7fffffff ? bytes : 0x7fffffff), kAwBufferFlags);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr)dst, 16, 16 * lane, 0, 0, 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr)(dst + 128), 16, 16 * lane + 1024, 0, 0, 0);
+}
+
 template <int D>
 __global__ void __launch_bounds__(kAwLanes * kAwWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
 aw_reverse_kernel(DevModel md, const double *__restrict__ cf, const int32_t *__restrict__ ci, int64_t n, int len,
@@ -1021,9 +1047,13 @@ aw_reverse_kernel(DevModel md, const double *__restrict__ cf, const int32_t *__r
   aw_get<D>(yb, ybuf + w * NF * kAwLanes, lane);
   double th[4] = {row[0], row[1], row[2], row[3]};
   const double logwb = row[kBscLogwb];
+  // (the wave's records are rw[0, len RS): interval j's copy may read (len - j) RS doubles)
+  if (len > 0) aw_rec_fetch(rw + (int64_t)(len - 1) * RS, RS, aw_recbuf<D>((len - 1) & 1), lane);
   for (int i = len - 1; i >= 0; --i) {
     aw_opaque<D>(cx);
-    const double *r = rw + (int64_t)i * RS;
+    __builtin_amdgcn_s_waitcnt(0);   // interval i's records have landed (and every earlier access is done)
+    if (i > 0) aw_rec_fetch(rw + (int64_t)(i - 1) * RS, (int64_t)(len - i + 1) * RS, aw_recbuf<D>((i - 1) & 1), lane);
+    const double *r = aw_recbuf<D>(i & 1);
     if (r[AwT<D>::RREC + 1] == 0.0) {
       aw_rk4_rev_fast<D>(md, (int)r[AwT<D>::RREC], cx, r, dt, yb, th, s);
     } else {
