@@ -440,12 +440,12 @@ __device__ inline void aw_vjp(const DevModel &md, int l, const typename AwT<D>::
   double Xb = 0.0, Pb = 0.0;
   if (lane < D) {
     const int i = lane;
-    Xb = i == 0 ? -lam * sumX : -lam * gXp0 - md.bath_k[i] * gxo;
+    Xb = i == 0 ? -lam * sumX : -lam * gXp0 - s.hk[i] * gxo;
     Pb = -gpo * im;
   } else if (lane < 2 * D) {
     const int i = lane - D;
     Xb = gxo * im + (i == 0 ? 2.0 * sgn * k.d21 * gL * im : 0.0);
-    Pb = i == 0 ? H00 * gPr0 + lam * sumP - sg * k.s3 * gi00 : lam * gPr0 + md.bath_k[i] * gpo;
+    Pb = i == 0 ? H00 * gPr0 + lam * sumP - sg * k.s3 * gi00 : lam * gPr0 + s.hk[i] * gpo;
   }
   Hb += Pp0 * gPr0;
   double sb[5];
@@ -1054,7 +1054,7 @@ aw_reverse_kernel(DevModel md, const double *__restrict__ cf, const int32_t *__r
     __builtin_amdgcn_s_waitcnt(0);   // interval i's records have landed (and every earlier access is done)
     if (i > 0) aw_rec_fetch(rw + (int64_t)(i - 1) * RS, (int64_t)(len - i + 1) * RS, aw_recbuf<D>((i - 1) & 1), lane);
     const double *r = aw_recbuf<D>(i & 1);
-    if (r[AwT<D>::RREC + 1] == 0.0) {
+    if (__builtin_expect(r[AwT<D>::RREC + 1] == 0.0, 1)) {   // (the hop path is the cold one)
       aw_rk4_rev_fast<D>(md, (int)r[AwT<D>::RREC], cx, r, dt, yb, th, s);
     } else {
       aw_put<D>(yb, io, lane);
