@@ -1025,10 +1025,10 @@ __device__ inline void aw_rec_fetch(const double *src, int64_t avail, double *ds
 
 template <int D>
 __global__ void __launch_bounds__(kAwLanes * kAwWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
-aw_reverse_kernel(DevModel md, const double *__restrict__ cf, const int32_t *__restrict__ ci, int64_t n, int len,
-                  int every, int first, int64_t b0, int64_t nb, uint64_t gid0, uint64_t seed, double dt,
-                  const double *__restrict__ recs, double *__restrict__ ybuf, double *__restrict__ bsc,
-                  double *__restrict__ gen) {
+aw_reverse_kernel(DevModel md, const char *__restrict__ ckpt, int64_t ckpt_stride, int64_t rows, int64_t n,
+                  int nsteps, int every, int c_hi, int c_lo, int64_t b0, int64_t nb, uint64_t gid0, uint64_t seed,
+                  double dt, const double *__restrict__ recs, int64_t seg_stride, double *__restrict__ ybuf,
+                  double *__restrict__ bsc, double *__restrict__ gen) {
   using Y = typename AwT<D>::Y;
   constexpr int NF = AwT<D>::NF, RS = adj_interval_rec(D);
   const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1039,7 +1039,6 @@ aw_reverse_kernel(DevModel md, const double *__restrict__ cf, const int32_t *__r
   pg_fill_const<D, kAwLanes, double>(lane, md.bath_k, s);
   const int64_t b = b0 + w;
   const uint64_t gid = gid0 + (uint64_t)b;
-  const double *rw = recs + w * (int64_t)every * RS;
   double *g = gen + w * aw_gen_doubles<D>();
   double *io = g + AwT<D>::REC + AwT<D>::RREC;
   double *row = bsc + b * kAdjVals;
@@ -1047,32 +1046,42 @@ aw_reverse_kernel(DevModel md, const double *__restrict__ cf, const int32_t *__r
   aw_get<D>(yb, ybuf + w * NF * kAwLanes, lane);
   double th[4] = {row[0], row[1], row[2], row[3]};
   const double logwb = row[kBscLogwb];
-  // (the wave's records are rw[0, len RS): interval j's copy may read (len - j) RS doubles)
-  if (len > 0) aw_rec_fetch(rw + (int64_t)(len - 1) * RS, RS, aw_recbuf<D>((len - 1) & 1), lane);
-  for (int i = len - 1; i >= 0; --i) {
-    aw_opaque<D>(cx);
-    __builtin_amdgcn_s_waitcnt(0);   // interval i's records have landed (and every earlier access is done)
-    if (i > 0) aw_rec_fetch(rw + (int64_t)(i - 1) * RS, (int64_t)(len - i + 1) * RS, aw_recbuf<D>((i - 1) & 1), lane);
-    const double *r = aw_recbuf<D>(i & 1);
-    if (__builtin_expect(r[AwT<D>::RREC + 1] == 0.0, 1)) {   // (the hop path is the cold one)
-      aw_rk4_rev_fast<D>(md, (int)r[AwT<D>::RREC], cx, r, dt, yb, th, s);
-    } else {
-      aw_put<D>(yb, io, lane);
-      aw_mem_sync();
-      aw_interval_rev_hop<D>(md, cf, ci, n, b, i, io, gid, seed, dt, logwb, g, g + AwT<D>::REC);
-      aw_get<D>(yb, io, lane);
+  // segments c_hi down to c_lo: checkpoint c at ckpt + c ckpt_stride, its
+  // records (every RS doubles per beam) at recs + (c - c_lo) seg_stride
+  for (int c = c_hi; c >= c_lo; --c) {
+    const char *base = ckpt + (int64_t)c * ckpt_stride;
+    const double *cf = (const double *)base;
+    const int32_t *ci = (const int32_t *)(base + rows * n * 8);
+    const int len = nsteps - c * every < every ? nsteps - c * every : every;
+    const double *rw = recs + (int64_t)(c - c_lo) * seg_stride + w * (int64_t)every * RS;
+    // (the wave's records are rw[0, len RS): interval j's copy may read (len - j) RS doubles)
+    if (len > 0) aw_rec_fetch(rw + (int64_t)(len - 1) * RS, RS, aw_recbuf<D>((len - 1) & 1), lane);
+    for (int i = len - 1; i >= 0; --i) {
+      aw_opaque<D>(cx);
+      __builtin_amdgcn_s_waitcnt(0);   // interval i's records have landed (and every earlier access is done)
+      if (i > 0)
+        aw_rec_fetch(rw + (int64_t)(i - 1) * RS, (int64_t)(len - i + 1) * RS, aw_recbuf<D>((i - 1) & 1), lane);
+      const double *r = aw_recbuf<D>(i & 1);
+      if (__builtin_expect(r[AwT<D>::RREC + 1] == 0.0, 1)) {   // (the hop path is the cold one)
+        aw_rk4_rev_fast<D>(md, (int)r[AwT<D>::RREC], cx, r, dt, yb, th, s);
+      } else {
+        aw_put<D>(yb, io, lane);
+        aw_mem_sync();
+        aw_interval_rev_hop<D>(md, cf, ci, n, b, i, io, gid, seed, dt, logwb, g, g + AwT<D>::REC);
+        aw_get<D>(yb, io, lane);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) th[k] += io[NF * kAwLanes + k];
+        for (int k = 0; k < 4; ++k) th[k] += io[NF * kAwLanes + k];
+      }
     }
   }
   aw_put<D>(yb, ybuf + w * NF * kAwLanes, lane);
-  const double pb = __shfl(yb.x[0], D, 64);   // adjoint of p1 at the segment's start
+  const double pb = __shfl(yb.x[0], D, 64);   // adjoint of p1 at the run's start (after segment 0)
   if (lane == 0) {
     row[0] = th[0];
     row[1] = th[1];
     row[2] = th[2];
     row[3] = th[3];
-    if (first) row[4] = pb;
+    if (c_lo == 0) row[4] = pb;
   }
 }
 
@@ -1141,22 +1150,28 @@ hipError_t launch_aw(const DevModel &md, const shgb_state &fin, const void *ckpt
     rs.m = 2 * D;
     rs.precision = SHGB_FP64;
     rs.f32 = nullptr;
+    const char *ck = (const char *)ckpt;
+    if (kept) {
+      // every segment in one launch: each wavefront sweeps its beam's segments
+      // last to first from the kept records
+      if (cl.n_ckpt > 0)
+        hipLaunchKernelGGL(aw_reverse_kernel<D>, dim3(blocks), dim3(kAwLanes * kAwWaves), 0, stream, md, ck,
+                           cl.stride_bytes, cl.rows, n, nsteps, every, cl.n_ckpt - 1, 0, b0, nb, fin.beam_id_offset,
+                           seed, dt, kept + b0 * seg, n * seg, ybuf, bsc, gen);
+      continue;
+    }
     for (int c = cl.n_ckpt - 1; c >= 0; --c) {
       const int start = c * every, len = nsteps - start < every ? nsteps - start : every;
-      const char *base = (const char *)ckpt + (int64_t)c * cl.stride_bytes;
+      const char *base = ck + (int64_t)c * cl.stride_bytes;
       const double *cf = (const double *)base;
       const int32_t *ci = (const int32_t *)(base + cl.rows * n * 8);
-      const double *rr = recs;
-      if (kept) {
-        rr = kept + ((int64_t)c * n + b0) * seg;
-      } else {
-        hipLaunchKernelGGL(aw_ckpt_load_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, stream, cf, ci, n,
-                           cl.rows, b0, nb, chunk, rf, rcomp, rnhop);
-        const hipError_t e = launch_step_wave_record(md, rs, len, dt, seed, recs, every, nullptr, stream);
-        if (e != hipSuccess) return e;
-      }
-      hipLaunchKernelGGL(aw_reverse_kernel<D>, dim3(blocks), dim3(kAwLanes * kAwWaves), 0, stream, md, cf, ci, n,
-                         len, every, c == 0 ? 1 : 0, b0, nb, fin.beam_id_offset, seed, dt, rr, ybuf, bsc, gen);
+      hipLaunchKernelGGL(aw_ckpt_load_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, stream, cf, ci, n,
+                         cl.rows, b0, nb, chunk, rf, rcomp, rnhop);
+      const hipError_t e = launch_step_wave_record(md, rs, len, dt, seed, recs, every, nullptr, stream);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(aw_reverse_kernel<D>, dim3(blocks), dim3(kAwLanes * kAwWaves), 0, stream, md, ck,
+                         cl.stride_bytes, cl.rows, n, nsteps, every, c, c, b0, nb, fin.beam_id_offset, seed, dt, recs,
+                         (int64_t)0, ybuf, bsc, gen);
     }
   }
   return launch_adj_final(bsc, n, out, stream);   // n = 0: zeros
