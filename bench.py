@@ -62,14 +62,14 @@ FLOPS_PER_BEAM_STEP_M24 = 4 * 3616 + 13 * 650
 # per beam-point evaluation of the m = 24 field: the exponent as a contraction over
 # F = 325 features for Re and Im (4 F = 1300, the matrix-core work)
 FLOPS_PER_EVAL_M24 = 4 * 325
-# FP64 operations per beam-interval of the m = 24 reverse sweep: the segment's replay
-# (one RK4 step, 22914, by the stepping kernel that writes the stage records) and the
-# reverse kernel: four vector-Jacobian products of the right-hand side (each as costly as
-# the right-hand side without its two-level quantities, 3616 - 87, plus 62 for the
-# cotangents of those quantities and their pullback through the 5 x 5 Jacobian), the
-# Jacobian itself once per step (five directional derivatives, 2 x 87 each) and the
-# reverse Runge-Kutta combinations (4 per state double and stage)
-FLOPS_PER_BEAM_STEP_ADJ_M24 = FLOPS_PER_BEAM_STEP_M24 + 4 * (3616 - 87 + 62) + 5 * 2 * 87 + 16 * 650
+# FP64 operations per beam-interval of the m = 24 reverse kernel: four vector-Jacobian
+# products of the right-hand side (each as costly as the right-hand side without its
+# two-level quantities, 3616 - 87, plus 62 for the cotangents of those quantities and their
+# pullback through the 5 x 5 Jacobian), the Jacobian itself once per step (five directional
+# derivatives, 2 x 87 each) and the reverse Runge-Kutta combinations (4 per state double and
+# stage); a reverse sweep that runs each segment again adds the replay's RK4 step (22914)
+FLOPS_PER_BEAM_STEP_REV_M24 = 4 * (3616 - 87 + 62) + 5 * 2 * 87 + 16 * 650
+FLOPS_PER_BEAM_STEP_ADJ_M24 = FLOPS_PER_BEAM_STEP_M24 + FLOPS_PER_BEAM_STEP_REV_M24
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector and FP64 matrix: 256 CU x 64 lanes x 2 flop x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector
 PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
@@ -526,9 +526,12 @@ def run_batch(name, steps, warmup):
 
 
 def run_grad(name, steps, warmup, with_tangent):
-    """The derivative workload: the ensemble sampled, stepped with checkpoints every 100 intervals
+    """The derivative workload: the ensemble sampled, stepped with a checkpoint every 100 intervals
     and reduced to populations, then one reverse sweep for the gradient of the upper population in
-    (A, B, C, D, p_mean); beside it the plain FP64 forward run (init, step, populations)."""
+    (A, B, C, D, p_mean); beside it the plain FP64 forward run (init, step, populations).  For
+    d > 1 the timed gradient keeps every interval's stage records in HBM during the forward run
+    (shgb_step_recorded, 1648 bytes per beam and interval at d = 12) and the reverse sweep reads
+    them; the sweep that runs each segment again from its checkpoint instead is timed beside it."""
     import numpy as np
     import torch
     from paper_1703_06116_amd import shgb, workloads
@@ -536,6 +539,7 @@ def run_grad(name, steps, warmup, with_tangent):
     c = workloads.config(name)
     N, nsteps, dt, seed, m = c["n_beams"], c["nsteps"], c["dt"], c["seed"], 2 * c["d"]
     every = 100
+    kept_mode = m > 2
     mdl = shgb.make_model(c["d"], c["mass"], c["eps"], c["A"], c["B"], c["C"], c["D"], c["lam"], c["bath_omega"])
     spec = shgb.make_init_spec(c["q_mean"], c["q_std"], c["p_dist"], c["p_a"], c["p_b"], c["comp0"])
     dev = "cuda:0"
@@ -547,8 +551,13 @@ def run_grad(name, steps, warmup, with_tangent):
     grad = torch.empty(6, dtype=torch.float64, device=dev)
     pops = torch.empty((4, 5), dtype=torch.float64, device=dev)
     pop_work = torch.empty(max(shgb.populations_workspace(N, m), 8), dtype=torch.uint8, device=dev)
+    if kept_mode:
+        recs = torch.empty(shgb.record_bytes(N, m, nsteps, every) // 8, dtype=torch.float64, device=dev)
+        kwork = torch.empty(max(shgb.population_adjoint_recorded_workspace(N, m, every), 8), dtype=torch.uint8,
+                            device=dev)
+        grad_k = torch.empty(6, dtype=torch.float64, device=dev)
 
-    def grad_step(evs=None):
+    def replay_step(evs=None):
         def mark(i):
             if evs is not None:
                 evs[i].record()
@@ -560,23 +569,45 @@ def run_grad(name, steps, warmup, with_tangent):
         shgb.population_adjoint(mdl, st, ckpt, nsteps, dt, seed, cot, N, every=every, out=grad, work=adj_work)
         mark(2)
 
+    def kept_step(evs=None):
+        def mark(i):
+            if evs is not None:
+                evs[i].record()
+        mark(0)
+        shgb.init_beams(mdl, spec, st, seed)
+        shgb.step_recorded(mdl, st, nsteps, dt, seed, every=every, ckpt=ckpt, recs=recs)
+        shgb.populations(mdl, st, out=pops, work=pop_work)
+        mark(1)
+        shgb.population_adjoint_recorded(mdl, st, ckpt, recs, nsteps, dt, seed, cot, N, every=every, out=grad_k,
+                                         work=kwork)
+        mark(2)
+
     def forward_step():
         shgb.init_beams(mdl, spec, st, seed)
         shgb.step_ensemble(mdl, st, nsteps, dt, seed)
         shgb.populations(mdl, st, out=pops, work=pop_work)
 
-    for _ in range(warmup):
-        grad_step()
-    torch.cuda.synchronize()
-    evs = [[_timer() for _ in range(3)] for _ in range(steps)]
-    t0 = time.perf_counter()
-    for k in range(steps):
-        grad_step(evs[k])
-    torch.cuda.synchronize()
-    ms_grad = (time.perf_counter() - t0) * 1e3 / steps
-    fwd_ckpt_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    adj_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    g = grad.cpu().numpy()
+    def timed(step):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [[_timer() for _ in range(3)] for _ in range(steps)]
+        t0 = time.perf_counter()
+        for k in range(steps):
+            step(evs[k])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        return (ms, float(np.mean([e[0].elapsed_time(e[1]) for e in evs])),
+                float(np.mean([e[1].elapsed_time(e[2]) for e in evs])))
+
+    ms_rep, fwd_rep_ms, rev_rep_ms = timed(replay_step)
+    g_rep = grad.cpu().numpy()
+    if kept_mode:
+        ms_grad, fwd_part_ms, adj_ms = timed(kept_step)
+        g = grad_k.cpu().numpy()
+        del recs
+    else:
+        ms_grad, fwd_part_ms, adj_ms, g = ms_rep, fwd_rep_ms, rev_rep_ms, g_rep
     for _ in range(warmup):
         forward_step()
     torch.cuda.synchronize()
@@ -586,72 +617,41 @@ def run_grad(name, steps, warmup, with_tangent):
     torch.cuda.synchronize()
     ms_fwd = (time.perf_counter() - t0) * 1e3 / steps
     p = pops.cpu().numpy()
-    kept = None
-    if m > 2:
-        # the same gradient with every interval's stage records kept from the forward run (memory
-        # instead of the reverse sweep's replay of each segment)
-        del adj_work
-        recs = torch.empty(shgb.record_bytes(N, m, nsteps, every) // 8, dtype=torch.float64, device=dev)
-        kwork = torch.empty(max(shgb.population_adjoint_recorded_workspace(N, m, every), 8), dtype=torch.uint8,
-                            device=dev)
-        grad_k = torch.empty(6, dtype=torch.float64, device=dev)
-
-        def kept_step(evs=None):
-            def mark(i):
-                if evs is not None:
-                    evs[i].record()
-            mark(0)
-            shgb.init_beams(mdl, spec, st, seed)
-            shgb.step_recorded(mdl, st, nsteps, dt, seed, every=every, ckpt=ckpt, recs=recs)
-            shgb.populations(mdl, st, out=pops, work=pop_work)
-            mark(1)
-            shgb.population_adjoint_recorded(mdl, st, ckpt, recs, nsteps, dt, seed, cot, N, every=every, out=grad_k,
-                                             work=kwork)
-            mark(2)
-
-        for _ in range(warmup):
-            kept_step()
-        torch.cuda.synchronize()
-        evk = [[_timer() for _ in range(3)] for _ in range(steps)]
-        t0 = time.perf_counter()
-        for k in range(steps):
-            kept_step(evk[k])
-        torch.cuda.synchronize()
-        ms_kept = (time.perf_counter() - t0) * 1e3 / steps
-        gk = grad_k.cpu().numpy()
-        kept = {"ms_per_step": ms_kept, "gradient_over_forward": ms_kept / ms_fwd,
-                "kernel_ms": {"forward_with_records": float(np.mean([e[0].elapsed_time(e[1]) for e in evk])),
-                              "reverse_sweep": float(np.mean([e[1].elapsed_time(e[2]) for e in evk]))},
-                "record_bytes": int(recs.numel() * 8),
-                "max_rel_diff_vs_replay": float(np.abs(gk[:5] - g[:5]).max() / max(np.abs(g[:5]).max(), 1e-300)),
-                "note": "shgb_step_recorded + shgb_population_adjoint_recorded: the forward run keeps every "
-                        "interval's stage records in HBM and the reverse sweep reads them instead of running each "
-                        "segment again"}
-        del recs
-    tflops = FLOPS_PER_BEAM_STEP_ADJ_M24 * N * nsteps / (adj_ms / 1e3) / 1e12
+    rev_flops = FLOPS_PER_BEAM_STEP_REV_M24 if kept_mode else FLOPS_PER_BEAM_STEP_ADJ_M24
+    tflops = rev_flops * N * nsteps / (adj_ms / 1e3) / 1e12
     line = {
         "value": N * nsteps / (ms_grad / 1e3), "unit": "beam-steps/s", "ms_per_step": ms_grad,
         "steps": steps, "warmup": warmup, "dtype": "f64",
         "config": {"workload": name, "system": f"qcle-two-level-{c['d']}d", "n_beams": N, "intervals": nsteps,
-                   "dt": dt, "eps": c["eps"], "phase_space_dim": m, "parameters": 5, "checkpoint_every": every},
-        "note": "one gradient step = init + checkpointed forward + populations + one reverse sweep for all five "
-                "parameters; value counts each beam-step once",
-        "kernel_ms": {"forward_with_checkpoints": fwd_ckpt_ms, "reverse_sweep": adj_ms},
+                   "dt": dt, "eps": c["eps"], "phase_space_dim": m, "parameters": 5, "checkpoint_every": every,
+                   "stage_records": "kept from the forward run" if kept_mode else "replayed per segment"},
+        "note": ("one gradient step = init + forward run (checkpoints every 100 intervals" +
+                 (", every interval's stage records kept in HBM" if kept_mode else "") +
+                 ") + populations + one reverse sweep for all five parameters; value counts each beam-step "
+                 "once"),
+        "kernel_ms": {("forward_with_records" if kept_mode else "forward_with_checkpoints"): fwd_part_ms,
+                      "reverse_sweep": adj_ms},
         "forward_fp64_ms_per_step": ms_fwd,
         "gradient_over_forward": ms_grad / ms_fwd,
-        "gradient_over_forward_kept_records": kept["gradient_over_forward"] if kept else None,
-        "kept_records": kept,
+        "replayed_segments": ({"ms_per_step": ms_rep, "gradient_over_forward": ms_rep / ms_fwd,
+                               "kernel_ms": {"forward_with_checkpoints": fwd_rep_ms, "reverse_sweep": rev_rep_ms},
+                               "max_rel_diff_vs_kept": float(np.abs(g_rep[:5] - g[:5]).max() /
+                                                             max(np.abs(g[:5]).max(), 1e-300)),
+                               "note": "shgb_step_checkpointed + shgb_population_adjoint: no records kept; "
+                                       "the reverse sweep runs each segment again from its checkpoint"}
+                              if kept_mode else None),
+        "record_bytes": int(shgb.record_bytes(N, m, nsteps, every)) if kept_mode else 0,
         "upper_population": float(p[0, 0] / N),
         "objective_from_reverse_sweep": float(g[5]),
         "d_upper_population": {n: float(g[j]) for j, n in enumerate(("A", "B", "C", "D", "p_mean"))},
         "roofline": {"bound": "alu",
-                     "kernel": (f"reverse sweep: step_wave_rec_kernel<{c['d']}, 32> replay + aw_reverse_kernel<{c['d']}>"
-                                if m > 2 else "adjoint_m2_kernel"),
+                     "kernel": (f"reverse sweep: aw_reverse_kernel<{c['d']}> over all segments from kept records"
+                                if kept_mode else "adjoint_m2_kernel"),
                      "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tflops / PEAK_FP64_TFLOPS, "flops_per_unit": FLOPS_PER_BEAM_STEP_ADJ_M24,
+                     "frac": tflops / PEAK_FP64_TFLOPS, "flops_per_unit": rev_flops,
                      "units_per_launch": N * nsteps, "traffic": None,
-                     "note": "time of the whole reverse-sweep call (seed, per segment the replay and the reverse "
-                             "kernel): a lower bound on the reverse kernel's rate; the split per kernel is in "
+                     "note": "time of the whole reverse-sweep call (the seed kernel and the reverse kernel): a "
+                             "lower bound on the reverse kernel's rate; the split per kernel is in "
                              "profiles/adjoint_wave_qcle12d_grad.md"},
     }
     if with_tangent:
