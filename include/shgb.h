@@ -349,11 +349,17 @@ int shgb_population_adjoint(const shgb_model *model, const shgb_state *st, const
  * the RK4 stages of Sec. 2.4 step 3).  shgb_step_recorded advances the
  * ensemble as shgb_step_checkpointed does (the same checkpoints, the same
  * final state, hops and diag counts) and also writes those records of every
- * interval into recs: device memory of shgb_record_bytes, 8 (4 (3 + 4d) + 2)
- * bytes per beam and interval rounded up to whole segments of `every`
- * (1648 bytes per beam and interval at d = 12: 108 GB for 65536 beams and
- * 1000 intervals).  Segment c, beam b, interval i of the segment at
- * recs + ((c n_beams + b) every + i) (4 (3 + 4d) + 2) doubles.
+ * interval into recs, and the start state of each interval with a hop into
+ * one of 4 slots per beam and segment (the reverse sweep starts such an
+ * interval there instead of running its segment again up to it; a beam's
+ * fifth and later hop intervals of a segment get no slot): device memory of
+ * shgb_record_bytes, per beam and whole segment of `every` intervals
+ * 8 every (4 (3 + 4d) + 2) bytes of records and 4 slots of
+ * 8 (2m + m (m + 1) + 5, rounded up to even) bytes (d = 12: 1648 bytes per
+ * beam and interval and 4 x 5232 bytes per beam and segment, 122 GB for
+ * 65536 beams and 1000 intervals in segments of 100).  Segment c, beam b,
+ * interval i of the segment at recs + ((c n_beams + b) every + i)
+ * (4 (3 + 4d) + 2) doubles; the slots after the n_seg segments' records.
  * shgb_population_adjoint_recorded then gives what shgb_population_adjoint
  * gives for the same stepped state and checkpoints, without the replays; its
  * workspace (shgb_population_adjoint_recorded_workspace) holds no records.

@@ -149,6 +149,20 @@ enum LegKind : int { kLegAccept = 0, kLegPartial = 1, kLegEnd = 2, kLegNow = 3 }
 __host__ __device__ constexpr int adj_stage_rec(int d) { return 3 + 4 * d; }
 __host__ __device__ constexpr int adj_interval_rec(int d) { return 4 * adj_stage_rec(d) + 2; }
 
+// Start states of the intervals with a hop.  The recording stepping kernel
+// writes the state at the start of each interval of a segment on which the
+// beam hops into one of kAdjSlots slots of the beam (slot k for the interval
+// that starts with k hops made in the segment; later ones get none), and
+// the interval's hop flag in its record says which: 0 no hop, k + 1 slot k,
+// -1 a hop without a slot.  The reverse sweep starts such an interval from
+// its slot instead of running the segment again from its checkpoint up to
+// it.  A slot: the trajectory rows (ld = 1), then S, Lam, E, comp, nhop,
+// padded to an even count of doubles (16-byte aligned slots).
+constexpr int kAdjSlots = 4;
+__host__ __device__ constexpr int adj_slot_doubles(int d) {
+  return (2 * (2 * d) + (2 * d) * (2 * d + 1) + 5 + 1) / 2 * 2;
+}
+
 // Per-block partial sums of the reverse kernels: dA, dB, dC, dD, dp_mean, the
 // objective, two unused.
 constexpr int kAdjVals = 8;

@@ -6,9 +6,12 @@
 // whole state is copied into its checkpoint.  Splitting the run into calls
 // leaves an FP64 state bitwise as one call would.  With a record buffer
 // (d > 1) each segment is run by the recording stepping kernel instead,
-// which keeps every interval's stage records, so that the reverse sweep
-// need not run the segments again: segment c's records are at
-// recs + c n every adj_interval_rec(d), in the layout of one replay.
+// which keeps every interval's stage records and the start states of the
+// intervals with a hop, so that the reverse sweep need not run the segments
+// again: segment c's records are at recs + c n every adj_interval_rec(d),
+// in the layout of one replay, and after the n_seg segments' records come
+// the segments' slots, segment c's at
+// recs + n_seg n every adj_interval_rec(d) + c n kAdjSlots adj_slot_doubles(d).
 #include "adjoint.h"
 
 namespace shgb {
@@ -16,7 +19,7 @@ namespace shgb {
 hipError_t launch_step_m2(const DevModel &, const shgb_state &, int, double, uint64_t, uint64_t *, hipStream_t);
 hipError_t launch_step_wave(const DevModel &, const shgb_state &, int, double, uint64_t, uint64_t *, hipStream_t);
 hipError_t launch_step_wave_record(const DevModel &, const shgb_state &, int, double, uint64_t, double *, int,
-                                   uint64_t *, hipStream_t);
+                                   double *, uint64_t *, hipStream_t);
 
 // Copy the FP64 state (rows of ld) into a checkpoint (rows of n).
 __global__ void __launch_bounds__(256) ckpt_save_kernel(const double *__restrict__ f64, const int32_t *__restrict__ comp,
@@ -38,13 +41,17 @@ hipError_t launch_step_checkpointed(const DevModel &md, const shgb_state &st, in
   if (recs && st.m == 2) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)((st.n_beams + 255) / 256);
   const int64_t seg = st.n_beams * (int64_t)every * adj_interval_rec(st.m / 2);
+  const int64_t sseg = st.n_beams * (int64_t)kAdjSlots * adj_slot_doubles(st.m / 2);
+  double *slots = recs ? recs + cl.n_ckpt * seg : nullptr;
   for (int c = 0; c < cl.n_ckpt; ++c) {
     hipLaunchKernelGGL(ckpt_save_kernel, dim3(blocks), dim3(256), 0, stream, st.f64, st.comp, st.nhop, st.n_beams,
                        st.ld, cl.rows, (char *)ckpt + (int64_t)c * cl.stride_bytes);
     const int len = nsteps - c * every < every ? nsteps - c * every : every;
-    const hipError_t e = recs        ? launch_step_wave_record(md, st, len, dt, seed, recs + c * seg, every, diag, stream)
-                         : st.m == 2 ? launch_step_m2(md, st, len, dt, seed, diag, stream)
-                                     : launch_step_wave(md, st, len, dt, seed, diag, stream);
+    const hipError_t e =
+        recs        ? launch_step_wave_record(md, st, len, dt, seed, recs + c * seg, every, slots + c * sseg, diag,
+                                              stream)
+        : st.m == 2 ? launch_step_m2(md, st, len, dt, seed, diag, stream)
+                    : launch_step_wave(md, st, len, dt, seed, diag, stream);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();

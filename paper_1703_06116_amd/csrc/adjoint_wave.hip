@@ -791,15 +791,16 @@ __device__ inline void aw_load(const typename AwT<D>::Cx &cx, const double *f, c
 }
 
 // Reverse sweep of interval i of a segment that has a hop: its start is
-// found again by running the segment from its checkpoint (cf, ci; the beam's
-// column b), the adjoint of its end is at io (replaced by that of its
-// start), the parameter adjoints it adds go to io + NF 64; rec and rr
-// hold the stage values of one step.
+// read from its slot sl (written by the recording stepping kernel) or, when
+// it has none, found again by running the segment from its checkpoint
+// (cf, ci; the beam's column b); the adjoint of its end is at io (replaced
+// by that of its start), the parameter adjoints it adds go to io + NF 64;
+// rec and rr hold the stage values of one step.
 template <int D>
 __device__ __attribute__((noinline)) void aw_interval_rev_hop(const DevModel &md, const double *cf, const int32_t *ci,
-                                                              int64_t n, int64_t b, int i, double *io, uint64_t gid,
-                                                              uint64_t seed, double dt, double logwb, double *rec,
-                                                              double *rr) {
+                                                              int64_t n, int64_t b, int i, const double *sl,
+                                                              double *io, uint64_t gid, uint64_t seed, double dt,
+                                                              double logwb, double *rec, double *rr) {
   using Y = typename AwT<D>::Y;
   constexpr int NF = AwT<D>::NF;
   constexpr int M = 2 * D;
@@ -807,16 +808,33 @@ __device__ __attribute__((noinline)) void aw_interval_rev_hop(const DevModel &md
   typename AwT<D>::Lds &s = aw_lds<D>();
   const int64_t tro = (int64_t)(2 * M + M * (M + 1));
   Y ys, yb;
-  aw_load<D>(cx, cf, cf + tro * n, n, b, ys);
-  HopScalars hs = aw_ckpt_h(cf, ci, tro, n, b);
-  for (int k = 0; k < i; ++k) {
-    Y yt;
-    aw_rk4<D>(md, hs.comp, cx, ys, dt, yt, s, nullptr);
-    if (!(yt.Lam >= hs.E)) {
-      ys = yt;
-    } else {
-      double rem;
-      aw_legs_general<D>(md, cx, ys, hs, gid, seed, dt, -1, rem, s);
+  HopScalars hs;
+  if (sl) {
+    // the slot's trajectory rows as a state of one beam (ld = 1); its S and
+    // Lam follow them (aw_load's scalar reads land inside the rows and are
+    // replaced)
+    aw_load<D>(cx, sl, sl, 1, 0, ys);
+    ys.S = sl[tro];
+    ys.Lam = sl[tro + 1];
+    hs.logw = 0.0;
+    hs.phre = 1.0;
+    hs.phim = 0.0;
+    hs.Lam = 0.0;
+    hs.E = sl[tro + 2];
+    hs.comp = (int32_t)sl[tro + 3];
+    hs.nhop = (uint32_t)sl[tro + 4];
+  } else {
+    aw_load<D>(cx, cf, cf + tro * n, n, b, ys);
+    hs = aw_ckpt_h(cf, ci, tro, n, b);
+    for (int k = 0; k < i; ++k) {
+      Y yt;
+      aw_rk4<D>(md, hs.comp, cx, ys, dt, yt, s, nullptr);
+      if (!(yt.Lam >= hs.E)) {
+        ys = yt;
+      } else {
+        double rem;
+        aw_legs_general<D>(md, cx, ys, hs, gid, seed, dt, -1, rem, s);
+      }
     }
   }
   aw_get<D>(yb, io, cx.r);
@@ -1027,8 +1045,9 @@ template <int D>
 __global__ void __launch_bounds__(kAwLanes * kAwWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
 aw_reverse_kernel(DevModel md, const char *__restrict__ ckpt, int64_t ckpt_stride, int64_t rows, int64_t n,
                   int nsteps, int every, int c_hi, int c_lo, int64_t b0, int64_t nb, uint64_t gid0, uint64_t seed,
-                  double dt, const double *__restrict__ recs, int64_t seg_stride, double *__restrict__ ybuf,
-                  double *__restrict__ bsc, double *__restrict__ gen) {
+                  double dt, const double *__restrict__ recs, int64_t seg_stride, const double *__restrict__ slots,
+                  int64_t slot_stride, double *__restrict__ ybuf, double *__restrict__ bsc,
+                  double *__restrict__ gen) {
   using Y = typename AwT<D>::Y;
   constexpr int NF = AwT<D>::NF, RS = adj_interval_rec(D);
   const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1047,7 +1066,9 @@ aw_reverse_kernel(DevModel md, const char *__restrict__ ckpt, int64_t ckpt_strid
   double th[4] = {row[0], row[1], row[2], row[3]};
   const double logwb = row[kBscLogwb];
   // segments c_hi down to c_lo: checkpoint c at ckpt + c ckpt_stride, its
-  // records (every RS doubles per beam) at recs + (c - c_lo) seg_stride
+  // records (every RS doubles per beam) at recs + (c - c_lo) seg_stride, its
+  // hop-interval start states (kAdjSlots per beam) at
+  // slots + (c - c_lo) slot_stride
   for (int c = c_hi; c >= c_lo; --c) {
     const char *base = ckpt + (int64_t)c * ckpt_stride;
     const double *cf = (const double *)base;
@@ -1065,9 +1086,13 @@ aw_reverse_kernel(DevModel md, const char *__restrict__ ckpt, int64_t ckpt_strid
       if (__builtin_expect(r[AwT<D>::RREC + 1] == 0.0, 1)) {   // (the hop path is the cold one)
         aw_rk4_rev_fast<D>(md, (int)r[AwT<D>::RREC], cx, r, dt, yb, th, s);
       } else {
+        const double flag = r[AwT<D>::RREC + 1];   // k + 1: the start is in slot k; -1: no slot
+        const double *sl = flag > 0.0 ? slots + (int64_t)(c - c_lo) * slot_stride +
+                                             (w * kAdjSlots + (int)flag - 1) * (int64_t)adj_slot_doubles(D)
+                                       : nullptr;
         aw_put<D>(yb, io, lane);
         aw_mem_sync();
-        aw_interval_rev_hop<D>(md, cf, ci, n, b, i, io, gid, seed, dt, logwb, g, g + AwT<D>::REC);
+        aw_interval_rev_hop<D>(md, cf, ci, n, b, i, sl, io, gid, seed, dt, logwb, g, g + AwT<D>::REC);
         aw_get<D>(yb, io, lane);
 #pragma unroll
         for (int k = 0; k < 4; ++k) th[k] += io[NF * kAwLanes + k];
@@ -1099,14 +1124,15 @@ int64_t aw_chunk(int64_t n) {
   return n < kAwChunk ? (n < 1 ? 1 : n) : kAwChunk;
 }
 
-// Workspace (doubles): the records of one segment for the chunk (none when
-// the forward run kept its records), the chunk's adjoint states, its buffers
+// Workspace (doubles): the records and hop-interval slots of one segment
+// for the chunk (none when the forward run kept them), the chunk's adjoint
+// states, its buffers
 // for intervals with a hop, its replay state (shgb_nfields rows, then comp
 // and nhop), and one row of kAdjVals per beam.
 template <int D>
 int64_t aw_workspace_bytes(int64_t n, int every, bool recorded) {
   const int64_t c = aw_chunk<D>(n);
-  const int64_t seg = recorded ? 0 : (int64_t)every * adj_interval_rec(D);
+  const int64_t seg = recorded ? 0 : (int64_t)every * adj_interval_rec(D) + (int64_t)kAdjSlots * adj_slot_doubles(D);
   const int64_t dbl = c * (seg + AwT<D>::NF * kAwLanes + aw_gen_doubles<D>() + shgb_nfields(2 * D) + 1) +
                       (n < 1 ? 1 : n) * kAdjVals;
   return dbl * 8;
@@ -1114,11 +1140,13 @@ int64_t aw_workspace_bytes(int64_t n, int every, bool recorded) {
 
 hipError_t launch_adj_final(const double *, int64_t, double *, hipStream_t);
 hipError_t launch_step_wave_record(const DevModel &, const shgb_state &, int, double, uint64_t, double *, int,
-                                   uint64_t *, hipStream_t);
+                                   double *, uint64_t *, hipStream_t);
 
 // kept: the forward run's records of every segment (segment c, beam b,
-// interval i at kept + ((c n + b) every + i) adj_interval_rec(d)), or null
-// for the replay of each segment from its checkpoint.
+// interval i at kept + ((c n + b) every + i) adj_interval_rec(d)), then its
+// slots (segment c, beam b at
+// kept + n_seg n every adj_interval_rec(d) + (c n + b) kAdjSlots adj_slot_doubles(d)),
+// or null for the replay of each segment from its checkpoint.
 template <int D>
 hipError_t launch_aw(const DevModel &md, const shgb_state &fin, const void *ckpt, const double *kept, int nsteps,
                      double dt, uint64_t seed, int every, const double *cot, int64_t n_traj, double *out, void *work,
@@ -1126,9 +1154,11 @@ hipError_t launch_aw(const DevModel &md, const shgb_state &fin, const void *ckpt
   const int64_t n = fin.n_beams;
   const int64_t chunk = aw_chunk<D>(n);
   const CkptLayout cl = ckpt_layout(n, 2 * D, nsteps, every);
-  const int64_t seg = (int64_t)every * adj_interval_rec(D);   // doubles per beam and segment
+  const int64_t seg = (int64_t)every * adj_interval_rec(D);     // record doubles per beam and segment
+  const int64_t sdb = (int64_t)kAdjSlots * adj_slot_doubles(D);  // slot doubles per beam and segment
   double *recs = (double *)work;
-  double *ybuf = recs + (kept ? 0 : chunk * seg);
+  double *wslots = recs + (kept ? 0 : chunk * seg);
+  double *ybuf = wslots + (kept ? 0 : chunk * sdb);
   double *gen = ybuf + chunk * AwT<D>::NF * kAwLanes;
   double *rf = gen + chunk * aw_gen_doubles<D>();
   int32_t *rcomp = (int32_t *)(rf + chunk * (int64_t)shgb_nfields(2 * D));
@@ -1157,7 +1187,8 @@ hipError_t launch_aw(const DevModel &md, const shgb_state &fin, const void *ckpt
       if (cl.n_ckpt > 0)
         hipLaunchKernelGGL(aw_reverse_kernel<D>, dim3(blocks), dim3(kAwLanes * kAwWaves), 0, stream, md, ck,
                            cl.stride_bytes, cl.rows, n, nsteps, every, cl.n_ckpt - 1, 0, b0, nb, fin.beam_id_offset,
-                           seed, dt, kept + b0 * seg, n * seg, ybuf, bsc, gen);
+                           seed, dt, kept + b0 * seg, n * seg, kept + cl.n_ckpt * n * seg + b0 * sdb, n * sdb, ybuf,
+                           bsc, gen);
       continue;
     }
     for (int c = cl.n_ckpt - 1; c >= 0; --c) {
@@ -1167,11 +1198,11 @@ hipError_t launch_aw(const DevModel &md, const shgb_state &fin, const void *ckpt
       const int32_t *ci = (const int32_t *)(base + cl.rows * n * 8);
       hipLaunchKernelGGL(aw_ckpt_load_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, stream, cf, ci, n,
                          cl.rows, b0, nb, chunk, rf, rcomp, rnhop);
-      const hipError_t e = launch_step_wave_record(md, rs, len, dt, seed, recs, every, nullptr, stream);
+      const hipError_t e = launch_step_wave_record(md, rs, len, dt, seed, recs, every, wslots, nullptr, stream);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(aw_reverse_kernel<D>, dim3(blocks), dim3(kAwLanes * kAwWaves), 0, stream, md, ck,
                          cl.stride_bytes, cl.rows, n, nsteps, every, c, c, b0, nb, fin.beam_id_offset, seed, dt, recs,
-                         (int64_t)0, ybuf, bsc, gen);
+                         (int64_t)0, wslots, (int64_t)0, ybuf, bsc, gen);
     }
   }
   return launch_adj_final(bsc, n, out, stream);   // n = 0: zeros

@@ -413,7 +413,8 @@ int64_t shgb_record_bytes(int64_t n_beams, int32_t m, int32_t nsteps, int32_t ev
   if (n_beams < 0 || m < 4 || m > 2 * SHGB_MAX_D || (m & 1) || nsteps < 0 || every < 1) return -1;
   if (!adjoint_wave_supported(m / 2)) return -1;
   const int64_t n_seg = ((int64_t)nsteps + every - 1) / every;
-  return n_seg * n_beams * (int64_t)every * adj_interval_rec(m / 2) * 8;
+  return n_seg * n_beams * ((int64_t)every * adj_interval_rec(m / 2) + (int64_t)kAdjSlots * adj_slot_doubles(m / 2)) *
+         8;
 }
 
 int shgb_step_recorded(const shgb_model *model, const shgb_state *st, int32_t nsteps, double dt, uint64_t seed,

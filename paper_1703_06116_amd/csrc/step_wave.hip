@@ -121,7 +121,8 @@ __device__ inline void home_put2(uint32_t home, int v, double a, double b) {
 // unit phase, event counts), in LDS rather than in registers.
 struct HopLds {
   double logw, phre, phim;
-  uint32_t cnt[6];   // hops, threshold ties, destination ties, cap, zero rate (non-finite: unused)
+  uint32_t cnt[5];   // hops, threshold ties, destination ties, cap, zero rate
+  uint32_t nhop0;    // the beam's hop count at the launch's start (the recording kernel's slots)
 };
 
 // A workgroup's LDS: the exchange areas (first, so that their addresses fit
@@ -541,6 +542,58 @@ __device__ inline void pg_add_inc(PgY<D, LPB, double> &y, const PgY<D, LPB, floa
   y.Lam = y.Lam + inc.Lam;
 }
 
+// The recording kernel's copy of an interval's start state into a slot
+// (adjoint.h: the trajectory rows with ld = 1, then S, Lam, E, comp, nhop):
+// every lane of the beam writes the values it owns; the first HS pair-group
+// slots come from their LDS home (their registers are not kept).
+template <int D, int LPB, int HS>
+__device__ inline void pg_save_start(const PgCtx<D, LPB, double> &cx, const PgAddr<D, LPB> &ad,
+                                     const PgY<D, LPB, double> &y, const HopScalars &h, double *slot) {
+  using C = PG<D, LPB>;
+  constexpr int M = 2 * D;
+  const Layout L(M, 1);
+#pragma unroll
+  for (int e = 0; e < C::NG; ++e) {
+    const int a = cx.a[e], bb = cx.b[e];
+    if (a < 0) continue;
+    double v[kGrpN];
+#pragma unroll
+    for (int j = 0; j < kGrpN; j += 2) {
+      if (e < HS) {
+        const Cx2<double> h2 = home_get2(ad.home, e * kGrpN + j);
+        v[j] = h2.re;
+        v[j + 1] = h2.im;
+      } else {
+        v[j] = y.g[e].v[j];
+        v[j + 1] = y.g[e].v[j + 1];
+      }
+    }
+    const int trr = Layout::tri(M, a, bb), tab = Layout::tri(M, a, D + bb), tba = Layout::tri(M, bb, D + a),
+              tpp = Layout::tri(M, D + a, D + bb);
+    const int row[kGrpN] = {L.Zre(trr), L.Zim(trr), L.Zre(tab), L.Zim(tab),
+                            L.Zre(tba), L.Zim(tba), L.Zre(tpp), L.Zim(tpp)};
+#pragma unroll
+    for (int j = 0; j < kGrpN; ++j)
+      if (a != bb || (j != kBaR && j != kBaI)) slot[row[j]] = v[j];
+  }
+#pragma unroll
+  for (int j = 0; j < C::NXP; ++j) {
+    const int c = cx.r + LPB * j;
+    if (c < M) {
+      slot[L.X(c)] = y.x[j];
+      slot[L.P(c)] = y.p[j];
+    }
+  }
+  if (cx.r == 0) {
+    const int T = L.traj_rows();
+    slot[T] = y.S;
+    slot[T + 1] = y.Lam;
+    slot[T + 2] = h.E;
+    slot[T + 3] = (double)h.comp;
+    slot[T + 4] = (double)h.nhop;
+  }
+}
+
 // One interval [t_n, t_n + dt] (Sec. 2.4 steps 3-5) for the group's beam: a
 // trial RK4 step; if Lam reaches the threshold, the step to the
 // interpolated hop time, the hop (at the state reached), and the rest of
@@ -549,7 +602,8 @@ __device__ inline void pg_add_inc(PgY<D, LPB, double> &y, const PgY<D, LPB, floa
 template <int D, int LPB, bool MIXED, int HS, bool REC = false>
 __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, PgCtx<D, LPB, double> &cx,
                                    const PgCtx<D, LPB, float> &cxf, PgAddr<D, LPB> &ad, int base, PgY<D, LPB, double> &y, HopCtx &hc,
-                                   double dt, Counters &cnt, void *lds, HopLds &hl, double *rec = nullptr) {
+                                   double dt, Counters &cnt, void *lds, HopLds &hl, double *rec = nullptr,
+                                   double *hslot = nullptr) {
   const double tie_rel = MIXED ? kTieRelMixed : kTieRel;
   double rem = dt, hstep = dt, theta = 1.0;
   bool partial = false;
@@ -585,9 +639,21 @@ __device__ inline void pg_interval(const DevModel &md, const QcleF &mf, PgCtx<D,
         else hl.cnt[1]++;   // every lane of the beam writes the same count
       }
       if constexpr (REC) {
-        if (hops == 0 && cx.r == 0 && rec) {
-          rec[4 * adj_stage_rec(D)] = (double)comp0;
-          rec[4 * adj_stage_rec(D) + 1] = (capped || !(lam_n >= E)) ? 0.0 : 1.0;
+        if (hops == 0 && rec) {
+          // the hop flag: 0 no hop, k + 1 the start state in slot k, -1 no slot
+          double flag = 0.0;
+          if (!capped && lam_n >= E) {
+            const uint32_t k = hc.h.nhop - hl.nhop0;
+            flag = -1.0;
+            if (hslot && k < (uint32_t)kAdjSlots) {
+              pg_save_start<D, LPB, HS>(cx, ad, y, hc.h, hslot + (int64_t)k * adj_slot_doubles(D));
+              flag = (double)(k + 1);
+            }
+          }
+          if (cx.r == 0) {
+            rec[4 * adj_stage_rec(D)] = (double)comp0;
+            rec[4 * adj_stage_rec(D) + 1] = flag;
+          }
         }
       }
       if (capped || !(lam_n >= E)) {
@@ -668,7 +734,7 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
                                  int32_t *__restrict__ comp, uint32_t *__restrict__ nhop, int64_t n, int64_t ld,
                                  uint64_t gid0, int nsteps, double dt, uint64_t seed, int64_t tile,
                                  TileLds<D, LPB, TS, WPB> &tl, Counters &cnt_out, double *__restrict__ recs = nullptr,
-                                 int every = 0) {
+                                 int every = 0, double *__restrict__ slots = nullptr) {
   constexpr int HS = TileLds<D, LPB, TS, WPB>::HS;
   PgLds<D, TS> *lds = tl.ex;
   using C = PG<D, LPB>;
@@ -746,7 +812,8 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
       hl.phre = h.phre;
       hl.phim = h.phim;
 #pragma unroll
-      for (int t = 0; t < 6; ++t) hl.cnt[t] = 0u;
+      for (int t = 0; t < 5; ++t) hl.cnt[t] = 0u;
+      hl.nhop0 = h.nhop;
     }
     PgAddr<D, LPB> ad{};
     if constexpr (!MIXED) {
@@ -759,7 +826,8 @@ __device__ inline void wave_tile(const DevModel &md, TS *__restrict__ tr, double
     }
     for (int st = 0; st < nsteps; ++st)
       pg_interval<D, LPB, MIXED, HS, REC>(md, mf, cx, cxf, ad, base, y, hc, dt, cnt, (void *)&lds[slot], hl,
-                                      REC ? recs + ((int64_t)b * every + st) * adj_interval_rec(D) : nullptr);
+                                      REC ? recs + ((int64_t)b * every + st) * adj_interval_rec(D) : nullptr,
+                                      REC && slots ? slots + (int64_t)b * kAdjSlots * adj_slot_doubles(D) : nullptr);
     // (every hop is completed where it starts, so none is pending here)
     // the beam index through an empty asm statement: the stores' addresses
     // are formed here, not kept from the loads before the interval loop
@@ -935,43 +1003,48 @@ step_wave_batched(const BatchItem *__restrict__ items, int n_items, int64_t tota
 }
 
 // The FP64 stepping kernel that also writes, for every interval, the stage
-// records of its trial step, its component and whether it has a hop (the
-// forward run that keeps its records, or the replay of a segment for the
-// reverse sweep; records of beam b, interval i at
-// recs + (b every + i) adj_interval_rec(d)).  diag may be null.
+// records of its trial step, its component and its hop flag (the forward run
+// that keeps its records, or the replay of a segment for the reverse sweep;
+// records of beam b, interval i at recs + (b every + i) adj_interval_rec(d)),
+// and the start states of the intervals with a hop in the beam's slots at
+// slots + b kAdjSlots adj_slot_doubles(d) (adjoint.h; slots may be null: then
+// the flags say "no slot").  One launch is one segment.  diag may be null.
 template <int D, int LPB>
 __global__ void __launch_bounds__(64 * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(2)))
 step_wave_rec_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
                      uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps, double dt,
-                     uint64_t seed, double *__restrict__ recs, int every, uint64_t *diag) {
+                     uint64_t seed, double *__restrict__ recs, int every, double *__restrict__ slots,
+                     uint64_t *diag) {
   __shared__ TileLds<D, LPB, double, kWavesPerBlock> tl;
   static_assert(sizeof(tl.ex) <= 65536, "16-bit LDS addresses (PgAddr)");
   Counters cnt;
   wave_tile<D, LPB, double, kWavesPerBlock, true>(md, tr, sc, comp, nhop, n, ld, gid0, nsteps, dt, seed,
                                                   xcd_line_tile<tiles_per_line<D, LPB, double>()>(blockIdx.x, gridDim.x),
-                                                  tl, cnt, recs, every);
+                                                  tl, cnt, recs, every, slots);
   flush_counters(cnt, diag);
 }
 
 template <int D, int LPB>
 static void launch_pg_rec(const DevModel &md, const shgb_state &st, int nsteps, double dt, uint64_t seed,
-                          double *recs, int every, uint64_t *diag, hipStream_t stream) {
+                          double *recs, int every, double *slots, uint64_t *diag, hipStream_t stream) {
   constexpr int beams_per_block = kWavesPerBlock * PG<D, LPB>::G;
   const int64_t blocks = (st.n_beams + beams_per_block - 1) / beams_per_block;
   hipLaunchKernelGGL((step_wave_rec_kernel<D, LPB>), dim3((unsigned)blocks), dim3(64 * kWavesPerBlock), 0, stream,
                      md, st.f64, scalar_block(st), st.comp, st.nhop, st.n_beams, st.ld, st.beam_id_offset, nsteps,
-                     dt, seed, recs, every, diag);
+                     dt, seed, recs, every, slots, diag);
 }
 
 hipError_t launch_step_wave_record(const DevModel &md, const shgb_state &st, int nsteps, double dt, uint64_t seed,
-                                   double *recs, int every, uint64_t *diag, hipStream_t stream) {
+                                   double *recs, int every, double *slots, uint64_t *diag, hipStream_t stream) {
   if (st.n_beams == 0 || nsteps == 0) return hipSuccess;
   if (mixed(st) || nsteps > every) return hipErrorInvalidValue;
   switch (md.d) {
-    case 2: launch_pg_rec<2, 8>(md, st, nsteps, dt, seed, recs, every, diag, stream); break;
-    case 3: launch_pg_rec<3, 8>(md, st, nsteps, dt, seed, recs, every, diag, stream); break;
-    case 4: launch_pg_rec<4, 8>(md, st, nsteps, dt, seed, recs, every, diag, stream); break;
-    case 12: launch_pg_rec<12, kLanesPerBeamD12>(md, st, nsteps, dt, seed, recs, every, diag, stream); break;
+    case 2: launch_pg_rec<2, 8>(md, st, nsteps, dt, seed, recs, every, slots, diag, stream); break;
+    case 3: launch_pg_rec<3, 8>(md, st, nsteps, dt, seed, recs, every, slots, diag, stream); break;
+    case 4: launch_pg_rec<4, 8>(md, st, nsteps, dt, seed, recs, every, slots, diag, stream); break;
+    case 12:
+      launch_pg_rec<12, kLanesPerBeamD12>(md, st, nsteps, dt, seed, recs, every, slots, diag, stream);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -49,7 +49,8 @@ def tangent_gradient(cfg, cot):
 
 # d > 1 sweeps beams in chunks of 65536: 65536 + 37 beams take a full chunk and a ragged one
 @pytest.mark.parametrize("d,n,nsteps,every", [(1, 2 * 256 + 37, 600, 100), (1, 300, 257, 37), (1, 64, 250, 400),
-                                              (2, 2 * 128 + 5, 500, 100), (12, 2 * 64 + 3, 450, 100),
+                                              (2, 2 * 128 + 5, 500, 100), (2, 2 * 128 + 5, 500, 500),
+                                              (12, 2 * 64 + 3, 450, 100),
                                               (12, 37, 330, 64), (2, 65536 + 37, 120, 48),
                                               (12, 65536 + 37, 120, 48)])
 def test_adjoint_equals_tangent(gpu, d, n, nsteps, every):
@@ -106,9 +107,12 @@ def test_adjoint_edge_cases(gpu):
 # state and event counts as the checkpointed run, and, from those records,
 # bitwise the reverse sweep that runs each segment again (both sweeps read
 # records written by the same recording kernel from the same states).
+# Intervals with a hop start from the state the forward run kept in one of
+# the beam's 4 slots per segment; later ones in a segment (one segment of 500
+# intervals below) are found again from the checkpoint.
 @pytest.mark.parametrize("d,n,nsteps,every", [(2, 2 * 128 + 5, 300, 100), (3, 70, 200, 64),
                                               (12, 2 * 64 + 3, 250, 100), (12, 37, 130, 64),
-                                              (12, 65536 + 37, 60, 48)])
+                                              (12, 65536 + 37, 60, 48), (2, 2000, 500, 500)])
 def test_kept_records_equal_replay(gpu, d, n, nsteps, every):
     cfg = crossing_cfg(n, nsteps, d=d)
     mdl = gpu_model(cfg)
@@ -129,6 +133,13 @@ def test_kept_records_equal_replay(gpu, d, n, nsteps, every):
     assert torch.equal(ckpt, ckref)
     assert (dg.cpu().numpy() == dref.cpu().numpy()).all()
     assert int(st.nhop.sum()) > 0
+    rs = 4 * (3 + 4 * d) + 2
+    nseg = (nsteps + every - 1) // every
+    flags = recs[:nseg * n * every * rs].view(nseg, n, every, rs)[..., rs - 1]
+    if nsteps <= every:
+        filled = flags.masked_fill(flags < 0, 0)[..., :nsteps]
+        assert (flags[..., :nsteps] > 0).any() and (flags[..., :nsteps] == -1).any()   # slots and the fallback
+        assert filled.max() <= 4
     rng = np.random.default_rng(11)
     for cot in ([1.0, 0, 0, 0, 0, 0, 0, 0], list(rng.normal(size=8))):
         c = torch.tensor(cot, dtype=torch.float64, device="cuda")

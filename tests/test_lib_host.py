@@ -240,13 +240,19 @@ def test_zero_work_calls_launch_nothing(binding):
 
 def test_kept_record_sizes_and_validation(binding):
     """Sizes of the kept stage records (8 (4 (3 + 4d) + 2) bytes per beam and interval, whole
-    segments) and the argument checks of the entry points that use them, before any device work."""
+    segments, and per beam and segment 4 slots of 8 (2m + m (m + 1) + 5, rounded up to even) bytes
+    for the starts of intervals with a hop) and the argument checks of the entry points that use
+    them, before any device work."""
     lib = binding._lib
     by = ctypes.byref
     nul = ctypes.c_void_p(0)
     EINVAL, EUNS, EWS = -1, -2, -4
-    assert lib.shgb_record_bytes(10, 24, 250, 100) == 3 * 10 * 100 * (4 * (3 + 4 * 12) + 2) * 8
-    assert lib.shgb_record_bytes(10, 4, 100, 100) == 10 * 100 * (4 * (3 + 8) + 2) * 8
+
+    def slot(m):
+        return (2 * m + m * (m + 1) + 6) // 2 * 2
+    assert slot(24) == 654
+    assert lib.shgb_record_bytes(10, 24, 250, 100) == 3 * 10 * (100 * (4 * (3 + 4 * 12) + 2) + 4 * slot(24)) * 8
+    assert lib.shgb_record_bytes(10, 4, 100, 100) == 10 * (100 * (4 * (3 + 8) + 2) + 4 * slot(4)) * 8
     assert lib.shgb_record_bytes(10, 24, 0, 100) == 0
     assert lib.shgb_record_bytes(10, 2, 100, 100) == -1       # the 1-D adjoint keeps no records
     assert lib.shgb_record_bytes(10, 10, 100, 100) == -1      # d = 5: no adjoint
@@ -256,7 +262,7 @@ def test_kept_record_sizes_and_validation(binding):
         kept = lib.shgb_population_adjoint_recorded_workspace(n, 24, every)
         replay = lib.shgb_population_adjoint_workspace(n, 24, every)
         assert 0 < kept < replay
-        assert replay - kept == min(n, 65536) * every * (4 * (3 + 4 * 12) + 2) * 8
+        assert replay - kept == min(n, 65536) * (every * (4 * (3 + 4 * 12) + 2) + 4 * slot(24)) * 8
     m12 = binding.make_model(12, mass=2000.0, eps=0.02, A=0.01, B=1.6, C=0.005, D=1.0, lam=1e-3,
                              bath_omega=[0.01] * 11)
     st = _desc(binding, n=16, m=24)
