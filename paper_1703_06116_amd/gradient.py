@@ -9,6 +9,11 @@ exactly), steps it with checkpoints every ``every`` intervals and forms the
 means on the device; its backward pass launches the reverse sweep
 (shgb_population_adjoint) with the incoming gradient as the cotangent, one
 sweep for all five parameters (hop sequences frozen, see include/shgb.h).
+For d > 1 the forward pass can keep every interval's stage records in device
+memory (shgb_step_recorded) so that the backward pass need not run the
+segments again (shgb_population_adjoint_recorded): ``keep_records`` True or
+False, or None to keep them when they take at most half of the free device
+memory.  Both give the same gradient.
 ``population_and_tangent`` gives the same derivative by forward (tangent)
 propagation, one pass per parameter: the check of the adjoint.
 """
@@ -49,35 +54,53 @@ def population_and_tangent(theta, cfg, device="cuda"):
     return out[0, :, 0:2].clone(), out[:, :, 2:4].clone()
 
 
+def _keep(cfg, every, keep_records):
+    if cfg["d"] == 1:
+        return False                      # the one-dimensional adjoint has no kept-records form
+    if keep_records is not None:
+        return bool(keep_records)
+    need = shgb.record_bytes(cfg["n_beams"], 2 * cfg["d"], cfg["nsteps"], every)
+    free, _ = torch.cuda.mem_get_info()
+    return need <= free // 2
+
+
 class _Populations(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, theta, cfg, every):
+    def forward(ctx, theta, cfg, every, keep_records):
         th = theta.detach().cpu().tolist()
         mdl = _model(th, cfg)
         st = shgb.State(cfg["n_beams"], 2 * cfg["d"])
         shgb.init_beams(mdl, _spec(th, cfg), st, cfg["seed"])
-        ckpt = shgb.step_checkpointed(mdl, st, cfg["nsteps"], cfg["dt"], cfg["seed"], every=every)
+        recs = None
+        if _keep(cfg, every, keep_records):
+            ckpt, recs = shgb.step_recorded(mdl, st, cfg["nsteps"], cfg["dt"], cfg["seed"], every=every)
+        else:
+            ckpt = shgb.step_checkpointed(mdl, st, cfg["nsteps"], cfg["dt"], cfg["seed"], every=every)
         stats = shgb.population_stats(shgb.populations(mdl, st), cfg["n_beams"])
-        ctx.run = (mdl, st, ckpt, cfg, every)
+        ctx.run = (mdl, st, ckpt, recs, cfg, every)
         ctx.theta_like = (theta.dtype, theta.device)
         return stats[:, 0:2].contiguous()
 
     @staticmethod
     def backward(ctx, grad):
-        mdl, st, ckpt, cfg, every = ctx.run
+        mdl, st, ckpt, recs, cfg, every = ctx.run
         cot = grad.to(dtype=torch.float64).contiguous().view(-1)
-        out = shgb.population_adjoint(mdl, st, ckpt, cfg["nsteps"], cfg["dt"], cfg["seed"], cot, cfg["n_beams"],
-                                      every=every)
+        if recs is not None:
+            out = shgb.population_adjoint_recorded(mdl, st, ckpt, recs, cfg["nsteps"], cfg["dt"], cfg["seed"], cot,
+                                                   cfg["n_beams"], every=every)
+        else:
+            out = shgb.population_adjoint(mdl, st, ckpt, cfg["nsteps"], cfg["dt"], cfg["seed"], cot,
+                                          cfg["n_beams"], every=every)
         dtype, device = ctx.theta_like
-        return out[:5].to(dtype=dtype, device=device), None, None
+        return out[:5].to(dtype=dtype, device=device), None, None, None
 
 
-def populations(theta, cfg, every=100):
+def populations(theta, cfg, every=100, keep_records=None):
     """(Re, Im) population means of the four components after the run of cfg, a (4, 2) device
     tensor, differentiable in theta = (A, B, C, D, p_mean) (a float64 tensor of 5)."""
-    return _Populations.apply(theta, cfg, every)
+    return _Populations.apply(theta, cfg, every, keep_records)
 
 
-def population(theta, cfg, component=0, every=100):
+def population(theta, cfg, component=0, every=100, keep_records=None):
     """Re of the population of `component` (0 = upper surface), differentiable in theta."""
-    return populations(theta, cfg, every)[component, 0]
+    return populations(theta, cfg, every, keep_records)[component, 0]

@@ -115,6 +115,14 @@ def test_autograd_backward_is_the_adjoint_and_equals_the_tangent(gpu, d):
     (gradient.populations(theta, cfg) * w).sum().backward()
     want = (deriv.numpy() * w.cpu().numpy()[None]).sum((1, 2)) / cfg["n_beams"]
     assert np.abs(theta.grad.numpy() - want).max() <= 1e-10 * np.abs(want).max()
+    if d > 1:
+        # with the stage records kept or not: bitwise the same gradient
+        grads = []
+        for keep in (True, False):
+            theta.grad = None
+            (gradient.populations(theta, cfg, keep_records=keep) * w).sum().backward()
+            grads.append(theta.grad.clone())
+        assert torch.equal(grads[0], grads[1])
 
 
 @pytest.mark.parametrize("d", [1, 12])
