@@ -142,44 +142,76 @@ __host__ __device__ inline void hop_finish(const DevModel &md, HopCtx &hc, doubl
   hc.pending = false;
 }
 
-// One interval [t_n, t_n + dt] for one beam with the classical RK4 step
-// (RK = 4) or Kutta's third-order step (RK = 3).
+// Where a beam stands inside its current interval [t_n, t_n + dt]: the time
+// left, the size of the next Runge-Kutta call, the interpolated hop
+// fraction, the hops taken in the interval, and whether the next call is
+// the shortened step to a hop time.
+struct IvPos {
+  double rem, hstep, theta;
+  int hops;
+  bool partial;
+};
+
+__host__ __device__ inline void iv_begin(IvPos &iv, double dt) {
+  iv.rem = dt;
+  iv.hstep = dt;
+  iv.theta = 1.0;
+  iv.hops = 0;
+  iv.partial = false;
+}
+
+// One call of the interval algorithm (Sec. 2.4 steps 3-5) for one beam with
+// the classical RK4 step (RK = 4) or Kutta's third-order step (RK = 3): a
+// trial over the rest of the interval, the shortened step to the
+// interpolated hop time, or, after a hop, a new trial on the new component.
+// Returns true when the interval is complete.  Each lane runs its own
+// sequence of calls, so a wave does not run extra passes for the shortened
+// and remaining steps of one lane's hop while the others wait: a lane that
+// completes an interval goes on with its next one.
 template <int RK = 4>
-__host__ __device__ inline void interval2(const DevModel &md, Ode2 &y, HopCtx &hc, double dt, Counters &cnt) {
-  double rem = dt;      // time left in the interval
-  double hstep = dt;    // size of the next RK4 call
-  double theta = 1.0;
-  bool partial = false; // the next call is the shortened step to the hop time
-  int hops = 0;
+__host__ __device__ inline bool interval2_call(const DevModel &md, Ode2 &y, HopCtx &hc, IvPos &iv, Counters &cnt) {
   Ode2 yn;
-  for (;;) {
-    if constexpr (RK == 3) rk3_2(md, hc, cnt, y, hstep, yn);
-    else rk4_2(md, hc, cnt, y, hstep, yn);
-    const double E = hc.h.E;
-    if (!partial) {
-      const bool capped = hops >= SHGB_HOP_CAP;
-      if (!capped && fabs(yn.Lam - E) <= kTieRel * E) cnt.thr_ties++;
-      if (capped || !(yn.Lam >= E)) {  // no hop in the rest of the interval
-        if (capped) cnt.cap++;
-        y = yn;
-        break;
-      }
-      theta = (E <= y.Lam) ? 0.0 : (E - y.Lam) / (yn.Lam - y.Lam);
-      if (theta > 0.0 && theta < 1.0) {
-        partial = true;
-        hstep = theta * rem;
-        continue;
-      }
-      if (theta >= 1.0) y = yn;  // hop exactly at the end; theta == 0: hop now
-    } else {
+  if constexpr (RK == 3) rk3_2(md, hc, cnt, y, iv.hstep, yn);
+  else rk4_2(md, hc, cnt, y, iv.hstep, yn);
+  const double E = hc.h.E;
+  if (!iv.partial) {
+    const bool capped = iv.hops >= SHGB_HOP_CAP;
+    if (!capped && fabs(yn.Lam - E) <= kTieRel * E) cnt.thr_ties++;
+    if (capped || !(yn.Lam >= E)) {  // no hop in the rest of the interval
+      if (capped) cnt.cap++;
       y = yn;
-      partial = false;
+      return true;
     }
-    hop_start(hc, y.Lam);
-    ++hops;
-    rem = rem * (1.0 - theta);
-    if (!(rem > 0.0)) break;
-    hstep = rem;
+    iv.theta = (E <= y.Lam) ? 0.0 : (E - y.Lam) / (yn.Lam - y.Lam);
+    if (iv.theta > 0.0 && iv.theta < 1.0) {
+      iv.partial = true;
+      iv.hstep = iv.theta * iv.rem;
+      return false;
+    }
+    if (iv.theta >= 1.0) y = yn;  // hop exactly at the end; theta == 0: hop now
+  } else {
+    y = yn;
+    iv.partial = false;
+  }
+  hop_start(hc, y.Lam);
+  ++iv.hops;
+  iv.rem = iv.rem * (1.0 - iv.theta);
+  if (!(iv.rem > 0.0)) return true;
+  iv.hstep = iv.rem;
+  return false;
+}
+
+// All nsteps intervals of one beam: calls until the last interval is complete.
+template <int RK = 4>
+__host__ __device__ inline void intervals2(const DevModel &md, Ode2 &y, HopCtx &hc, int nsteps, double dt,
+                                           Counters &cnt) {
+  IvPos iv;
+  iv_begin(iv, dt);
+  for (int s = 0; s < nsteps;) {
+    if (interval2_call<RK>(md, y, hc, iv, cnt)) {
+      ++s;
+      iv_begin(iv, dt);
+    }
   }
 }
 
@@ -215,7 +247,7 @@ __device__ inline void m2_beam(const DevModel &md, double *__restrict__ tr, doub
     hc.pending = false;
     hc.gid = gid0 + (uint64_t)b;
     hc.seed = seed;
-    for (int s = 0; s < nsteps; ++s) interval2<RK>(md, y, hc, dt, cnt);
+    intervals2<RK>(md, y, hc, nsteps, dt, cnt);
     hop_finish(md, hc, y.q, y.p, cnt, kTieRel);
     const double chk = y.q + y.p + y.Pq + y.Pp + y.zr11 + y.zr12 + y.zr22 + y.zi11 + y.zi12 +
                        y.zi22 + y.S + y.Lam + h.logw;
@@ -357,40 +389,48 @@ __host__ __device__ inline void add_inc2m(Ode2 &y, const Inc2m &inc) {
   y.Lam = y.Lam + inc.Lam;
 }
 
-// The interval algorithm of interval2 on the mixed state.
-__host__ __device__ inline void interval2m(const QcleF &mf, Ode2 &y, HopCtx &hc, double dt, Counters &cnt) {
-  double rem = dt, hstep = dt, theta = 1.0;
-  bool partial = false;
-  int hops = 0;
+// One call of the interval algorithm of interval2_call on the mixed state.
+__host__ __device__ inline bool interval2m_call(const QcleF &mf, Ode2 &y, HopCtx &hc, IvPos &iv, Counters &cnt) {
   Inc2m inc;
-  for (;;) {
-    rk4_2m(mf, hc, cnt, y, hstep, inc);
-    const double E = hc.h.E;
-    if (!partial) {
-      const bool capped = hops >= SHGB_HOP_CAP;
-      const double lam_n = y.Lam + inc.Lam;
-      if (!capped && fabs(lam_n - E) <= kTieRelMixed * E) cnt.thr_ties++;
-      if (capped || !(lam_n >= E)) {
-        if (capped) cnt.cap++;
-        add_inc2m(y, inc);
-        break;
-      }
-      theta = (E <= y.Lam) ? 0.0 : (E - y.Lam) / (lam_n - y.Lam);
-      if (theta > 0.0 && theta < 1.0) {
-        partial = true;
-        hstep = theta * rem;
-        continue;
-      }
-      if (theta >= 1.0) add_inc2m(y, inc);
-    } else {
+  rk4_2m(mf, hc, cnt, y, iv.hstep, inc);
+  const double E = hc.h.E;
+  if (!iv.partial) {
+    const bool capped = iv.hops >= SHGB_HOP_CAP;
+    const double lam_n = y.Lam + inc.Lam;
+    if (!capped && fabs(lam_n - E) <= kTieRelMixed * E) cnt.thr_ties++;
+    if (capped || !(lam_n >= E)) {
+      if (capped) cnt.cap++;
       add_inc2m(y, inc);
-      partial = false;
+      return true;
     }
-    hop_start(hc, y.Lam);
-    ++hops;
-    rem = rem * (1.0 - theta);
-    if (!(rem > 0.0)) break;
-    hstep = rem;
+    iv.theta = (E <= y.Lam) ? 0.0 : (E - y.Lam) / (lam_n - y.Lam);
+    if (iv.theta > 0.0 && iv.theta < 1.0) {
+      iv.partial = true;
+      iv.hstep = iv.theta * iv.rem;
+      return false;
+    }
+    if (iv.theta >= 1.0) add_inc2m(y, inc);
+  } else {
+    add_inc2m(y, inc);
+    iv.partial = false;
+  }
+  hop_start(hc, y.Lam);
+  ++iv.hops;
+  iv.rem = iv.rem * (1.0 - iv.theta);
+  if (!(iv.rem > 0.0)) return true;
+  iv.hstep = iv.rem;
+  return false;
+}
+
+__host__ __device__ inline void intervals2m(const QcleF &mf, Ode2 &y, HopCtx &hc, int nsteps, double dt,
+                                            Counters &cnt) {
+  IvPos iv;
+  iv_begin(iv, dt);
+  for (int s = 0; s < nsteps;) {
+    if (interval2m_call(mf, y, hc, iv, cnt)) {
+      ++s;
+      iv_begin(iv, dt);
+    }
   }
 }
 #undef SHGB_TRAJ2_FIELDS
@@ -427,7 +467,7 @@ __device__ inline void m2m_beam(const DevModel &md, float *__restrict__ tr, doub
     hc.pending = false;
     hc.gid = gid0 + (uint64_t)b;
     hc.seed = seed;
-    for (int s = 0; s < nsteps; ++s) interval2m(mf, y, hc, dt, cnt);
+    intervals2m(mf, y, hc, nsteps, dt, cnt);
     if (hc.pending) {  // FP32 coupling at the stored (rounded) state, as inside the loop
       const Q1f k = qcle_q1f(mf, (float)y.q);
       hop_choose((double)((float)y.p * mf.inv_mass * k.d21), h, hc.gid, hc.seed, cnt, kTieRelMixed);
