@@ -157,8 +157,8 @@ def test_batch_instances_match_the_oracle(gpu, d, precision, sizes, nsteps):
             for f in ("X", "P", "M", "N"):
                 getattr(e, f)[:] = getattr(e, f).astype(np.float32).astype(np.float64)
         oshgb.advance(oracle_model(c), e, nsteps, c["dt"], c["seed"], tie_rel=tie)
-        min_ok = (0.98 if precision == "fp64" else 0.9) if c["n_beams"] > 20 else 0.7
-        errs, ties = compare_states(gpu.unpack(st), e, rtol=rtol, min_ok=min_ok,
+        # the oracle runs of these instances meet at most 4 tie beams (1025-beam mixed instance)
+        errs, ties = compare_states(gpu.unpack(st), e, rtol=rtol, max_ties=1 + c["n_beams"] // 100,
                                     label=f"instance {i} C={c['C']} eps={c['eps']}")
         hops += int(e.nhop.sum())
         sums = gpu.populations(gpu_model(c), st)

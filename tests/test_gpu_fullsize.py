@@ -50,7 +50,7 @@ def test_full_size_sampled_beams(gpu, name, k):
     g = {key: v[ids] for key, v in g_all.items()}
     e = oracle_init_ids(c, ids)
     oshgb.advance(oracle_model(c), e, c["nsteps"], c["dt"], c["seed"])
-    errs, ties = compare_states(g, e, min_ok=0.97, label=name)
+    errs, ties = compare_states(g, e, max_ties=1, label=name)     # the oracle runs meet none
     assert e.nhop.sum() > 0
     d = diag.cpu().numpy()
     assert d[3] == 0 and d[4] == 0
@@ -98,7 +98,7 @@ def test_full_size_d12_sampled_beams(gpu):
     g = {key: v[ids] for key, v in g_all.items()}
     e = oracle_init_ids(c, ids)
     oshgb.advance(oracle_model(c), e, c["nsteps"], c["dt"], c["seed"])
-    errs, ties = compare_states(g, e, min_ok=0.95, label="qcle12d")
+    errs, ties = compare_states(g, e, max_ties=1, label="qcle12d")    # the oracle run meets none
     d = diag.cpu().numpy()
     assert d[3] == 0 and d[4] == 0 and d[0] > c["n_beams"]
     assert d[1] <= MAX_TIES_PER_BEAM_FP64 * c["n_beams"], d
@@ -126,8 +126,9 @@ def test_full_size_d12_field(gpu):
     assert np.abs(ref).max() > 0
 
 
-@pytest.mark.parametrize("name,k", [("qcle1d_1e6", 32), ("qcle12d_2p18", 16)])
-def test_full_size_mixed_sampled_beams(gpu, name, k):
+# the oracle runs of the sampled beams meet 0 and 1 tie beams
+@pytest.mark.parametrize("name,k,max_ties", [("qcle1d_1e6", 32, 1), ("qcle12d_2p18", 16, 2)])
+def test_full_size_mixed_sampled_beams(gpu, name, k, max_ties):
     """The bench workloads on a mixed-precision state at full size; sampled beams by the FP64
     oracle from their global ids, started from the float32-rounded draws (ties within 1e-5
     excluded, 1e-4 bar)."""
@@ -144,7 +145,7 @@ def test_full_size_mixed_sampled_beams(gpu, name, k):
     for f in ("X", "P", "M", "N"):      # the FP64 draws as the mixed state stores them
         getattr(e, f)[:] = getattr(e, f).astype(np.float32).astype(np.float64)
     oshgb.advance(oracle_model(c), e, c["nsteps"], c["dt"], c["seed"], tie_rel=oshgb.TIE_REL_MIXED)
-    errs, ties = compare_states(g, e, rtol=1e-4, min_ok=0.9, label=f"{name} mixed")
+    errs, ties = compare_states(g, e, rtol=1e-4, max_ties=max_ties, label=f"{name} mixed")
     d = diag.cpu().numpy()
     assert d[3] == 0 and d[4] == 0
     assert d[1] <= MAX_TIES_PER_BEAM_MIXED * c["n_beams"], d

@@ -73,7 +73,8 @@ def test_mixed_step_from_oracle_state(gpu, d, n, nsteps):
     g = gpu.unpack(st)
     e = ensemble_from_arrays(a0)
     oshgb.advance(oracle_model(c), e, nsteps, c["dt"], c["seed"], tie_rel=oshgb.TIE_REL_MIXED)
-    errs, ties = compare_states(g, e, rtol=RTOL_MIXED, min_ok=0.9, label=f"mixed d={d}")
+    # the oracle runs meet 5, 0, 1 and 2 tie beams (d = 1, 2, 3, 12)
+    errs, ties = compare_states(g, e, rtol=RTOL_MIXED, max_ties=1 + n // 50, label=f"mixed d={d}")
     dg = diag.cpu().numpy()
     assert dg[3] == 0 and dg[4] == 0 and e.nhop.sum() > n
     print(f"mixed d={d}", errs, "tie beams", ties)
