@@ -252,6 +252,9 @@ __device__ inline void m2_beam(const DevModel &md, double *__restrict__ tr, doub
     const double chk = y.q + y.p + y.Pq + y.Pp + y.zr11 + y.zr12 + y.zr22 + y.zi11 + y.zi12 +
                        y.zi22 + y.S + y.Lam + h.logw;
     if (!isfinite(chk)) cnt.nonfinite++;
+    // The stores' addresses are formed here rather than kept from the loads
+    // across the interval loop (which would hold 36 registers for them).
+    asm volatile("" : "+v"(b));
     tr[L.X(0) * ld + b] = y.q;
     tr[L.X(1) * ld + b] = y.p;
     tr[L.P(0) * ld + b] = y.Pq;
@@ -273,9 +276,9 @@ __device__ inline void m2_beam(const DevModel &md, double *__restrict__ tr, doub
   }
 }
 
-// Two waves per SIMD (197 registers, no spills): the state moves through
-// HBM exactly once each way.  A three-wave build spills to scratch, doubling
-// the traffic for a 2 % gain.
+// Three waves per SIMD (167 registers, no spills; the store addresses are
+// formed after the interval loop): the state moves through HBM exactly once
+// each way.  Two waves per SIMD run as fast.
 __global__ void __launch_bounds__(256)
 step_m2_kernel(DevModel md, double *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
                uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps,
@@ -476,6 +479,7 @@ __device__ inline void m2m_beam(const DevModel &md, float *__restrict__ tr, doub
     const double chk = y.q + y.p + y.Pq + y.Pp + y.zr11 + y.zr12 + y.zr22 + y.zi11 + y.zi12 + y.zi22 + y.S +
                        y.Lam + h.logw;
     if (!isfinite(chk)) cnt.nonfinite++;
+    asm volatile("" : "+v"(b));  // store addresses formed here, as in m2_beam
     tr[L.X(0) * ld + b] = (float)y.q;
     tr[L.X(1) * ld + b] = (float)y.p;
     tr[L.P(0) * ld + b] = (float)y.Pq;
@@ -497,9 +501,9 @@ __device__ inline void m2m_beam(const DevModel &md, float *__restrict__ tr, doub
   }
 }
 
-// Two waves per SIMD (184 registers, no spills): as fast as three waves
-// with 14 registers spilled to scratch, without the scratch traffic.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+// Three waves per SIMD (148 registers, no spills): 4 % faster than two
+// waves per SIMD when the store addresses were kept across the loop.
+__global__ void __launch_bounds__(256)
 step_m2_mixed_kernel(DevModel md, float *__restrict__ tr, double *__restrict__ sc, int32_t *__restrict__ comp,
                      uint32_t *__restrict__ nhop, int64_t n, int64_t ld, uint64_t gid0, int nsteps, double dt,
                      uint64_t seed, uint64_t *diag) {
