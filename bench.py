@@ -78,8 +78,9 @@ PEAK_HBM_GBPS = 8000.0    # MI355X HBM3E
 # (profiles/step_m2_qcle1d_1e6.md, profiles/step_wave_qcle12d_2p18.md).  Each entry names the
 # kernel it was taken on; remove it when that kernel changes.
 STEP_TRAFFIC = {
-    "qcle1d_1e6": ((66697.4 * 2.0 + 133300.8 * 1.0) * 1024,
-                   "step_m2_kernel (per-lane interval calls), profiles/step_m2_qcle1d_1e6.md"),
+    "qcle1d_1e6": ((66703.4 * 2.0 + 133300.8 * 1.0) * 1024,
+                   "step_m2_kernel (per-lane interval calls, three waves per SIMD), "
+                   "profiles/step_m2_qcle1d_1e6.md"),
     "qcle12d_2p18": ((672048.0 * 2.0 + 1658031.0 * 1.0) * 1024,
                      "step_wave_kernel<12, 32, double> (two wavefronts per SIMD, no scratch, the tile's rows "
                      "written through LDS), profiles/step_wave_qcle12d_2p18.md"),
