@@ -178,3 +178,45 @@ def test_kept_records_edge_cases(gpu):
     assert gpu.record_bytes(5, 2, 10, 100) == -1
     with pytest.raises(gpu.ShgbError):
         gpu.step_recorded(gpu_model(c1), s1, 10, 0.5, 1, recs=small)
+
+
+def test_full_size_gradient_workload(gpu):
+    """The derivative workload at full size (d = 12, 2^16 beams x 1000 intervals, FP64, checkpoints
+    every 100 intervals, the stage records kept: 122 GB) in the calls the bench times, for the
+    gradient of the upper population: the forward run leaves the state bitwise as
+    shgb_step_ensemble does, the objective the sweep reports is that state's population, the sweep
+    from kept records equals the segment-replay sweep bitwise, and both equal the five-direction
+    tangent to 1e-10 of the gradient's size."""
+    from paper_1703_06116_amd import workloads
+    cfg = workloads.config("qcle12d_grad")
+    n, m, nsteps, every = cfg["n_beams"], 2 * cfg["d"], cfg["nsteps"], 100
+    mdl = gpu_model(cfg)
+    st = gpu.State(n, m)
+    gpu.init_beams(mdl, gpu_spec(cfg), st, cfg["seed"])
+    ref = gpu.State(n, m)
+    gpu.init_beams(mdl, gpu_spec(cfg), ref, cfg["seed"])
+    cot = [1.0, 0, 0, 0, 0, 0, 0, 0]
+    c = torch.tensor(cot, dtype=torch.float64, device="cuda")
+    recs = None
+    try:
+        ckpt, recs = gpu.step_recorded(mdl, st, nsteps, cfg["dt"], cfg["seed"], every=every)
+        gpu.step_ensemble(mdl, ref, nsteps, cfg["dt"], cfg["seed"])
+        assert torch.equal(st.f64, ref.f64) and torch.equal(st.comp, ref.comp) and torch.equal(st.nhop, ref.nhop)
+        assert int(st.nhop.sum()) > n
+        del ref
+        kept = gpu.population_adjoint_recorded(mdl, st, ckpt, recs, nsteps, cfg["dt"], cfg["seed"], c, n,
+                                               every=every)
+        recs = None
+        torch.cuda.empty_cache()
+        replay = gpu.population_adjoint(mdl, st, ckpt, nsteps, cfg["dt"], cfg["seed"], c, n, every=every)
+        assert torch.equal(kept, replay)
+        out = kept.cpu().numpy()
+        pops = gpu.populations(mdl, st).cpu().numpy()
+        assert abs(out[5] - pops[0, 0] / n) <= 1e-12 * np.abs(pops[:, :2]).sum() / n
+        tan = tangent_gradient(cfg, cot)
+        scale = np.abs(tan).max()
+        print("full size: kept", out, "tangent", tan, "rel", np.abs(out[:5] - tan).max() / scale)
+        assert scale > 0 and np.abs(out[:5] - tan).max() <= 1e-10 * scale, (out[:5], tan)
+    finally:
+        recs = None
+        torch.cuda.empty_cache()

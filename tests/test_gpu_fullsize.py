@@ -150,3 +150,43 @@ def test_full_size_mixed_sampled_beams(gpu, name, k, max_ties):
     assert d[3] == 0 and d[4] == 0
     assert d[1] <= MAX_TIES_PER_BEAM_MIXED * c["n_beams"], d
     print(name, "mixed errors", errs, "ties", ties)
+
+
+def test_full_size_batch64_sampled_beams(gpu):
+    """The 64-instance batch at full size (about 2.25e6 beams of the d = 12 model with per-instance
+    C and eps, 500 intervals, mixed precision) in one persistent launch of the shape the bench's
+    autotuner picks on the MI355X (4 waves per block, 2 blocks per CU, 4 tiles per grab): of each of
+    eight instances three fixed beams and the two with the most hops (few beams reach the crossing in
+    500 intervals) by the FP64 oracle from their global ids and float32-rounded draws (ties within
+    1e-5 excluded, 1e-4 bar); diag counts over the whole batch."""
+    cs = workloads.batch_instances("batch64_d12")
+    models = [gpu_model(c) for c in cs]
+    sts = []
+    for c, mdl in zip(cs, models):
+        st = gpu.State(c["n_beams"], 2 * c["d"], device="cuda", precision="mixed")
+        gpu.init_beams(mdl, gpu_spec(c), st, c["seed"])
+        sts.append(st)
+    diag = gpu.new_diag()
+    gpu.Batch(models, sts, [c["seed"] for c in cs], config=(4, 2, 4)).step(cs[0]["nsteps"], cs[0]["dt"], diag)
+    d = diag.cpu().numpy()
+    n_all = sum(c["n_beams"] for c in cs)
+    assert d[3] == 0 and d[4] == 0 and d[0] > 0
+    assert d[1] <= MAX_TIES_PER_BEAM_MIXED * n_all, d
+    rng = np.random.default_rng(21)
+    picks = sorted({0, len(cs) - 1, *rng.choice(np.arange(1, len(cs) - 1), 6, replace=False).tolist()})
+    hops = 0
+    for i in picks:
+        c = cs[i]
+        g_all = gpu.unpack(sts[i])
+        most = np.argsort(g_all["nhop"], kind="stable")[-2:]
+        ids = np.unique(np.concatenate([sample_ids(c["n_beams"], 3, seed=i), most]))
+        g = {key: v[ids] for key, v in g_all.items()}
+        e = oracle_init_ids(c, ids)
+        for f in ("X", "P", "M", "N"):
+            getattr(e, f)[:] = getattr(e, f).astype(np.float32).astype(np.float64)
+        oshgb.advance(oracle_model(c), e, c["nsteps"], c["dt"], c["seed"], tie_rel=oshgb.TIE_REL_MIXED)
+        errs, ties = compare_states(g, e, rtol=1e-4, max_ties=2, label=f"batch64 instance {i}")
+        np.testing.assert_array_equal(g["A"], e.A)
+        hops += int(e.nhop.sum())
+        print(f"instance {i}: n={c['n_beams']} C={c['C']:.4f} eps={c['eps']} ties={ties} errs={errs}")
+    assert hops > 0
