@@ -263,6 +263,28 @@ struct Counters {
   uint32_t hops = 0, thr_ties = 0, dest_ties = 0, cap = 0, zero_rate = 0, nonfinite = 0;
 };
 
+// Where a beam stands inside its current interval [t_n, t_n + dt] of the
+// interval algorithm (Sec. 2.4 steps 3-5), for the kernels that run one beam
+// per lane with one call per Runge-Kutta step: the time left, the size of the
+// next call, the interpolated hop fraction, the hops taken in the interval,
+// and whether the next call is the shortened step to a hop time.  Each lane
+// runs its own sequence of calls and starts its next interval as soon as it
+// completes one, so a wave does not run extra passes for one lane's
+// shortened and remaining steps while the others wait.
+struct IvPos {
+  double rem, hstep, theta;
+  int hops;
+  bool partial;
+};
+
+__host__ __device__ inline void iv_begin(IvPos &iv, double dt) {
+  iv.rem = dt;
+  iv.hstep = dt;
+  iv.theta = 1.0;
+  iv.hops = 0;
+  iv.partial = false;
+}
+
 // Relative bands within which threshold and destination comparisons are
 // counted as ties: FP64 trajectories, and FP32 trajectories (mixed states).
 constexpr double kTieRel = 1e-12;

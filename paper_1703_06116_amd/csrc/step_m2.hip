@@ -142,24 +142,6 @@ __host__ __device__ inline void hop_finish(const DevModel &md, HopCtx &hc, doubl
   hc.pending = false;
 }
 
-// Where a beam stands inside its current interval [t_n, t_n + dt]: the time
-// left, the size of the next Runge-Kutta call, the interpolated hop
-// fraction, the hops taken in the interval, and whether the next call is
-// the shortened step to a hop time.
-struct IvPos {
-  double rem, hstep, theta;
-  int hops;
-  bool partial;
-};
-
-__host__ __device__ inline void iv_begin(IvPos &iv, double dt) {
-  iv.rem = dt;
-  iv.hstep = dt;
-  iv.theta = 1.0;
-  iv.hops = 0;
-  iv.partial = false;
-}
-
 // One call of the interval algorithm (Sec. 2.4 steps 3-5) for one beam with
 // the classical RK4 step (RK = 4) or Kutta's third-order step (RK = 3): a
 // trial over the rest of the interval, the shortened step to the

@@ -132,42 +132,40 @@ __host__ __device__ inline void hop_p32(double x1, double x2, HopScalars &h, uin
   cnt.hops++;
 }
 
-__host__ __device__ inline void interval_p32(OdeP32 &y, HopScalars &h, double dt, uint64_t gid, uint64_t seed,
-                                             Counters &cnt) {
-  double rem = dt, hstep = dt, theta = 1.0;
-  bool partial = false;
-  int hops = 0;
+// One call of the interval algorithm (Sec. 2.4 steps 3-5), as
+// interval_lq_call; true when the interval is complete.
+__host__ __device__ inline bool interval_p32_call(OdeP32 &y, HopScalars &h, IvPos &iv, uint64_t gid, uint64_t seed,
+                                                  Counters &cnt) {
   OdeP32 yn;
-  for (;;) {
-    rk4_p32(h.comp, y, hstep, yn);
-    if (!partial) {
-      const bool capped = hops >= SHGB_HOP_CAP;
-      if (!capped && fabs(yn.Lam - h.E) <= kTieRel * h.E) cnt.thr_ties++;
-      if (capped || !(yn.Lam >= h.E)) {
-        if (capped) cnt.cap++;
-        y = yn;
-        break;
-      }
-      theta = (h.E <= y.Lam) ? 0.0 : (h.E - y.Lam) / (yn.Lam - y.Lam);
-      if (theta > 0.0 && theta < 1.0) {
-        partial = true;
-        hstep = theta * rem;
-        continue;
-      }
-      if (theta >= 1.0) y = yn;
-    } else {
+  rk4_p32(h.comp, y, iv.hstep, yn);
+  if (!iv.partial) {
+    const bool capped = iv.hops >= SHGB_HOP_CAP;
+    if (!capped && fabs(yn.Lam - h.E) <= kTieRel * h.E) cnt.thr_ties++;
+    if (capped || !(yn.Lam >= h.E)) {
+      if (capped) cnt.cap++;
       y = yn;
-      partial = false;
+      return true;
     }
-    h.logw += y.Lam;
-    y.Lam = 0.0;
-    h.Lam = 0.0;
-    hop_p32(y.x1, y.x2, h, gid, seed, cnt);
-    ++hops;
-    rem = rem * (1.0 - theta);
-    if (!(rem > 0.0)) break;
-    hstep = rem;
+    iv.theta = (h.E <= y.Lam) ? 0.0 : (h.E - y.Lam) / (yn.Lam - y.Lam);
+    if (iv.theta > 0.0 && iv.theta < 1.0) {
+      iv.partial = true;
+      iv.hstep = iv.theta * iv.rem;
+      return false;
+    }
+    if (iv.theta >= 1.0) y = yn;
+  } else {
+    y = yn;
+    iv.partial = false;
   }
+  h.logw += y.Lam;
+  y.Lam = 0.0;
+  h.Lam = 0.0;
+  hop_p32(y.x1, y.x2, h, gid, seed, cnt);
+  ++iv.hops;
+  iv.rem = iv.rem * (1.0 - iv.theta);
+  if (!(iv.rem > 0.0)) return true;
+  iv.hstep = iv.rem;
+  return false;
 }
 
 __global__ void __launch_bounds__(256)
@@ -202,32 +200,41 @@ step_p32_kernel(double *__restrict__ tr, double *__restrict__ sc, int32_t *__res
     h.nhop = nhop[b];
     h.Lam = y.Lam;
     const uint64_t gid = gid0 + (uint64_t)b;
-    for (int s = 0; s < nsteps; ++s) interval_p32(y, h, dt, gid, seed, cnt);
+    IvPos iv;
+    iv_begin(iv, dt);
+    for (int s = 0; s < nsteps;) {
+      if (interval_p32_call(y, h, iv, gid, seed, cnt)) {
+        ++s;
+        iv_begin(iv, dt);
+      }
+    }
     double chk = h.logw;
 #define F(f) chk += y.f;
     SHGB_ODEP32_FIELDS(F)
 #undef F
     if (!isfinite(chk)) cnt.nonfinite++;
-    tr[L.X(0) * ld + b] = y.x1;
-    tr[L.X(1) * ld + b] = y.x2;
-    tr[L.P(0) * ld + b] = y.P1;
-    tr[L.P(1) * ld + b] = y.P2;
-    tr[L.Zre(0) * ld + b] = y.zr11;
-    tr[L.Zre(1) * ld + b] = y.zr12;
-    tr[L.Zre(2) * ld + b] = y.zr22;
-    tr[L.Zim(0) * ld + b] = y.zi11;
-    tr[L.Zim(1) * ld + b] = y.zi12;
-    tr[L.Zim(2) * ld + b] = y.zi22;
-    sc[kRowS * ld + b] = y.S;
-    sc[kRowAre * ld + b] = y.Are;
-    sc[kRowAim * ld + b] = y.Aim;
-    sc[kRowLam * ld + b] = y.Lam;
-    sc[kRowLogw * ld + b] = h.logw;
-    sc[kRowPhre * ld + b] = h.phre;
-    sc[kRowPhim * ld + b] = h.phim;
-    sc[kRowE * ld + b] = h.E;
-    comp[b] = h.comp;
-    nhop[b] = h.nhop;
+    int64_t bs = b;
+    asm volatile("" : "+v"(bs));  // store addresses formed after the interval loop
+    tr[L.X(0) * ld + bs] = y.x1;
+    tr[L.X(1) * ld + bs] = y.x2;
+    tr[L.P(0) * ld + bs] = y.P1;
+    tr[L.P(1) * ld + bs] = y.P2;
+    tr[L.Zre(0) * ld + bs] = y.zr11;
+    tr[L.Zre(1) * ld + bs] = y.zr12;
+    tr[L.Zre(2) * ld + bs] = y.zr22;
+    tr[L.Zim(0) * ld + bs] = y.zi11;
+    tr[L.Zim(1) * ld + bs] = y.zi12;
+    tr[L.Zim(2) * ld + bs] = y.zi22;
+    sc[kRowS * ld + bs] = y.S;
+    sc[kRowAre * ld + bs] = y.Are;
+    sc[kRowAim * ld + bs] = y.Aim;
+    sc[kRowLam * ld + bs] = y.Lam;
+    sc[kRowLogw * ld + bs] = h.logw;
+    sc[kRowPhre * ld + bs] = h.phre;
+    sc[kRowPhim * ld + bs] = h.phim;
+    sc[kRowE * ld + bs] = h.E;
+    comp[bs] = h.comp;
+    nhop[bs] = h.nhop;
   }
   flush_counters(cnt, diag);
 }
