@@ -424,11 +424,11 @@ __device__ inline void pg_rk4(const DevModel &md, const QcleF &mf, const HopCtx 
 // y0 rounded to FP32 (c = h/2, h/2, h; 0 in the last stage); S and Lam
 // accumulate in FP64.  pg_rk4_m turns acc into the step's increment h/6 acc.
 template <int D, int LPB>
-__device__ inline void pg_stage_m(const DevModel &md, const QcleF &mf, HopCtx &hc, Counters &cnt,
+__device__ inline void pg_stage_m(const DevModel &md, const QcleF &mf, int comp,
                                   const PgCtx<D, LPB, float> &cx, const PgY<D, LPB, double> &y0,
                                   PgY<D, LPB, float> &ys, PgY<D, LPB, float> &acc, float w, float c,
                                   const PgLds<D, float> &s) {
-  const StageCoef<float> sc = stage_coef<D, float>(md, mf, hc.h.comp, s);
+  const StageCoef<float> sc = stage_coef<D, float>(md, mf, comp, s);
   auto fold = [&](float &a, float &yv, double y0v, float d) {
     a = fmaf(w, d, a);
     yv = fmaf(c, d, (float)y0v);
@@ -504,10 +504,14 @@ __device__ inline void pg_rk4_m(const DevModel &md, const QcleF &mf, HopCtx &hc,
     inc.x[j] = inc.p[j] = 0.0f;
   }
   inc.S = inc.Lam = 0.0;
+  // the component once per step: the hop scalars live in scratch memory
+  // (their address goes to the out-of-line hop), read there by every stage
+  // they cost a scratch load each
+  const int comp = hc.h.comp;
 #pragma unroll 1
   for (int st = 0; st < 4; ++st) {
     pg_publish_f(cx, ys, s);
-    pg_stage_m(md, mf, hc, cnt, cx, y, ys, inc, (st == 0 || st == 3) ? 1.0f : 2.0f,
+    pg_stage_m(md, mf, comp, cx, y, ys, inc, (st == 0 || st == 3) ? 1.0f : 2.0f,
                (float)(st == 3 ? 0.0 : (st == 2 ? h : 0.5 * h)), s);
     wave_lds_sync();
   }
